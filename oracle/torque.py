@@ -1,0 +1,60 @@
+"""Torques (FP64): LLG (Eq. 2) and Zhang-Li spin-transfer torque.
+
+LLG: tau = -gamma/(1+alpha^2) [m x B + alpha m x (m x B)].
+
+Zhang-Li (Methods, "Micromagnetism": implemented as in mumax3, whose text is
+not reproduced in the paper):
+  tau_ZL = -1/(1+alpha^2) [(1 + xi alpha) m x (m x (u.grad) m)
+                           + (xi - alpha) m x (u.grad) m]
+with the drift velocity u = P mu_B j / (e Ms) (g = 2).  This prefactor is a
+reading of this build; only its structure is pinned (a uniform state feels
+no torque), so the Zhang-Li term is "parity unpinned" beyond GPU/oracle
+agreement.  (u.grad) m uses central differences with clamped neighbours
+(the boundary cell stands in for the missing one) over 2*d.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .constants import MU_B, QE
+
+
+def cross(a, b):
+    return np.stack([
+        a[1] * b[2] - a[2] * b[1],
+        a[2] * b[0] - a[0] * b[2],
+        a[0] * b[1] - a[1] * b[0],
+    ])
+
+
+def llg_torque(m, B, gamma, alpha):
+    mxB = cross(m, B)
+    return -gamma / (1.0 + alpha * alpha) * (mxB + alpha * cross(m, mxB))
+
+
+def drift_velocity(P, j, Ms):
+    if Ms == 0.0:
+        return np.zeros(3)
+    return P * MU_B * np.asarray(j, dtype=np.float64) / (QE * Ms)
+
+
+def directional_derivative(m, u, d):
+    """(u.grad) m with clamped neighbours and 2d central differences."""
+    g = np.pad(m, ((0, 0), (1, 1), (1, 1), (1, 1)), mode="edge")
+    out = np.zeros_like(m)
+    if u[0] != 0.0:
+        out += u[0] * (g[:, 1:-1, 1:-1, 2:] - g[:, 1:-1, 1:-1, :-2]) / (2.0 * d[0])
+    if u[1] != 0.0:
+        out += u[1] * (g[:, 1:-1, 2:, 1:-1] - g[:, 1:-1, :-2, 1:-1]) / (2.0 * d[1])
+    if u[2] != 0.0:
+        out += u[2] * (g[:, 2:, 1:-1, 1:-1] - g[:, :-2, 1:-1, 1:-1]) / (2.0 * d[2])
+    return out
+
+
+def zhang_li_torque(m, u, alpha, xi, d):
+    if not np.any(u):
+        return np.zeros_like(m)
+    dm = directional_derivative(m, u, d)
+    mxdm = cross(m, dm)
+    return -1.0 / (1.0 + alpha * alpha) * (
+        (1.0 + xi * alpha) * cross(m, mxdm) + (xi - alpha) * mxdm)

@@ -1,0 +1,91 @@
+"""Pins for the oracle's elastodynamics (not GPU).
+
+* The first-derivative operator is exact on polynomials of degree <= 4 in
+  the bulk, <= 2 one cell in from a face and <= 1 on a face cell.
+* The paper's racetrack demonstration (Table 1 parameters for NiO) prints
+  a shear pulse travelling at about 4 km/s with a strain of about 0.14 %
+  for a 0.3 GPa shear traction; a bar driven by one period of that traction
+  through the oracle reproduces both numbers.
+* With no damping, no coupling and no drive the elastic energy
+  1/2 sigma:eps + 1/2 rho v^2 of an interior pulse is conserved.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import elastic as el
+from oracle.system import Problem
+from paper_2411_18194_amd import inputs
+
+
+def test_derivative_polynomial_exactness():
+    n, h = 12, 0.7
+    x = np.arange(n) * h
+    for deg in range(5):
+        f = x ** deg
+        df = deg * x ** (deg - 1) if deg else 0 * x
+        d = el.deriv(f, 0, h)
+        bulk = slice(2, n - 2)
+        assert np.allclose(d[bulk], df[bulk], rtol=1e-12, atol=1e-9)
+        if deg <= 2:
+            assert np.allclose(d[[1, n - 2]], df[[1, n - 2]], rtol=1e-12, atol=1e-9)
+        if deg <= 1:
+            assert np.allclose(d[[0, n - 1]], df[[0, n - 1]], rtol=1e-12, atol=1e-9)
+    # a single cell has no derivative
+    assert el.deriv(np.ones((1, 3)), 0, 1.0).max() == 0.0
+
+
+def _nio_bar(nx, dx):
+    p = inputs.base_params((nx, 1, 1), (dx, dx, dx))
+    # Table 1: rho, C11, C12, C44 of NiO; magnetisation switched off
+    p.update(Ms=[0.0], elastic=dict(rho=6853.0, C11=330e9, C12=60e9, C44=110e9,
+                                    eta=0.0, trac_amp=0.3e9, trac_freq=8e9))
+    return p
+
+
+def test_printed_racetrack_numbers():
+    nx, dx = 400, 3e-9
+    p = _nio_bar(nx, dx)
+    P = Problem(p)
+    m = np.zeros((1, 3, 1, 1, nx))
+    m[0, 2] = 1.0
+    y = P.initial_state(m)
+    # one period of the 8 GHz drive, then switch it off and let it travel
+    dt = 1e-13
+    nper = int(round(1 / 8e9 / dt))
+    y, t = P.run_fixed(y, 0.0, dt, nper)
+    P.p = dict(p)
+    P.p["elastic"] = dict(p["elastic"], trac_amp=0.0)
+    P.stepper.invalidate()
+    t1 = t
+    y, t = P.run_fixed(y, t, dt, 600)
+    uz = y[1][2, 0, 0, :]
+    eps_xz = el.strain(y[1], p["cell"])[4, 0, 0, :]
+    # pulse front position: the leading edge where |u_z| rises above 1 %
+    x = (np.arange(nx) + 0.5) * dx
+    front = x[np.nonzero(np.abs(uz) > 0.01 * np.abs(uz).max())[0].max()]
+    speed = front / t
+    c_shear = math.sqrt(110e9 / 6853.0)
+    assert c_shear == pytest.approx(4006, rel=1e-3)        # "about 4 km/s"
+    assert speed == pytest.approx(c_shear, rel=0.06)
+    # strain amplitude in the travelling pulse: sigma/(2 C44) ~ 0.136 %
+    assert np.abs(eps_xz).max() == pytest.approx(0.3e9 / (2 * 110e9), rel=0.06)
+    assert abs(np.abs(eps_xz).max() * 100 - 0.14) < 0.01   # "approximately 0.14 %"
+
+
+def test_energy_conservation_free_pulse():
+    nx, dx = 200, 2e-9
+    p = _nio_bar(nx, dx)
+    p["elastic"] = dict(p["elastic"], trac_amp=0.0)
+    P = Problem(p)
+    m = np.zeros((1, 3, 1, 1, nx))
+    m[0, 2] = 1.0
+    y = P.initial_state(m)
+    x = np.arange(nx) * dx
+    y[1][2, 0, 0, :] = 1e-11 * np.exp(-((x - 200e-9) / 20e-9) ** 2)
+    y[1][0, 0, 0, :] = 5e-12 * np.exp(-((x - 200e-9) / 25e-9) ** 2)
+    E0 = P.energies(y[0], y[1], y[2])["elastic"]
+    y, t = P.run_fixed(y, 0.0, 2e-14, 500)
+    E1 = P.energies(y[0], y[1], y[2])["elastic"]
+    assert E1 == pytest.approx(E0, rel=1e-5)

@@ -1,0 +1,173 @@
+"""Pins for the oracle's short-range field terms (not GPU).
+
+* Exchange: a spin spiral (cos kx, sin kx, 0) is an eigenvector of the
+  discrete Laplacian, so in the interior B = -(2A/Ms)(2 - 2 cos k d)/d^2 m.
+* Interfacial DMI: a cycloid (cos kx, 0, sin kx) gives in the interior
+  B = (2D/Ms)(sin kd/d)(cos kx, 0, sin kx).
+* Uniform states feel no exchange, no inter-sublattice Laplacian term.
+* Field = -(1/(Ms V)) dE/dm of the independently written energy density
+  (finite differences of the FP64 energy) for every local term and for the
+  bulk of exchange/DMI.
+* The edge canting along x of a relaxed wide strip with exchange +
+  interfacial DMI + perpendicular anisotropy converges to the 1-D problem
+  A theta'' = K sin(theta) cos(theta), theta' = -D/(2A) at both ends
+  (natural boundary condition of the DMI energy), solved by scipy.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.integrate import solve_bvp
+
+from oracle import fields as fl
+from oracle.system import Problem, TERMS
+from paper_2411_18194_amd import inputs
+
+
+def test_exchange_spin_spiral():
+    n, d = (40, 3, 1), (1e-9, 1e-9, 1e-9)
+    k = 2 * math.pi / 17e-9
+    x = np.arange(n[0]) * d[0]
+    m = np.zeros((3, 1, 3, 40))
+    m[0] = np.cos(k * x)
+    m[1] = np.sin(k * x)
+    A, Ms = 1.3e-11, 8e5
+    B = fl.exchange_field(m, Ms, A, d)
+    ref = -(2 * A / Ms) * (2 - 2 * math.cos(k * d[0])) / d[0] ** 2 * m
+    inner = (slice(None), slice(None), slice(None), slice(1, -1))
+    assert np.abs(B[inner] - ref[inner]).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_dmi_cycloid():
+    n, d = (40, 4, 1), (2e-9, 2e-9, 2e-9)
+    k = 2 * math.pi / 23e-9
+    x = np.arange(n[0]) * d[0]
+    m = np.zeros((3, 1, 4, 40))
+    m[0] = np.cos(k * x)
+    m[2] = np.sin(k * x)
+    D, Ms, A = 3e-3, 1.1e6, 1.5e-11
+    B = fl.dmi_field(m, Ms, A, D, d)
+    ref = (2 * D / Ms) * math.sin(k * d[0]) / d[0] * np.stack(
+        [np.cos(k * x), 0 * x, np.sin(k * x)])[:, None, None, :]
+    inner = (slice(None), slice(None), slice(1, -1), slice(1, -1))
+    assert np.abs(B[inner] - np.broadcast_to(ref, B.shape)[inner]).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_uniform_no_exchange():
+    m = np.zeros((3, 2, 5, 6))
+    m[0] = 0.6
+    m[2] = 0.8
+    assert np.abs(fl.exchange_field(m, 8e5, 1e-11, (1e-9,) * 3)).max() == 0.0
+    assert np.abs(fl.afm_nn_field(m, 8e5, -5e-12, (1e-9,) * 3)).max() == 0.0
+
+
+def _energy_gradient_check(p, m, terms, interior_only=False, u=None):
+    P = Problem(p)
+    V = P.V
+    B = P.eval_heff(m, terms, u=u)
+    rng = np.random.default_rng(3)
+    nsub, _, nz, ny, nx = m.shape
+    for _ in range(6):
+        s = rng.integers(nsub)
+        c = rng.integers(3)
+        if interior_only:
+            z = rng.integers(nz)
+            y = rng.integers(1, ny - 1)
+            x = rng.integers(1, nx - 1)
+        else:
+            z, y, x = rng.integers(nz), rng.integers(ny), rng.integers(nx)
+        h = 1e-6
+
+        def E(delta):
+            mm = m.copy()
+            mm[s, c, z, y, x] += delta
+            en = P.energies(mm, u=u)
+            return sum(en[t] for t in terms)
+        g = (E(h) - E(-h)) / (2 * h)
+        expect = -g / (p["Ms"][s] * V)
+        assert B[s, c, z, y, x] == pytest.approx(expect, rel=2e-6, abs=1e-9 * np.abs(B).max())
+
+
+def test_energy_gradient_local_terms():
+    p = inputs.base_params((5, 4, 2), (2e-9, 3e-9, 1e-9), nsub=2)
+    p.update(Ms=[8e5, 5e5], Ku1=[5e5, 3e5], Ku2=[1e5, 0.0],
+             anis_u=[(0.6, 0, 0.8), (0, 1, 0)], Kc1=[2e4, -3e4],
+             cub_c1=[(1, 0, 0), (0.6, 0.8, 0)], cub_c2=[(0, 1, 0), (-0.8, 0.6, 0)],
+             B_ext=(0.01, -0.02, 0.05), A0=-2e-11, latcon=0.35e-9)
+    m = inputs.random_unit(inputs.rng(1), 2, p["n"])
+    for terms in (("anis_u",), ("anis_c",), ("zeeman",), ("afm_cell",)):
+        _energy_gradient_check(p, m, terms)
+
+
+def test_energy_gradient_exchange_afm():
+    p = inputs.base_params((6, 5, 3), (2e-9, 3e-9, 1.5e-9), nsub=2)
+    p.update(Ms=[8e5, 5e5], A11=[1e-11, 2e-11], A12=-5e-12)
+    m = inputs.random_unit(inputs.rng(2), 2, p["n"])
+    _energy_gradient_check(p, m, ("exch",))
+    _energy_gradient_check(p, m, ("afm_nn",))
+
+
+def test_energy_gradient_dmi_bulk():
+    p = inputs.base_params((8, 7, 2), (2e-9, 2e-9, 2e-9))
+    p.update(Ms=[1.1e6], A11=[1.5e-11], Dint=[3e-3], dmi_layer=0)
+    m = inputs.random_unit(inputs.rng(3), 1, p["n"])
+    _energy_gradient_check(p, m, ("dmi",), interior_only=True)
+    _energy_gradient_check(p, m, ("exch",), interior_only=True)
+
+
+def test_magnetoelastic_energy_gradient():
+    p = inputs.base_params((6, 5, 1), (2e-9, 2e-9, 2e-9), nsub=2)
+    p.update(Ms=[4e5, 3e5], B1=[-6e6, 2e6], B2=[-3e6, 5e6],
+             elastic=dict(rho=6800.0, C11=3.2e11, C12=1.3e11, C44=1.1e11,
+                          eta=0.0, trac_amp=0.0, trac_freq=0.0))
+    m = inputs.random_unit(inputs.rng(4), 2, p["n"])
+    u = inputs.rng(5).standard_normal((3, 1, 5, 6)) * 1e-11
+    _energy_gradient_check(p, m, ("mel",), u=u)
+
+
+def _relax_strip(nx, ny, dx, A, D, K, Ms):
+    p = inputs.base_params((nx, ny, 1), (dx, dx, dx))
+    p.update(Ms=[Ms], A11=[A], Dint=[D], Ku1=[K], anis_u=[(0, 0, 1)],
+             alpha=[1.0])
+    m = np.zeros((1, 3, 1, ny, nx))
+    m[0, 2] = 1.0
+    P = Problem(p)
+    y, t, info, _ = P.run([m], 0.0, 0.3e-9, tol=1e-7, dt0=1e-14)
+    mm = y[0][0, :, 0, ny // 2, :]
+    return np.arctan2(mm[0], mm[2])
+
+
+def test_dmi_edge_canting_bvp():
+    """Middle row of a wide strip vs the 1-D natural-BC problem along x.
+
+    The strip is 40 nm long and 60 nm wide (15 exchange lengths), so the
+    y-edge canting has decayed to ~1e-4 rad at the middle row.
+    """
+    A, D, K, Ms = 1.5e-11, 3e-3, 1e6, 1.1e6
+    L = 40e-9
+    # lengths in nm for the solver
+    kk = K / A * 1e-18
+    slope = -D / (2 * A) * 1e-9
+
+    def f(x, y):
+        return np.vstack([y[1], kk * np.sin(y[0]) * np.cos(y[0])])
+
+    def bc(ya, yb):
+        return np.array([ya[1] - slope, yb[1] - slope])
+
+    xs = np.linspace(0, L * 1e9, 401)
+    sol = solve_bvp(f, bc, xs, np.zeros((2, xs.size)), tol=1e-10, max_nodes=100000)
+    assert sol.success
+    # the continuum edge angle obeys sin(theta0) = D / (2 sqrt(A K))
+    assert math.sin(sol.sol(0.0)[0]) == pytest.approx(D / (2 * math.sqrt(A * K)), rel=1e-3)
+    errs = []
+    for nx in (20, 40):
+        dx = L / nx
+        th = _relax_strip(nx, int(round(60e-9 / dx)), dx, A, D, K, Ms)
+        xc = (np.arange(nx) + 0.5) * dx
+        ref = sol.sol(xc * 1e9)[0]
+        errs.append(np.abs(th - ref).max())
+    # converges (first order: the ghost carries the face derivative from the
+    # cell centre) to the continuum profile
+    assert errs[1] < 0.005 * abs(sol.sol(0.0)[0])
+    assert errs[0] / errs[1] > 1.7

@@ -1,0 +1,148 @@
+"""Pins for the oracle's time integration and torques (not GPU).
+
+* The Dormand-Prince tableau satisfies the order conditions of a 5th-order
+  method (b) and of a 4th-order method (b*), with row sums c_i.
+* 5th-order convergence on a smooth ODE (error ratio ~32 per halving).
+* A single spin in a static field B z follows the closed-form damped
+  precession phi = phi0 + g' B t, tan(theta/2) = tan(theta0/2) exp(-a g' B t),
+  g' = gamma/(1+a^2); the precession frequency is gamma B/(2 pi (1+a^2)).
+  A one-cell cube with demag on gives the same (its self-field is parallel
+  to m).
+* Two sublattices coupled by homogeneous exchange with uniaxial anisotropy
+  resonate at omega = gamma sqrt(B_A (2 B_E + B_A)) (Kittel-Keffer AFMR),
+  B_E = 4|A0|/(Ms a^2), B_A = 2K/Ms.
+* |m| = 1 after every step; energy does not increase with damping, no
+  current and no time dependence.
+* Zhang-Li: a uniform state feels no spin-transfer torque.
+"""
+import math
+from fractions import Fraction as F
+
+import numpy as np
+import pytest
+
+from oracle import rk
+from oracle import torque as tq
+from oracle.system import Problem
+from paper_2411_18194_amd import inputs
+
+
+def test_order_conditions():
+    c, A, b, bs = rk.C, rk.A, rk.B5, rk.B4
+    for i in range(1, 7):
+        assert sum(A[i]) == c[i]
+    for w, order in ((b, 5), (bs, 4)):
+        s = len(w)
+        cc = c[:s]
+
+        def Ac(v):
+            return [sum((A[i][j] * v[j] for j in range(i)), F(0)) if i > 0 else F(0)
+                    for i in range(s)]
+        assert sum(w) == 1
+        assert sum(wi * ci for wi, ci in zip(w, cc)) == F(1, 2)
+        assert sum(wi * ci ** 2 for wi, ci in zip(w, cc)) == F(1, 3)
+        assert sum(wi * x for wi, x in zip(w, Ac(cc))) == F(1, 6)
+        assert sum(wi * ci ** 3 for wi, ci in zip(w, cc)) == F(1, 4)
+        assert sum(wi * ci * x for wi, ci, x in zip(w, cc, Ac(cc))) == F(1, 8)
+        assert sum(wi * x for wi, x in zip(w, Ac([ci ** 2 for ci in cc]))) == F(1, 12)
+        assert sum(wi * x for wi, x in zip(w, Ac(Ac(cc)))) == F(1, 24)
+        fifth = sum(wi * ci ** 4 for wi, ci in zip(w, cc)) == F(1, 5)
+        assert fifth == (order == 5)
+    # FSAL: the last row is b
+    assert A[6] == rk.B5[:6]
+
+
+def test_fifth_order_convergence():
+    def rhs(t, y):
+        return [np.array([y[0][0] * math.cos(t) - y[0][1], y[0][0] + 0.3 * y[0][1]])]
+
+    def run(n):
+        st = rk.Stepper(rhs, lambda y: y, lambda e: 0.0)
+        y = [np.array([1.0, 0.5])]
+        h = 2.0 / n
+        for i in range(n):
+            y, k7, _ = st.step(i * h, y, h)
+            st.accept(k7)
+        return y[0]
+    ref = run(2048)
+    e1 = np.abs(run(16) - ref).max()
+    e2 = np.abs(run(32) - ref).max()
+    assert 26 < e1 / e2 < 40
+
+
+def _single_spin(alpha, B, th0, t_end, demag=False):
+    p = inputs.base_params((1, 1, 1), (3e-9,) * 3)
+    p.update(Ms=[8e5], alpha=[alpha], B_ext=(0.0, 0.0, B), demag=demag)
+    m = np.array([math.sin(th0), 0.0, math.cos(th0)]).reshape(1, 3, 1, 1, 1)
+    P = Problem(p)
+    samples = []
+    y, t, info, s = P.run([m], 0.0, t_end, tol=1e-9, dt0=1e-14,
+                          sample_every=t_end / 20, sample=lambda y: y[0].ravel().copy())
+    return p, s
+
+
+@pytest.mark.parametrize("alpha,demag", [(0.0, False), (0.1, False), (0.02, True)])
+def test_single_spin_closed_form(alpha, demag):
+    B, th0 = 0.1, 1.0
+    p, s = _single_spin(alpha, B, th0, 200e-12, demag)
+    gp = p["gamma"] / (1 + alpha ** 2)
+    for t, m in s:
+        th = 2 * math.atan(math.tan(th0 / 2) * math.exp(-alpha * gp * B * t))
+        ph = gp * B * t
+        ref = np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)])
+        assert np.abs(m - ref).max() < 2e-6
+        assert abs(np.linalg.norm(m) - 1) < 1e-14
+
+
+def test_afmr_frequency():
+    Ms, A0, a, K = 4e5, -1e-13, 0.35e-9, 6e4
+    p = inputs.base_params((1, 1, 1), (1e-9,) * 3, nsub=2)
+    p.update(Ms=[Ms, Ms], A0=A0, latcon=a, Ku1=[K, K], alpha=[0.0, 0.0])
+    BE = 4 * abs(A0) / (Ms * a * a)
+    BA = 2 * K / Ms
+    w = p["gamma"] * math.sqrt(BA * (2 * BE + BA))
+    T = 2 * math.pi / w
+    eps = 0.01
+    m = np.zeros((2, 3, 1, 1, 1))
+    m[0, :, 0, 0, 0] = [math.sin(eps), 0, math.cos(eps)]
+    m[1, :, 0, 0, 0] = [math.sin(eps), 0, -math.cos(eps)]
+    P = Problem(p)
+    n = 200
+    y, t, info, s = P.run([m], 0.0, 4 * T, tol=1e-10, dt0=1e-15,
+                          sample_every=4 * T / n, sample=lambda y: y[0][0, 0].ravel()[0])
+    ts = np.array([a for a, _ in s])
+    mx = np.array([b for _, b in s])
+    # least-squares fit of a cos(wt) + b sin(wt) + c over a fine grid of w
+    ws = np.linspace(0.9 * w, 1.1 * w, 2001)
+    res = []
+    for wi in ws:
+        X = np.stack([np.cos(wi * ts), np.sin(wi * ts), np.ones_like(ts)], axis=1)
+        coef, r, *_ = np.linalg.lstsq(X, mx, rcond=None)
+        res.append(np.sum((X @ coef - mx) ** 2))
+    wfit = ws[int(np.argmin(res))]
+    assert wfit == pytest.approx(w, rel=2e-3)
+
+
+def test_energy_decreases_and_norm():
+    p, m0 = inputs.config_c1()
+    p = dict(p)
+    p["alpha"] = [0.5]
+    P = Problem(p)
+    y = [m0.copy()]
+    E_prev = sum(P.energies(y[0]).values())
+    t = 0.0
+    for _ in range(8):
+        y, t, info, _ = P.run(y, t, t + 2e-12, tol=1e-6, dt0=1e-14)
+        E = sum(P.energies(y[0]).values())
+        assert E <= E_prev + 1e-12 * abs(E_prev)
+        E_prev = E
+        assert np.abs(np.linalg.norm(y[0], axis=1) - 1).max() < 1e-14
+
+
+def test_zhang_li_uniform_zero():
+    m = np.zeros((3, 1, 4, 5))
+    m[0] = 0.6
+    m[1] = 0.8
+    u = tq.drift_velocity(0.5, (1e12, 0, 0), 4e5)
+    assert np.abs(tq.zhang_li_torque(m, u, 0.01, 0.1, (1e-9,) * 3)).max() == 0.0
+    assert u[0] == pytest.approx(0.5 * 9.2740100783e-24 * 1e12 / (1.602176634e-19 * 4e5))
