@@ -1,0 +1,253 @@
+/*
+ * mmp.h - C ABI of the MI355X micromagnetic hot path (libmmp.so).
+ *
+ * The library evaluates the effective field of a finite-difference
+ * micromagnet and integrates the Landau-Lifshitz-Gilbert equation with the
+ * Dormand-Prince 5(4) Runge-Kutta pair, following Moreels et al., "mumax+:
+ * extensible GPU-accelerated micromagnetics and beyond" (arXiv 2411.18194),
+ * Methods section:
+ *   dm/dt = tau (Eq. 1), tau = LLG torque (Eq. 2) + Zhang-Li torque;
+ *   B_eff = demag (zero-padded FFT convolution with the Newell tensor,
+ *   asymptotic far field; "Magnetostatic field") + exchange (Eq. 3, with
+ *   the intra- and inter-sublattice terms of an antiferromagnet) +
+ *   interfacial DMI (Eq. 4 special case, boundary condition Eq. 5) +
+ *   uniaxial/cubic anisotropy + Zeeman + magnetoelastic field (Eq. 9);
+ *   elastodynamics (Eq. 7) with the magnetoelastic force (Eq. 8);
+ *   the time solver is the Dormand-Prince pair of Table 2.
+ *
+ * Conventions
+ *   Units are SI; fields are in tesla.  Host arrays are FP64, structure of
+ *   arrays, index [sub][comp][z][y][x] with x fastest (N = nx*ny*nz cells):
+ *   m has nsub*3*N values, u and v have 3*N.
+ *   Every call returns an mmp_status: 0 on success, MMP_PENDING from
+ *   mmp_poll while a request runs, a negative code on error; the message
+ *   of the last error on the calling thread is mmp_last_error().  No call
+ *   throws across the ABI.  Inputs are copied; outputs go to caller-owned
+ *   buffers of the documented size.  A grid handle is used by one thread
+ *   at a time; a server handle is thread-safe.
+ *
+ * Precision: the state, FFTs and stencils run in FP32 or FP64 (per grid);
+ * the demagnetising tensor is built in FP64, the RK error norm, the time
+ * and the energies are FP64 in both cases.
+ */
+#ifndef MMP_H
+#define MMP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mmp_status;
+#define MMP_OK               0
+#define MMP_PENDING          1
+#define MMP_E_ARG           -1   /* invalid argument or size              */
+#define MMP_E_NOMEM         -2   /* device allocation failed               */
+#define MMP_E_HIP           -3   /* HIP runtime error                      */
+#define MMP_E_NONFINITE     -4   /* NaN/Inf appeared in the state          */
+#define MMP_E_DT_UNDERFLOW  -5   /* adaptive step fell below dt_min        */
+#define MMP_E_TOO_LARGE     -6   /* request exceeds the server's HBM budget*/
+#define MMP_E_STATE         -7   /* call out of order (e.g. no params)     */
+#define MMP_E_TICKET        -8   /* unknown ticket                         */
+
+#define MMP_FP32 0
+#define MMP_FP64 1
+
+/* Effective-field terms (bit mask for mmp_eval_heff). */
+#define MMP_T_DEMAG     (1u << 0)  /* magnetostatic field                  */
+#define MMP_T_EXCH      (1u << 1)  /* 2 A11/Ms lap m   (Eq. 3, term 1)     */
+#define MMP_T_AFM_NN    (1u << 2)  /* A12/Ms lap m'    (Eq. 3, term 2)     */
+#define MMP_T_AFM_CELL  (1u << 3)  /* 4 A0/(Ms a^2) m' (Eq. 3, term 3)     */
+#define MMP_T_DMI       (1u << 4)  /* interfacial DMI                      */
+#define MMP_T_ANIS_U    (1u << 5)  /* uniaxial anisotropy                  */
+#define MMP_T_ANIS_C    (1u << 6)  /* cubic anisotropy                     */
+#define MMP_T_ZEEMAN    (1u << 7)  /* external field                       */
+#define MMP_T_MEL       (1u << 8)  /* magnetoelastic field (Eq. 9)         */
+#define MMP_T_ALL       0x1FFu
+#define MMP_T_ZL        (1u << 9)  /* add Zhang-Li torque (torque output)  */
+#define MMP_OUT_TORQUE  (1u << 16) /* b_out receives dm/dt, not B          */
+
+/* energy_out of mmp_eval_heff: MMP_NENERGY doubles, joules, in this order:
+ * demag, exch, afm_nn, afm_cell, dmi, anis_u, anis_c, zeeman, mel, elastic */
+#define MMP_NENERGY 10
+
+typedef struct mmp_grid_s* mmp_grid;
+typedef struct mmp_server_s* mmp_server;
+
+/* Per-sublattice material constants. */
+typedef struct {
+  double Ms;          /* saturation magnetisation, A/m (0 = empty)        */
+  double A11;         /* exchange stiffness, J/m                          */
+  double alpha;       /* Gilbert damping                                  */
+  double Ku1, Ku2;    /* uniaxial anisotropy, J/m^3                       */
+  double anis_u[3];   /* uniaxial axis (unit)                             */
+  double Kc1;         /* cubic anisotropy, J/m^3                          */
+  double cub_c1[3];   /* cubic axes c1, c2 (c3 = c1 x c2)                 */
+  double cub_c2[3];
+  double Dint;        /* interfacial DMI, J/m^2 (one sublattice only)     */
+  double B1, B2;      /* magnetoelastic coupling, J/m^3                   */
+  double zl_P;        /* Zhang-Li spin polarisation                       */
+  double zl_xi;       /* Zhang-Li non-adiabaticity                        */
+} mmp_sublattice;
+
+typedef struct {
+  uint32_t struct_size;   /* sizeof(mmp_params)                           */
+  int32_t precision;      /* MMP_FP32 or MMP_FP64                          */
+  int32_t nsub;           /* 1 (ferromagnet) or 2 (two sublattices)        */
+  int32_t demag;          /* nonzero: magnetostatic field on               */
+  double gamma;           /* gyromagnetic ratio, rad/(s T)                 */
+  mmp_sublattice sub[2];
+  double A0;              /* homogeneous inter-sublattice exchange, J/m    */
+  double A12;             /* inhomogeneous inter-sublattice exchange, J/m  */
+  double latcon;          /* lattice constant a, m                         */
+  double B_ext[3];        /* external field, T                             */
+  double j[3];            /* current density, A/m^2 (Zhang-Li)             */
+  int32_t dmi_layer;      /* z-layer carrying the DMI; -1 = every layer    */
+  int32_t ngrains;        /* 0 = no grains; else grain/grain_axes given    */
+  const uint16_t* grain;  /* N grain ids (copied), or NULL                 */
+  const double* grain_axes; /* ngrains*3 uniaxial axes (copied), or NULL   */
+  int32_t elastic;        /* nonzero: elastodynamics on (u, v in state)    */
+  int32_t pad0;
+  double rho, C11, C12, C44, eta;  /* kg/m^3, Pa, kg/(m^3 s)               */
+  double trac_amp;        /* shear traction sigma_xz on x=0 face, Pa       */
+  double trac_freq;       /* ... times sin(2 pi f t), Hz                   */
+  double tol;             /* adaptive error tolerance (default 1e-5)       */
+  double dt0;             /* first adaptive step, s (default 1e-14)        */
+  double dt_min;          /* underflow limit, s (default 1e-20)            */
+} mmp_params;
+
+typedef struct {
+  double t;         /* time after the call, s                            */
+  double dt;        /* controller's next step, s                         */
+  double err;       /* last error estimate                               */
+  int64_t steps;    /* accepted steps                                    */
+  int64_t rejects;  /* rejected attempts                                 */
+} mmp_step_info;
+
+typedef struct {
+  uint32_t struct_size;
+  int32_t max_samples;    /* capacity of sample_t / sample_m               */
+  double sample_every;    /* output interval, s (0 = only t_end)           */
+  double* sample_t;       /* [max_samples] sample times, or NULL           */
+  double* sample_m;       /* [max_samples][nsub][3] averages of m, or NULL */
+  int64_t max_steps;      /* safety limit on attempts (0 = none)           */
+} mmp_run_opts;
+
+typedef struct {
+  double t;
+  double dt;
+  int64_t steps;
+  int64_t rejects;
+  int32_t nsamples;
+  int32_t status;
+} mmp_run_info;
+
+/* ---------------------------------------------------------------- grid -- */
+
+/* Create a grid of nx*ny*nz cells of size cellsize[3] (metres).  The grid
+ * owns its device memory until mmp_grid_destroy.  MMP_E_ARG for any size
+ * < 1 or a demag pad above 4096 per axis. */
+mmp_status mmp_grid_create(int32_t nx, int32_t ny, int32_t nz,
+                           const double cellsize[3], mmp_grid* out);
+mmp_status mmp_grid_destroy(mmp_grid g);
+
+/* Copy the material, precision and solver settings (p->struct_size must
+ * match).  Builds the demagnetising kernel (FP64 Newell / quadrature /
+ * asymptotic tensor, transformed on the GPU) when p->demag is set and the
+ * geometry changed.  Invalidates the FSAL stage. */
+mmp_status mmp_set_params(mmp_grid g, const mmp_params* p);
+
+/* Upload the state: m (nsub*3*N, normalised by the caller), u and v (3*N
+ * each, may be NULL = zero; ignored without elasticity), time t. */
+mmp_status mmp_set_state(mmp_grid g, const double* m, const double* u,
+                         const double* v, double t);
+/* Download the state; any pointer may be NULL. */
+mmp_status mmp_get_state(mmp_grid g, double* m, double* u, double* v,
+                         double* t, double* dt);
+
+/* Evaluate the effective field of the current state for the terms in
+ * term_mask.  b_out (nsub*3*N, may be NULL) receives B (T) or, with
+ * MMP_OUT_TORQUE, dm/dt (1/s) of those terms (+ Zhang-Li with MMP_T_ZL).
+ * energy_out (MMP_NENERGY, may be NULL) receives per-term energies of all
+ * terms (FP64 accumulation).  Synchronous. */
+mmp_status mmp_eval_heff(mmp_grid g, uint32_t term_mask, double* b_out,
+                         double* energy_out);
+
+/* One Dormand-Prince step.  dt_fixed > 0: fixed step, enqueued without a
+ * host synchronisation when info is NULL.  dt_fixed == 0: adaptive, retried
+ * until accepted (synchronous). */
+mmp_status mmp_step(mmp_grid g, double dt_fixed, mmp_step_info* info);
+
+/* nsteps fixed steps of dt, all enqueued on the grid's stream with no host
+ * synchronisation (info may be NULL; when given the call synchronises). */
+mmp_status mmp_run_fixed(mmp_grid g, double dt, int64_t nsteps,
+                         mmp_step_info* info);
+
+/* Adaptive run from the current time to t_end with device-side step control
+ * (no host round trip per step); steps land exactly on sample times and on
+ * t_end.  opts may be NULL. */
+mmp_status mmp_run(mmp_grid g, double t_end, const mmp_run_opts* opts,
+                   mmp_run_info* info);
+
+/* Use an existing HIP stream (e.g. torch.cuda.current_stream().cuda_stream)
+ * for all later work on this grid; NULL = the library's own stream. */
+mmp_status mmp_set_stream(mmp_grid g, void* hip_stream);
+mmp_status mmp_synchronize(mmp_grid g);
+
+/* Device footprint of the grid in bytes (state, stages, FFT buffers, kernel). */
+mmp_status mmp_grid_bytes(mmp_grid g, int64_t* bytes);
+
+/* FP64 demagnetising tensor on non-negative offsets, 6*N values ordered
+ * (xx, yy, zz, xy, xz, yz)[z][y][x] (offset (x dx, y dy, z dz)). */
+mmp_status mmp_get_demag_tensor(mmp_grid g, double* n6);
+
+/* Kernel timing with HIP events on the grid's stream.  While enabled every
+ * launch of the hot path is bracketed by events; mmp_prof_read returns,
+ * for kernel class idx (0 <= idx < mmp_prof_count()), its name, the summed
+ * duration in ms and the launch count since the last reset. */
+mmp_status mmp_prof_enable(mmp_grid g, int32_t on);
+int32_t mmp_prof_count(void);
+mmp_status mmp_prof_read(mmp_grid g, int32_t idx, const char** name,
+                         double* total_ms, int64_t* launches);
+mmp_status mmp_prof_reset(mmp_grid g);
+
+/* -------------------------------------------------------------- server -- */
+
+typedef struct {
+  uint32_t struct_size;
+  int64_t hbm_budget;     /* bytes of device memory for requests           */
+  int32_t max_active;     /* concurrent requests on the device             */
+  int32_t precision;      /* MMP_FP32 or MMP_FP64 for every request        */
+} mmp_server_opts;
+
+typedef struct {
+  uint32_t struct_size;
+  int32_t nx, ny, nz;
+  double cellsize[3];
+  mmp_params params;      /* precision field is overridden by the server   */
+  const double* m0;       /* nsub*3*N initial state (copied at submit)     */
+  double t_relax;         /* relaxation time, s                            */
+} mmp_request;
+
+typedef struct {
+  int32_t status;         /* MMP_OK or an error code                       */
+  int32_t nsub;
+  double m_avg[2][3];     /* average m per sublattice at t_relax           */
+  double energy;          /* total energy, J                               */
+  int64_t steps, rejects;
+  double t_submit, t_admit, t_done;  /* seconds on the server's clock      */
+} mmp_result;
+
+mmp_status mmp_server_create(const mmp_server_opts* o, mmp_server* out);
+mmp_status mmp_submit(mmp_server s, const mmp_request* r, uint64_t* ticket);
+mmp_status mmp_poll(mmp_server s, uint64_t ticket, mmp_result* out);
+mmp_status mmp_server_destroy(mmp_server s);
+double mmp_server_clock(mmp_server s);
+
+const char* mmp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MMP_H */

@@ -1,0 +1,71 @@
+// Field/torque/RK kernels: argument structs and launchers.
+#pragma once
+
+#include "common.h"
+#include "prof.h"
+
+namespace mmp {
+
+constexpr int kNE = 10;  // energy terms, order of MMP_NENERGY
+constexpr int kTileX = 64, kTileY = 4;
+
+template <typename T>
+struct SubC {
+  T ms;                       // Ms (demag source)
+  T cex, cnn, ccell;          // 2A11/Ms, A12/Ms, 4A0/(Ms a^2)
+  T cdmi, kdmi;               // 2D/Ms, ghost slope -D/(2 A11)
+  T cku1, cku2, u[3];         // 2Ku1/Ms, 4Ku2/Ms, axis
+  T ckc, c1[3], c2[3], c3[3]; // 2Kc1/Ms, cubic frame
+  T cmel1, cmel2;             // 2B1/Ms, 2B2/Ms
+  T gl, alpha;                // gamma/(1+alpha^2), alpha
+  T zu[3], zla, zlb;          // drift velocity, (1+xi a)/(1+a^2), (xi-a)/(1+a^2)
+  int has_zl;
+  int nonzero;                // Ms != 0
+  double Ms_d, Ku1_d, Ku2_d, Kc1_d, B1_d, B2_d;
+};
+
+template <typename T>
+struct FieldArgs {
+  int nx, ny, nz, nsub;
+  long N;
+  T dx, dy, dz, idx2, idy2, idz2, i2dx, i2dy, i2dz;
+  SubC<T> sc[2];
+  T bext[3];
+  int dmi_layer;
+  int has_demag, has_dmi, has_anis_u, has_anis_c, has_mel;
+  const uint16_t* grain;
+  const T* gaxes;
+  const T* Bd;
+  const T* eps;
+  const Table<T>* tbl;
+  Ctrl* ctrl;
+  int stage;
+  int fuse2;
+  double* errpart;
+  uint32_t mask;
+  T* bout;
+  int out_torque;
+  int add_zl;
+  double* epart;
+  double V;
+  int nbx, nby, nb_pad;
+};
+
+template <typename T>
+void launch_field(const FieldArgs<T>& a, bool eval, hipStream_t st, Prof* prof);
+
+template <typename T>
+void launch_combine2(const Table<T>* tbl, const Ctrl* ctrl, long Ncell, int nsub, hipStream_t st,
+                     Prof* prof);
+
+template <typename T>
+void launch_control(Ctrl* ctrl, Table<T>* tbl, const double* errpart, int nerr, int elastic,
+                    hipStream_t st, Prof* prof);
+
+template <typename T>
+void launch_sample(Ctrl* ctrl, const Table<T>* tbl, int nsub, long N, double* part, int nblk,
+                   double* sample_t, double* sample_m, int cap, hipStream_t st, Prof* prof);
+
+void launch_energy_final(const double* epart, int nblk, double* out, hipStream_t st);
+
+}  // namespace mmp

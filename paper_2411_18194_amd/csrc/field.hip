@@ -1,0 +1,530 @@
+// Fused effective field + torque + Runge-Kutta stage kernel.
+//
+// One thread owns an (x, y) column and marches along z with the z
+// neighbours kept in registers; x/y neighbours come from global memory
+// through L1/L2 (a 64x4 tile per block, blocks remapped so neighbouring
+// tiles share an XCD's L2).  Per cell and sublattice it forms
+//   B = B_demag + exchange (Eq. 3: 2A11/Ms lap m, A12/Ms lap m', 4A0/(Ms a^2) m')
+//     + interfacial DMI + uniaxial/cubic anisotropy + Zeeman + B_mel (Eq. 9)
+// and the torque tau = LLG (Eq. 2) + Zhang-Li, then, in a Runge-Kutta
+// stage, writes k_s and immediately the next stage input
+// y_{s+1} = normalise(y_n + h sum_j a_{s+1,j} k_j) (all point-wise), or at
+// the last stage the FP64 error norm |sum_j e_j k_j| (Dormand-Prince 5(4)).
+//
+// Boundaries: a missing neighbour is the cell itself (Neumann), except in a
+// layer with interfacial DMI, where the ghost is m -/+ d (dm/dn) with the
+// natural boundary condition 2A dn m = -D (z x n) x m (Eq. 5 for one
+// sublattice).  Zhang-Li uses clamped central differences.
+#include "field.h"
+
+namespace mmp {
+
+template <typename T>
+__device__ __forceinline__ void cross3(const T* a, const T* b, T* o) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+template <typename T>
+__device__ __forceinline__ double dot3d(const T* a, const T* b) {
+  return (double)a[0] * b[0] + (double)a[1] * b[1] + (double)a[2] * b[2];
+}
+
+template <typename T, int NSUB, bool EVAL>
+__global__ __launch_bounds__(256) void k_field(const FieldArgs<T> a) {
+  if (ctrl_stopped(a.ctrl)) return;
+  const int w = xcd_remap(blockIdx.x, a.nb_pad);
+  if (w >= a.nbx * a.nby) return;
+  const int x = (w % a.nbx) * kTileX + (int)(threadIdx.x % kTileX);
+  const int y = (w / a.nbx) * kTileY + (int)(threadIdx.x / kTileX);
+  const bool in = x < a.nx && y < a.ny;
+  const long N = a.N;
+  const long N3 = 3 * N;
+  const int stage = a.stage;
+  const T* __restrict__ m = EVAL ? a.tbl->yn : stage_in(a.tbl, stage);
+
+  double h = 0.0;
+  T ca[6] = {0, 0, 0, 0, 0, 0};
+  const T* kin[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  T* kout = nullptr;
+  T* ynext = nullptr;
+  const T* yn = nullptr;
+  if (!EVAL) {
+    h = a.ctrl->h;
+    kout = a.tbl->k[stage - 1];
+    yn = a.tbl->yn;
+    for (int j = 0; j < stage - 1; ++j) kin[j] = a.tbl->k[j];
+    if (stage < 7) {
+      ynext = stage_out(a.tbl, stage);
+      for (int j = 0; j < stage; ++j) ca[j] = (T)(DP::a[stage][j] * h);
+    } else {
+      if (a.fuse2) ynext = a.tbl->sa;
+      ca[0] = (T)(DP::a[1][0] * h);
+      for (int j = 0; j < 6; ++j) kin[j] = a.tbl->k[j];
+    }
+  }
+
+  double eacc[kNE];
+  for (int t = 0; t < kNE; ++t) eacc[t] = 0.0;
+  double emax = 0.0;
+
+  if (in) {
+    T cur[NSUB][3], zm[NSUB][3], zp[NSUB][3];
+    const long col = (long)y * a.nx + x;
+    const long plane = (long)a.nx * a.ny;
+#pragma unroll
+    for (int s = 0; s < NSUB; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        cur[s][c] = m[s * N3 + c * N + col];
+        zm[s][c] = cur[s][c];
+      }
+    for (int z = 0; z < a.nz; ++z) {
+      const long i = (long)z * plane + col;
+#pragma unroll
+      for (int s = 0; s < NSUB; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          zp[s][c] = (z + 1 < a.nz) ? m[s * N3 + c * N + i + plane] : cur[s][c];
+      // clamped in-plane neighbours
+      T xm[NSUB][3], xp[NSUB][3], ym[NSUB][3], yp[NSUB][3];
+#pragma unroll
+      for (int s = 0; s < NSUB; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const T* mc = m + s * N3 + c * N + i;
+          xm[s][c] = x > 0 ? mc[-1] : cur[s][c];
+          xp[s][c] = x + 1 < a.nx ? mc[1] : cur[s][c];
+          ym[s][c] = y > 0 ? mc[-a.nx] : cur[s][c];
+          yp[s][c] = y + 1 < a.ny ? mc[a.nx] : cur[s][c];
+        }
+      T Bd[3] = {0, 0, 0};
+      if (a.has_demag) {
+        Bd[0] = a.Bd[i];
+        Bd[1] = a.Bd[N + i];
+        Bd[2] = a.Bd[2 * N + i];
+      }
+      T ep[6] = {0, 0, 0, 0, 0, 0};
+      if (a.has_mel) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) ep[c] = a.eps[c * N + i];
+      }
+      T uax[3];
+      if (a.has_anis_u && a.grain) {
+        const int g = a.grain[i];
+        uax[0] = a.gaxes[3 * g];
+        uax[1] = a.gaxes[3 * g + 1];
+        uax[2] = a.gaxes[3 * g + 2];
+      }
+      const bool dmil = NSUB == 1 && a.has_dmi && (a.dmi_layer < 0 || z == a.dmi_layer);
+
+#pragma unroll
+      for (int s = 0; s < NSUB; ++s) {
+        const SubC<T>& C = a.sc[s];
+        const T* mm = cur[s];
+        // ghosted in-plane neighbours for exchange/DMI
+        T gxm[3], gxp[3], gym[3], gyp[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          gxm[c] = xm[s][c]; gxp[c] = xp[s][c]; gym[c] = ym[s][c]; gyp[c] = yp[s][c];
+        }
+        if (dmil) {
+          const T k = C.kdmi;
+          if (x == 0) {
+            gxm[0] = mm[0] - a.dx * k * mm[2]; gxm[1] = mm[1]; gxm[2] = mm[2] + a.dx * k * mm[0];
+          }
+          if (x + 1 == a.nx) {
+            gxp[0] = mm[0] + a.dx * k * mm[2]; gxp[1] = mm[1]; gxp[2] = mm[2] - a.dx * k * mm[0];
+          }
+          if (y == 0) {
+            gym[0] = mm[0]; gym[1] = mm[1] - a.dy * k * mm[2]; gym[2] = mm[2] + a.dy * k * mm[1];
+          }
+          if (y + 1 == a.ny) {
+            gyp[0] = mm[0]; gyp[1] = mm[1] + a.dy * k * mm[2]; gyp[2] = mm[2] - a.dy * k * mm[1];
+          }
+        }
+        T B[3] = {0, 0, 0};
+        T bt[3];
+        auto add = [&](int term, const T* b) {
+          if (!EVAL || (a.mask & (1u << term))) {
+            B[0] += b[0]; B[1] += b[1]; B[2] += b[2];
+          }
+        };
+        // exchange
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const T l = ((gxm[c] - mm[c]) + (gxp[c] - mm[c])) * a.idx2 +
+                      ((gym[c] - mm[c]) + (gyp[c] - mm[c])) * a.idy2 +
+                      ((zm[s][c] - mm[c]) + (zp[s][c] - mm[c])) * a.idz2;
+          bt[c] = C.cex * l;
+        }
+        add(1, bt);
+        if (EVAL) eacc[1] += -0.5 * C.Ms_d * dot3d(mm, bt);
+        // interfacial DMI
+        if (dmil) {
+          bt[0] = C.cdmi * ((gxp[2] - gxm[2]) * a.i2dx);
+          bt[1] = C.cdmi * ((gyp[2] - gym[2]) * a.i2dy);
+          bt[2] = -C.cdmi * ((gxp[0] - gxm[0]) * a.i2dx + (gyp[1] - gym[1]) * a.i2dy);
+          add(4, bt);
+          if (EVAL) eacc[4] += -0.5 * C.Ms_d * dot3d(mm, bt);
+        }
+        // two-sublattice exchange
+        if (NSUB == 2) {
+          const int o = 1 - s;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const T mo = cur[o][c];
+            const T l = ((xm[o][c] - mo) + (xp[o][c] - mo)) * a.idx2 +
+                        ((ym[o][c] - mo) + (yp[o][c] - mo)) * a.idy2 +
+                        ((zm[o][c] - mo) + (zp[o][c] - mo)) * a.idz2;
+            bt[c] = C.cnn * l;
+          }
+          add(2, bt);
+          if (EVAL) eacc[2] += -0.5 * C.Ms_d * dot3d(mm, bt);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) bt[c] = C.ccell * cur[o][c];
+          add(3, bt);
+          if (EVAL) eacc[3] += -0.5 * C.Ms_d * dot3d(mm, bt);
+        }
+        // demag
+        if (a.has_demag && C.nonzero) {
+          add(0, Bd);
+          if (EVAL) eacc[0] += -0.5 * C.Ms_d * dot3d(mm, Bd);
+        }
+        // uniaxial anisotropy
+        if (a.has_anis_u) {
+          const T* u = a.grain ? uax : C.u;
+          const T um = u[0] * mm[0] + u[1] * mm[1] + u[2] * mm[2];
+          const T f = C.cku1 * um + C.cku2 * um * um * um;
+          bt[0] = f * u[0]; bt[1] = f * u[1]; bt[2] = f * u[2];
+          add(5, bt);
+          if (EVAL && C.nonzero) {
+            const double umd = (double)um;
+            eacc[5] += -C.Ku1_d * umd * umd - C.Ku2_d * umd * umd * umd * umd;
+          }
+        }
+        // cubic anisotropy
+        if (a.has_anis_c) {
+          const T a1 = C.c1[0] * mm[0] + C.c1[1] * mm[1] + C.c1[2] * mm[2];
+          const T a2 = C.c2[0] * mm[0] + C.c2[1] * mm[1] + C.c2[2] * mm[2];
+          const T a3 = C.c3[0] * mm[0] + C.c3[1] * mm[1] + C.c3[2] * mm[2];
+          const T f1 = -C.ckc * a1 * (a2 * a2 + a3 * a3);
+          const T f2 = -C.ckc * a2 * (a1 * a1 + a3 * a3);
+          const T f3 = -C.ckc * a3 * (a1 * a1 + a2 * a2);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) bt[c] = f1 * C.c1[c] + f2 * C.c2[c] + f3 * C.c3[c];
+          add(6, bt);
+          if (EVAL && C.nonzero) {
+            const double d1 = a1, d2 = a2, d3 = a3;
+            eacc[6] += C.Kc1_d * (d1 * d1 * d2 * d2 + d2 * d2 * d3 * d3 + d3 * d3 * d1 * d1);
+          }
+        }
+        // Zeeman
+        add(7, a.bext);
+        if (EVAL) eacc[7] += -C.Ms_d * dot3d(mm, a.bext);
+        // magnetoelastic field
+        if (a.has_mel) {
+          bt[0] = -(C.cmel1 * ep[0] * mm[0] + C.cmel2 * (ep[3] * mm[1] + ep[4] * mm[2]));
+          bt[1] = -(C.cmel1 * ep[1] * mm[1] + C.cmel2 * (ep[3] * mm[0] + ep[5] * mm[2]));
+          bt[2] = -(C.cmel1 * ep[2] * mm[2] + C.cmel2 * (ep[4] * mm[0] + ep[5] * mm[1]));
+          add(8, bt);
+          if (EVAL && C.nonzero) {
+            const double m0 = mm[0], m1 = mm[1], m2 = mm[2];
+            eacc[8] += C.B1_d * ((double)ep[0] * m0 * m0 + (double)ep[1] * m1 * m1 +
+                                 (double)ep[2] * m2 * m2) +
+                       2.0 * C.B2_d * ((double)ep[3] * m0 * m1 + (double)ep[4] * m0 * m2 +
+                                       (double)ep[5] * m1 * m2);
+          }
+        }
+        // torque
+        T mxB[3], mxmxB[3], tau[3];
+        cross3(mm, B, mxB);
+        cross3(mm, mxB, mxmxB);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) tau[c] = -C.gl * (mxB[c] + C.alpha * mxmxB[c]);
+        const bool zl = EVAL ? (a.add_zl && C.has_zl) : C.has_zl;
+        if (zl) {
+          T dm[3], mxdm[3], mxmxdm[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            dm[c] = C.zu[0] * (xp[s][c] - xm[s][c]) * a.i2dx +
+                    C.zu[1] * (yp[s][c] - ym[s][c]) * a.i2dy +
+                    C.zu[2] * (zp[s][c] - zm[s][c]) * a.i2dz;
+          cross3(mm, dm, mxdm);
+          cross3(mm, mxdm, mxmxdm);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) tau[c] -= C.zla * mxmxdm[c] + C.zlb * mxdm[c];
+        }
+        const long base = s * N3 + i;
+        if (EVAL) {
+          if (a.bout) {
+            const T* o = a.out_torque ? tau : B;
+            a.bout[base] = o[0];
+            a.bout[base + N] = o[1];
+            a.bout[base + 2 * N] = o[2];
+          }
+        } else {
+          if (!(isfinite(tau[0]) && isfinite(tau[1]) && isfinite(tau[2])))
+            atomicOr(&a.ctrl->nonfinite, 1);
+          kout[base] = tau[0];
+          kout[base + N] = tau[1];
+          kout[base + 2 * N] = tau[2];
+          if (stage < 7) {
+            T v[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              T acc = yn[base + c * N];
+              for (int j = 0; j < stage - 1; ++j) acc += ca[j] * kin[j][base + c * N];
+              acc += ca[stage - 1] * tau[c];
+              v[c] = acc;
+            }
+            const T inv = T(1) / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            ynext[base] = v[0] * inv;
+            ynext[base + N] = v[1] * inv;
+            ynext[base + 2 * N] = v[2] * inv;
+          } else if (!a.fuse2) {
+            double ev[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              double acc = DP::e[6] * (double)tau[c];
+              for (int j = 0; j < 6; ++j)
+                if (DP::e[j] != 0.0) acc += DP::e[j] * (double)kin[j][base + c * N];
+              ev[c] = acc;
+            }
+            const double nrm = sqrt(ev[0] * ev[0] + ev[1] * ev[1] + ev[2] * ev[2]);
+            emax = nrm > emax ? nrm : emax;
+          } else {
+            {
+              T v[3];
+#pragma unroll
+              for (int c = 0; c < 3; ++c) v[c] = mm[c] + ca[0] * tau[c];
+              const T inv = T(1) / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+              ynext[base] = v[0] * inv;
+              ynext[base + N] = v[1] * inv;
+              ynext[base + 2 * N] = v[2] * inv;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < NSUB; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          zm[s][c] = cur[s][c];
+          cur[s][c] = zp[s][c];
+        }
+    }
+  }
+
+  if (EVAL) {
+    if (a.epart) {
+      __shared__ double red[kNE][256];
+      for (int t = 0; t < kNE; ++t) red[t][threadIdx.x] = eacc[t] * a.V;
+      __syncthreads();
+      for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st)
+          for (int t = 0; t < kNE; ++t) red[t][threadIdx.x] += red[t][threadIdx.x + st];
+        __syncthreads();
+      }
+      if (threadIdx.x < kNE) a.epart[(long)w * kNE + threadIdx.x] = red[threadIdx.x][0];
+    }
+  } else if (stage == 7 && !a.fuse2) {
+    __shared__ double red[256];
+    red[threadIdx.x] = emax;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) a.errpart[w] = red[0];
+  }
+}
+
+template <typename T>
+void launch_field(const FieldArgs<T>& a, bool eval, hipStream_t st, Prof* prof) {
+  ProfScope ps(prof, P_FIELD, st);
+  const dim3 g(a.nb_pad), b(256);
+  if (a.nsub == 1) {
+    if (eval) hipLaunchKernelGGL((k_field<T, 1, true>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((k_field<T, 1, false>), g, b, 0, st, a);
+  } else {
+    if (eval) hipLaunchKernelGGL((k_field<T, 2, true>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((k_field<T, 2, false>), g, b, 0, st, a);
+  }
+}
+
+// --------------------------------------------------------- combine2 ----
+// Stage-2 input for a new attempt: normalise(y_n + h a21 k1).
+template <typename T>
+__global__ void k_combine2_cells(const Table<T>* tbl, const Ctrl* ctrl, long Ncell, int nsub) {
+  if (ctrl_stopped(ctrl)) return;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Ncell * nsub) return;
+  const long s = i / Ncell, cell = i - s * Ncell;
+  const long base = s * 3 * Ncell + cell;
+  const T c = (T)(DP::a[1][0] * ctrl->h);
+  const T* yn = tbl->yn;
+  const T* k1 = tbl->k[0];
+  T v[3];
+  for (int q = 0; q < 3; ++q) v[q] = yn[base + q * Ncell] + c * k1[base + q * Ncell];
+  const T inv = T(1) / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  T* o = tbl->sa;
+  for (int q = 0; q < 3; ++q) o[base + q * Ncell] = v[q] * inv;
+}
+
+template <typename T>
+void launch_combine2(const Table<T>* tbl, const Ctrl* ctrl, long Ncell, int nsub, hipStream_t st,
+                     Prof* prof) {
+  ProfScope ps(prof, P_COMBINE, st);
+  const long n = Ncell * nsub;
+  hipLaunchKernelGGL((k_combine2_cells<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                     tbl, ctrl, Ncell, nsub);
+}
+
+// ---------------------------------------------------------- control ----
+template <typename T>
+__global__ void k_control(Ctrl* c, Table<T>* tbl, const double* errpart, int nerr, int elastic) {
+  if (c->done || c->status) return;
+  __shared__ double red[256];
+  double e = 0.0;
+  if (!c->fixed)
+    for (int i = threadIdx.x; i < nerr; i += blockDim.x) e = fmax(e, errpart[i]);
+  red[threadIdx.x] = e;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  if (c->nonfinite) {
+    c->status = MMP_E_NONFINITE;
+    c->done = 1;
+    return;
+  }
+  const double h = c->h;
+  const double err = c->fixed ? 0.0 : h * red[0];
+  c->err = err;
+  const bool acc = c->fixed || err <= c->tol;
+  c->accepted = acc ? 1 : 0;
+  if (acc) {
+    T* t;
+    t = tbl->yn; tbl->yn = tbl->ynew; tbl->ynew = t;
+    t = tbl->k[0]; tbl->k[0] = tbl->k[6]; tbl->k[6] = t;
+    if (elastic) {
+      t = tbl->un; tbl->un = tbl->unew; tbl->unew = t;
+      t = tbl->vn; tbl->vn = tbl->vnew; tbl->vnew = t;
+      t = tbl->ku[0]; tbl->ku[0] = tbl->ku[6]; tbl->ku[6] = t;
+      t = tbl->kv[0]; tbl->kv[0] = tbl->kv[6]; tbl->kv[6] = t;
+    }
+    c->steps += 1;
+    if (c->fixed) {
+      c->sample_k += 1;  // counts steps of this segment
+      c->t = c->t0 + (double)c->sample_k * h;
+      if (c->max_attempts > 0 && c->sample_k >= c->max_attempts) c->done = 1;
+    } else {
+      c->t = c->land ? fmin(c->t_next, c->t_end) : c->t + h;
+      if (c->land && c->sample_every > 0.0 && c->t == c->t_next) {
+        c->sample_pending = 1;
+        c->sample_k += 1;
+        c->t_next = c->t0 + (double)c->sample_k * c->sample_every;
+      }
+      if (c->t >= c->t_end) c->done = 1;
+    }
+  } else {
+    c->rejects += 1;
+  }
+  if (!c->fixed) {
+    double fac = 2.0;
+    if (err > 0.0) fac = 0.8 * pow(c->tol / err, 0.2);
+    fac = fmin(2.0, fmax(0.1, fac));
+    c->dt = h * fac;
+    if (c->dt < c->dt_min) {
+      c->status = MMP_E_DT_UNDERFLOW;
+      c->done = 1;
+    }
+    if (c->max_attempts > 0 && c->steps + c->rejects >= c->max_attempts) c->done = 1;
+    const double target = fmin(c->t_next, c->t_end);
+    const double rem = target - c->t;
+    c->land = c->dt >= rem ? 1 : 0;
+    c->h = c->land ? rem : c->dt;
+  }
+}
+
+template <typename T>
+void launch_control(Ctrl* ctrl, Table<T>* tbl, const double* errpart, int nerr, int elastic,
+                    hipStream_t st, Prof* prof) {
+  ProfScope ps(prof, P_CONTROL, st);
+  hipLaunchKernelGGL((k_control<T>), dim3(1), dim3(256), 0, st, ctrl, tbl, errpart, nerr, elastic);
+}
+
+// ----------------------------------------------------------- sampling --
+template <typename T>
+__global__ void k_sample_part(const Ctrl* c, const Table<T>* tbl, int nsub, long N, double* part) {
+  if (!c->sample_pending) return;
+  __shared__ double red[6][256];
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  const T* y = tbl->yn;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x)
+    for (int s = 0; s < nsub; ++s)
+      for (int q = 0; q < 3; ++q) acc[s * 3 + q] += (double)y[(s * 3 + q) * N + i];
+  for (int q = 0; q < 6; ++q) red[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st)
+      for (int q = 0; q < 6; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_sample_final(Ctrl* c, const double* part, int nblk, long N, int nsub,
+                               double* sample_t, double* sample_m, int cap) {
+  if (!c->sample_pending) return;
+  if (threadIdx.x != 0) return;
+  const int k = c->nsamples;
+  if (k < cap) {
+    sample_t[k] = c->t;
+    for (int q = 0; q < 3 * nsub; ++q) {
+      double acc = 0.0;
+      for (int b = 0; b < nblk; ++b) acc += part[b * 6 + q];
+      sample_m[k * 3 * nsub + q] = acc / (double)N;
+    }
+  }
+  c->nsamples = k + 1;
+  c->sample_pending = 0;
+}
+
+template <typename T>
+void launch_sample(Ctrl* ctrl, const Table<T>* tbl, int nsub, long N, double* part, int nblk,
+                   double* sample_t, double* sample_m, int cap, hipStream_t st, Prof* prof) {
+  ProfScope ps(prof, P_REDUCE, st);
+  hipLaunchKernelGGL((k_sample_part<T>), dim3(nblk), dim3(256), 0, st, ctrl, tbl, nsub, N, part);
+  hipLaunchKernelGGL(k_sample_final, dim3(1), dim3(64), 0, st, ctrl, part, nblk, N, nsub, sample_t,
+                     sample_m, cap);
+}
+
+__global__ void k_energy_final(const double* epart, int nblk, double* out) {
+  const int t = threadIdx.x;
+  if (t >= kNE) return;
+  double acc = 0.0;
+  for (int b = 0; b < nblk; ++b) acc += epart[(long)b * kNE + t];
+  out[t] = acc;
+}
+
+void launch_energy_final(const double* epart, int nblk, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(64), 0, st, epart, nblk, out);
+}
+
+#define INST(T)                                                                              \
+  template void launch_field<T>(const FieldArgs<T>&, bool, hipStream_t, Prof*);             \
+  template void launch_combine2<T>(const Table<T>*, const Ctrl*, long, int, hipStream_t,    \
+                                   Prof*);                                                   \
+  template void launch_control<T>(Ctrl*, Table<T>*, const double*, int, int, hipStream_t,   \
+                                  Prof*);                                                    \
+  template void launch_sample<T>(Ctrl*, const Table<T>*, int, long, double*, int, double*,  \
+                                 double*, int, hipStream_t, Prof*);
+INST(float)
+INST(double)
+
+}  // namespace mmp

@@ -1,0 +1,640 @@
+// Grid driver: device buffers, parameter coefficients, and the enqueueing
+// of Dormand-Prince steps whose control lives on the device.
+#include <algorithm>
+#include <cstring>
+
+#include "grid.h"
+
+namespace mmp {
+
+template <typename T>
+struct Buf {
+  T* p = nullptr;
+  size_t n = 0;
+  int alloc(size_t count) {
+    n = count;
+    if (count == 0) return 0;
+    return hipMalloc(&p, count * sizeof(T)) == hipSuccess ? 0 : -1;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+template <typename T>
+struct Grid final : GridBase {
+  // state and stages
+  Buf<T> y[2], sa, sb, k[7];
+  Buf<T> u[2], v[2], usa, usb, vsa, vsb, ku[7], kv[7], eps, sig;
+  Buf<T> Bd, gax;
+  Buf<uint16_t> gid;
+  Buf<double> errpart, epart, eout, spart, samp_t, samp_m, elpart;
+  Buf<Table<T>> dtbl;
+  Buf<Ctrl> dctrl;
+  Ctrl* hctrl = nullptr;  // pinned mirror
+  // demag
+  DemagPlan plan{};
+  DemagBufs<T> db{};
+  Buf<cpx<T>> S1, S2, tw;
+  Buf<T> K;
+  bool demag_built = false;
+  // layout of the current allocation
+  bool allocated = false;
+  int a_nsub = 0, a_elastic = 0, a_demag = 0;
+  bool k1_valid = false;
+  double t_host = 0.0, dt_host = 0.0;
+  FieldArgs<T> fa{};
+  ElasticArgs<T> ea{};
+  int nblk = 0, nb_pad = 0, nsamp_blk = 0;
+  int samp_cap = 0;
+
+  ~Grid() override {
+    if (stream) (void)hipStreamSynchronize(stream);
+    free_all();
+    if (hctrl) (void)hipHostFree(hctrl);
+    if (chunk_ev) (void)hipEventDestroy(chunk_ev);
+  }
+
+  void free_all() {
+    for (auto* b : {&y[0], &y[1], &sa, &sb, &u[0], &u[1], &v[0], &v[1], &usa, &usb, &vsa, &vsb,
+                    &eps, &sig, &Bd, &gax, &K})
+      b->release();
+    for (int i = 0; i < 7; ++i) { k[i].release(); ku[i].release(); kv[i].release(); }
+    gid.release();
+    for (auto* b : {&errpart, &epart, &eout, &spart, &samp_t, &samp_m, &elpart}) b->release();
+    dtbl.release();
+    dctrl.release();
+    S1.release(); S2.release(); tw.release();
+    allocated = false;
+    demag_built = false;
+  }
+
+  long long bytes() const override {
+    long long b = 0;
+    auto add = [&](size_t n, size_t sz) { b += (long long)(n * sz); };
+    add(y[0].n * 4 + 7 * k[0].n, sizeof(T));
+    add((u[0].n * 4 + usa.n * 4 + 14 * ku[0].n + eps.n + sig.n), sizeof(T));
+    add(Bd.n + K.n, sizeof(T));
+    add(S1.n + S2.n + tw.n, sizeof(cpx<T>));
+    return b;
+  }
+
+  int alloc_layout() {
+    free_all();
+    const int ns = p.nsub;
+    const size_t nm = (size_t)ns * 3 * N;
+    int rc = 0;
+    rc |= y[0].alloc(nm); rc |= y[1].alloc(nm); rc |= sa.alloc(nm); rc |= sb.alloc(nm);
+    for (int i = 0; i < 7; ++i) rc |= k[i].alloc(nm);
+    if (p.elastic) {
+      const size_t n3 = 3 * (size_t)N;
+      rc |= u[0].alloc(n3); rc |= u[1].alloc(n3); rc |= v[0].alloc(n3); rc |= v[1].alloc(n3);
+      rc |= usa.alloc(n3); rc |= usb.alloc(n3); rc |= vsa.alloc(n3); rc |= vsb.alloc(n3);
+      for (int i = 0; i < 7; ++i) { rc |= ku[i].alloc(n3); rc |= kv[i].alloc(n3); }
+      rc |= eps.alloc(6 * (size_t)N);
+      rc |= sig.alloc(6 * (size_t)N);
+    }
+    const int nbx = (nx + kTileX - 1) / kTileX, nby = (ny + kTileY - 1) / kTileY;
+    nblk = nbx * nby;
+    nb_pad = round_up(nblk, 8);
+    rc |= errpart.alloc(nb_pad);
+    rc |= epart.alloc((size_t)nb_pad * kNE);
+    rc |= eout.alloc(kNE);
+    nsamp_blk = (int)std::min<long>(256, (N + 255) / 256);
+    rc |= spart.alloc((size_t)nsamp_blk * 6);
+    rc |= elpart.alloc((N + 255) / 256);
+    rc |= dtbl.alloc(1);
+    rc |= dctrl.alloc(1);
+    if (p.demag) {
+      if (demag_plan(nx, ny, nz, (int)sizeof(T), &plan) != 0) {
+        set_error("demag pad exceeds 4096 along an axis");
+        return MMP_E_ARG;
+      }
+      rc |= Bd.alloc(3 * (size_t)N);
+      rc |= S1.alloc(plan.s1_elems);
+      rc |= S2.alloc(plan.s2_elems);
+      rc |= K.alloc(plan.k_elems);
+      rc |= tw.alloc((size_t)plan.Px + plan.Py + plan.Pz);
+      db.S1 = S1.p; db.S2 = S2.p; db.K = K.p; db.Bd = Bd.p;
+      db.twx = tw.p; db.twy = tw.p + plan.Px; db.twz = tw.p + plan.Px + plan.Py;
+    }
+    if (rc) {
+      set_error("device allocation failed");
+      free_all();
+      return MMP_E_NOMEM;
+    }
+    if (!hctrl) MMP_HIP_TRY(hipHostMalloc((void**)&hctrl, sizeof(Ctrl), 0));
+    // pointer table
+    Table<T> t{};
+    t.yn = y[0].p; t.ynew = y[1].p; t.sa = sa.p; t.sb = sb.p;
+    for (int i = 0; i < 7; ++i) t.k[i] = k[i].p;
+    if (p.elastic) {
+      t.un = u[0].p; t.unew = u[1].p; t.vn = v[0].p; t.vnew = v[1].p;
+      t.usa = usa.p; t.usb = usb.p; t.vsa = vsa.p; t.vsb = vsb.p;
+      for (int i = 0; i < 7; ++i) { t.ku[i] = ku[i].p; t.kv[i] = kv[i].p; }
+    }
+    MMP_HIP_TRY(hipMemcpyAsync(dtbl.p, &t, sizeof(t), hipMemcpyHostToDevice, stream));
+    MMP_HIP_TRY(hipMemsetAsync(y[0].p, 0, nm * sizeof(T), stream));
+    if (p.elastic) {
+      MMP_HIP_TRY(hipMemsetAsync(u[0].p, 0, 3 * N * sizeof(T), stream));
+      MMP_HIP_TRY(hipMemsetAsync(v[0].p, 0, 3 * N * sizeof(T), stream));
+    }
+    Ctrl c{};
+    MMP_HIP_TRY(hipMemcpyAsync(dctrl.p, &c, sizeof(c), hipMemcpyHostToDevice, stream));
+    MMP_HIP_TRY(hipStreamSynchronize(stream));
+    allocated = true;
+    a_nsub = p.nsub; a_elastic = p.elastic; a_demag = p.demag;
+    state_set = false;
+    return 0;
+  }
+
+  static void fill_sub(SubC<T>& s, const mmp_sublattice& b, const mmp_params& p) {
+    const double Ms = b.Ms;
+    const bool nz = Ms != 0.0;
+    s.ms = (T)Ms;
+    s.nonzero = nz ? 1 : 0;
+    s.cex = (T)(nz ? 2.0 * b.A11 / Ms : 0.0);
+    s.cnn = (T)(nz ? p.A12 / Ms : 0.0);
+    s.ccell = (T)(nz ? 4.0 * p.A0 / (Ms * p.latcon * p.latcon) : 0.0);
+    s.cdmi = (T)(nz ? 2.0 * b.Dint / Ms : 0.0);
+    s.kdmi = (T)((b.A11 != 0.0 && b.Dint != 0.0) ? -b.Dint / (2.0 * b.A11) : 0.0);
+    s.cku1 = (T)(nz ? 2.0 * b.Ku1 / Ms : 0.0);
+    s.cku2 = (T)(nz ? 4.0 * b.Ku2 / Ms : 0.0);
+    for (int c = 0; c < 3; ++c) s.u[c] = (T)b.anis_u[c];
+    s.ckc = (T)(nz ? 2.0 * b.Kc1 / Ms : 0.0);
+    const double* c1 = b.cub_c1;
+    const double* c2 = b.cub_c2;
+    const double c3[3] = {c1[1] * c2[2] - c1[2] * c2[1], c1[2] * c2[0] - c1[0] * c2[2],
+                          c1[0] * c2[1] - c1[1] * c2[0]};
+    for (int c = 0; c < 3; ++c) { s.c1[c] = (T)c1[c]; s.c2[c] = (T)c2[c]; s.c3[c] = (T)c3[c]; }
+    s.cmel1 = (T)(nz ? 2.0 * b.B1 / Ms : 0.0);
+    s.cmel2 = (T)(nz ? 2.0 * b.B2 / Ms : 0.0);
+    const double al = b.alpha;
+    s.gl = (T)(p.gamma / (1.0 + al * al));
+    s.alpha = (T)al;
+    double zu[3] = {0, 0, 0};
+    if (nz)
+      for (int c = 0; c < 3; ++c) zu[c] = b.zl_P * kMuB * p.j[c] / (kQe * Ms);
+    s.has_zl = (zu[0] != 0.0 || zu[1] != 0.0 || zu[2] != 0.0) ? 1 : 0;
+    for (int c = 0; c < 3; ++c) s.zu[c] = (T)zu[c];
+    s.zla = (T)((1.0 + b.zl_xi * al) / (1.0 + al * al));
+    s.zlb = (T)((b.zl_xi - al) / (1.0 + al * al));
+    s.Ms_d = Ms; s.Ku1_d = b.Ku1; s.Ku2_d = b.Ku2; s.Kc1_d = b.Kc1; s.B1_d = b.B1; s.B2_d = b.B2;
+  }
+
+  int apply_params() override {
+    if (p.nsub == 2)
+      for (int s = 0; s < 2; ++s)
+        if (p.sub[s].Dint != 0.0) {
+          set_error("interfacial DMI is implemented for one sublattice");
+          return MMP_E_ARG;
+        }
+    if (!allocated || a_nsub != p.nsub || a_elastic != (p.elastic != 0) ||
+        a_demag != (p.demag != 0)) {
+      p.elastic = p.elastic != 0;
+      p.demag = p.demag != 0;
+      const int rc = alloc_layout();
+      if (rc) return rc;
+    }
+    // grains
+    gid.release();
+    gax.release();
+    if (p.ngrains > 0) {
+      if (gid.alloc(N) || gax.alloc(3 * (size_t)p.ngrains)) {
+        set_error("device allocation failed");
+        return MMP_E_NOMEM;
+      }
+      MMP_HIP_TRY(hipMemcpy(gid.p, grain.data(), N * sizeof(uint16_t), hipMemcpyHostToDevice));
+      std::vector<T> ax(grain_axes.begin(), grain_axes.end());
+      MMP_HIP_TRY(hipMemcpy(gax.p, ax.data(), ax.size() * sizeof(T), hipMemcpyHostToDevice));
+    }
+    // demag kernel
+    if (p.demag && !demag_built) {
+      double* n6 = nullptr;
+      MMP_HIP_TRY(hipMalloc(&n6, 6 * (size_t)N * sizeof(double)));
+      build_twiddles<T>(db.twx, plan.Px, stream);
+      build_twiddles<T>(db.twy, plan.Py, stream);
+      build_twiddles<T>(db.twz, plan.Pz, stream);
+      const int rc = demag_kernel_build<T>(plan, d[0], d[1], d[2], n6, db.K, stream);
+      (void)hipFree(n6);
+      if (rc) {
+        set_error("demag kernel build failed");
+        return MMP_E_HIP;
+      }
+      demag_built = true;
+    }
+    // field kernel arguments
+    FieldArgs<T> a{};
+    a.nx = nx; a.ny = ny; a.nz = nz; a.nsub = p.nsub; a.N = N;
+    a.dx = (T)d[0]; a.dy = (T)d[1]; a.dz = (T)d[2];
+    a.idx2 = (T)(1.0 / (d[0] * d[0])); a.idy2 = (T)(1.0 / (d[1] * d[1]));
+    a.idz2 = (T)(1.0 / (d[2] * d[2]));
+    a.i2dx = (T)(0.5 / d[0]); a.i2dy = (T)(0.5 / d[1]); a.i2dz = (T)(0.5 / d[2]);
+    for (int s = 0; s < p.nsub; ++s) fill_sub(a.sc[s], p.sub[s], p);
+    for (int c = 0; c < 3; ++c) a.bext[c] = (T)p.B_ext[c];
+    a.dmi_layer = p.dmi_layer;
+    a.has_demag = p.demag ? 1 : 0;
+    a.has_dmi = (p.nsub == 1 && p.sub[0].Dint != 0.0) ? 1 : 0;
+    a.has_anis_u = 0;
+    a.has_anis_c = 0;
+    a.has_mel = 0;
+    for (int s = 0; s < p.nsub; ++s) {
+      if (p.sub[s].Ku1 != 0.0 || p.sub[s].Ku2 != 0.0) a.has_anis_u = 1;
+      if (p.sub[s].Kc1 != 0.0) a.has_anis_c = 1;
+      if (p.elastic && (p.sub[s].B1 != 0.0 || p.sub[s].B2 != 0.0)) a.has_mel = 1;
+    }
+    a.grain = p.ngrains > 0 ? gid.p : nullptr;
+    a.gaxes = p.ngrains > 0 ? gax.p : nullptr;
+    a.Bd = Bd.p;
+    a.eps = eps.p;
+    a.tbl = dtbl.p;
+    a.ctrl = dctrl.p;
+    a.errpart = errpart.p;
+    a.V = d[0] * d[1] * d[2];
+    a.nbx = (nx + kTileX - 1) / kTileX;
+    a.nby = (ny + kTileY - 1) / kTileY;
+    a.nb_pad = nb_pad;
+    fa = a;
+    // elastic arguments
+    ElasticArgs<T> e{};
+    e.nx = nx; e.ny = ny; e.nz = nz; e.nsub = p.nsub; e.N = N;
+    e.dx = (T)d[0]; e.dy = (T)d[1]; e.dz = (T)d[2];
+    e.C11 = (T)p.C11; e.C12 = (T)p.C12; e.C44 = (T)p.C44; e.eta = (T)p.eta;
+    e.inv_rho = (T)(p.rho != 0.0 ? 1.0 / p.rho : 0.0);
+    e.trac_amp = p.trac_amp;
+    e.trac_omega = 2.0 * kPi * p.trac_freq;
+    for (int s = 0; s < p.nsub; ++s) {
+      e.B1[s] = (T)p.sub[s].B1;
+      e.B2[s] = (T)p.sub[s].B2;
+      e.mel[s] = (p.sub[s].Ms != 0.0 && (p.sub[s].B1 != 0.0 || p.sub[s].B2 != 0.0)) ? 1 : 0;
+    }
+    e.tbl = dtbl.p; e.ctrl = dctrl.p; e.eps = eps.p; e.sig = sig.p; e.epart = elpart.p;
+    e.V = a.V; e.rho = p.rho;
+    ea = e;
+    k1_valid = false;
+    params_set = true;
+    return 0;
+  }
+
+  int set_state(const double* m, const double* uu, const double* vv, double t) override {
+    const size_t nm = (size_t)p.nsub * 3 * N;
+    // the pointer table may have been swapped by earlier steps: reset it
+    Table<T> tb{};
+    MMP_HIP_TRY(hipMemcpy(&tb, dtbl.p, sizeof(tb), hipMemcpyDeviceToHost));
+    std::vector<T> tmp(nm);
+    for (size_t i = 0; i < nm; ++i) tmp[i] = (T)m[i];
+    MMP_HIP_TRY(hipMemcpy(tb.yn, tmp.data(), nm * sizeof(T), hipMemcpyHostToDevice));
+    if (p.elastic) {
+      std::vector<T> t3(3 * (size_t)N);
+      for (size_t i = 0; i < t3.size(); ++i) t3[i] = uu ? (T)uu[i] : T(0);
+      MMP_HIP_TRY(hipMemcpy(tb.un, t3.data(), t3.size() * sizeof(T), hipMemcpyHostToDevice));
+      for (size_t i = 0; i < t3.size(); ++i) t3[i] = vv ? (T)vv[i] : T(0);
+      MMP_HIP_TRY(hipMemcpy(tb.vn, t3.data(), t3.size() * sizeof(T), hipMemcpyHostToDevice));
+    }
+    Ctrl c{};
+    c.t = t;
+    c.dt = p.dt0 > 0 ? p.dt0 : 1e-14;
+    MMP_HIP_TRY(hipMemcpy(dctrl.p, &c, sizeof(c), hipMemcpyHostToDevice));
+    t_host = t;
+    dt_host = c.dt;
+    k1_valid = false;
+    state_set = true;
+    return 0;
+  }
+
+  int get_state(double* m, double* uu, double* vv, double* t, double* dt) override {
+    MMP_HIP_TRY(hipStreamSynchronize(stream));
+    Table<T> tb{};
+    MMP_HIP_TRY(hipMemcpy(&tb, dtbl.p, sizeof(tb), hipMemcpyDeviceToHost));
+    Ctrl c{};
+    MMP_HIP_TRY(hipMemcpy(&c, dctrl.p, sizeof(c), hipMemcpyDeviceToHost));
+    if (m) {
+      const size_t nm = (size_t)p.nsub * 3 * N;
+      std::vector<T> tmp(nm);
+      MMP_HIP_TRY(hipMemcpy(tmp.data(), tb.yn, nm * sizeof(T), hipMemcpyDeviceToHost));
+      for (size_t i = 0; i < nm; ++i) m[i] = (double)tmp[i];
+    }
+    if (p.elastic && (uu || vv)) {
+      std::vector<T> t3(3 * (size_t)N);
+      if (uu) {
+        MMP_HIP_TRY(hipMemcpy(t3.data(), tb.un, t3.size() * sizeof(T), hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < t3.size(); ++i) uu[i] = (double)t3[i];
+      }
+      if (vv) {
+        MMP_HIP_TRY(hipMemcpy(t3.data(), tb.vn, t3.size() * sizeof(T), hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < t3.size(); ++i) vv[i] = (double)t3[i];
+      }
+    } else if (!p.elastic) {
+      if (uu) std::fill(uu, uu + 3 * N, 0.0);
+      if (vv) std::fill(vv, vv + 3 * N, 0.0);
+    }
+    if (t) *t = c.t;
+    if (dt) *dt = c.dt;
+    return 0;
+  }
+
+  // ---------------------------------------------------------- stages --
+  void stage(int s, bool fuse2) {
+    if (p.elastic) {
+      ElasticArgs<T> e = ea;
+      e.stage = s;
+      launch_strain(e, stream, &prof);
+    }
+    if (p.demag)
+      demag_field<T>(plan, db, dtbl.p, s, dctrl.p, (T)p.sub[0].Ms,
+                     (T)(p.nsub == 2 ? p.sub[1].Ms : 0.0), p.nsub, stream, &prof);
+    FieldArgs<T> a = fa;
+    a.stage = s;
+    a.fuse2 = fuse2 ? 1 : 0;
+    launch_field<T>(a, false, stream, &prof);
+    if (p.elastic) {
+      ElasticArgs<T> e = ea;
+      e.stage = s;
+      e.fuse2 = fuse2 ? 1 : 0;
+      launch_elastic_stage<T>(e, false, stream, &prof);
+    }
+  }
+
+  void combine2() {
+    launch_combine2<T>(dtbl.p, dctrl.p, N, p.nsub, stream, &prof);
+    if (p.elastic) launch_elastic_combine2<T>(dtbl.p, dctrl.p, N, stream, &prof);
+  }
+
+  // one attempt: stages 2..7 + control (+ sampling, + next stage-2 input)
+  void attempt(bool fixed_mode, bool sampling) {
+    for (int s = 2; s <= 7; ++s) stage(s, fixed_mode && s == 7);
+    launch_control<T>(dctrl.p, dtbl.p, errpart.p, nblk, p.elastic ? 1 : 0, stream, &prof);
+    if (sampling)
+      launch_sample<T>(dctrl.p, dtbl.p, p.nsub, N, spart.p, nsamp_blk, samp_t.p, samp_m.p,
+                       samp_cap, stream, &prof);
+    if (!fixed_mode) combine2();
+  }
+
+  int ensure_ready() {
+    if (!params_set) { set_error("mmp_set_params has not been called"); return MMP_E_STATE; }
+    if (!state_set) { set_error("mmp_set_state has not been called"); return MMP_E_STATE; }
+    return 0;
+  }
+
+  // set up the controller for a run segment; returns after the first
+  // stage-2 input is prepared
+  int begin_segment(const Ctrl& init) {
+    Ctrl c{};
+    MMP_HIP_TRY(hipMemcpyAsync(hctrl, dctrl.p, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
+    MMP_HIP_TRY(hipStreamSynchronize(stream));
+    c = *hctrl;
+    c.t_end = init.t_end; c.t_next = init.t_next; c.sample_every = init.sample_every;
+    c.t0 = c.t; c.tol = init.tol; c.dt_min = init.dt_min; c.fixed = init.fixed;
+    c.max_attempts = init.max_attempts;
+    c.done = 0; c.status = 0; c.sample_k = init.fixed ? 0 : 1; c.nsamples = 0;
+    c.sample_pending = 0; c.nonfinite = 0;
+    if (init.fixed) {
+      c.h = init.h;
+      c.land = 0;
+    } else {
+      if (c.dt <= 0) c.dt = p.dt0 > 0 ? p.dt0 : 1e-14;
+      const double target = std::min(c.t_next, c.t_end);
+      const double rem = target - c.t;
+      c.land = c.dt >= rem ? 1 : 0;
+      c.h = c.land ? rem : c.dt;
+    }
+    *hctrl = c;
+    MMP_HIP_TRY(hipMemcpyAsync(dctrl.p, hctrl, sizeof(Ctrl), hipMemcpyHostToDevice, stream));
+    if (!k1_valid) {
+      stage(1, false);
+      k1_valid = true;
+    } else {
+      combine2();
+    }
+    return 0;
+  }
+
+  int read_ctrl(Ctrl* c) {
+    MMP_HIP_TRY(hipMemcpyAsync(hctrl, dctrl.p, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
+    MMP_HIP_TRY(hipStreamSynchronize(stream));
+    *c = *hctrl;
+    return 0;
+  }
+
+  int run_fixed(double dt, long long n, mmp_step_info* info) override {
+    int rc = ensure_ready();
+    if (rc) return rc;
+    if (!(dt > 0.0) || n < 0) { set_error("dt must be > 0 and nsteps >= 0"); return MMP_E_ARG; }
+    if (n == 0) return 0;
+    Ctrl init{};
+    init.fixed = 1; init.h = dt; init.t_end = 1e300; init.t_next = 1e300;
+    init.max_attempts = n; init.tol = 0; init.dt_min = 0;
+    if ((rc = begin_segment(init))) return rc;
+    for (long long i = 0; i < n; ++i) attempt(true, false);
+    MMP_HIP_TRY(hipGetLastError());
+    if (info) {
+      Ctrl c{};
+      if ((rc = read_ctrl(&c))) return rc;
+      info->t = c.t; info->dt = dt; info->err = 0; info->steps = c.steps; info->rejects = c.rejects;
+      if (c.status) { set_error("non-finite state"); return c.status; }
+    }
+    return 0;
+  }
+
+  int step(double dt_fixed, mmp_step_info* info) override {
+    if (dt_fixed > 0.0) return run_fixed(dt_fixed, 1, info);
+    int rc = ensure_ready();
+    if (rc) return rc;
+    // adaptive: attempts until one is accepted
+    Ctrl init{};
+    init.fixed = 0; init.t_end = 1e300; init.t_next = 1e300;
+    init.tol = p.tol > 0 ? p.tol : 1e-5;
+    init.dt_min = p.dt_min > 0 ? p.dt_min : 1e-20;
+    if ((rc = begin_segment(init))) return rc;
+    Ctrl c{};
+    const int64_t s0 = hctrl->steps;
+    for (int it = 0; it < 1000; ++it) {
+      attempt(false, false);
+      if ((rc = read_ctrl(&c))) return rc;
+      if (c.status) { set_error(c.status == MMP_E_DT_UNDERFLOW ? "time step underflow" : "non-finite state"); return c.status; }
+      if (c.steps > s0) break;
+    }
+    if (info) {
+      info->t = c.t; info->dt = c.dt; info->err = c.err; info->steps = c.steps; info->rejects = c.rejects;
+    }
+    return 0;
+  }
+
+  int run(double t_end, const mmp_run_opts* o, mmp_run_info* info) override {
+    int rc = ensure_ready();
+    if (rc) return rc;
+    Ctrl cur{};
+    if ((rc = read_ctrl(&cur))) return rc;
+    if (!(t_end > cur.t)) {
+      if (info) { std::memset(info, 0, sizeof(*info)); info->t = cur.t; info->dt = cur.dt; }
+      return 0;
+    }
+    const double every = o ? o->sample_every : 0.0;
+    const int cap = o ? o->max_samples : 0;
+    if (every > 0.0 && cap > samp_cap) {
+      samp_t.release(); samp_m.release();
+      if (samp_t.alloc(cap) || samp_m.alloc((size_t)cap * 6)) {
+        set_error("device allocation failed");
+        return MMP_E_NOMEM;
+      }
+      samp_cap = cap;
+    }
+    Ctrl init{};
+    init.fixed = 0;
+    init.t_end = t_end;
+    init.sample_every = every > 0.0 ? every : 0.0;
+    init.t_next = every > 0.0 ? cur.t + every : t_end;
+    init.tol = p.tol > 0 ? p.tol : 1e-5;
+    init.dt_min = p.dt_min > 0 ? p.dt_min : 1e-20;
+    init.max_attempts = o ? o->max_steps : 0;
+    if ((rc = begin_segment(init))) return rc;
+    const bool sampling = every > 0.0;
+    // enqueue attempts in chunks; the device ignores the ones after done
+    const int chunk = N > 4096 ? 16 : 64;
+    Ctrl c{};
+    long long last = -1;
+    while (true) {
+      for (int i = 0; i < chunk; ++i) attempt(false, sampling);
+      MMP_HIP_TRY(hipGetLastError());
+      if ((rc = read_ctrl(&c))) return rc;
+      if (c.done || c.status) break;
+      const long long made = c.steps + c.rejects;
+      if (made == last) {
+        set_error("step controller made no progress");
+        return MMP_E_STATE;
+      }
+      last = made;
+    }
+    if (info) {
+      info->t = c.t; info->dt = c.dt; info->steps = c.steps; info->rejects = c.rejects;
+      info->nsamples = c.nsamples; info->status = c.status;
+    }
+    if (sampling && o && c.nsamples > 0) {
+      const int ns = std::min(c.nsamples, samp_cap);
+      std::vector<double> tt(ns), mm((size_t)ns * 6);
+      MMP_HIP_TRY(hipMemcpy(tt.data(), samp_t.p, ns * sizeof(double), hipMemcpyDeviceToHost));
+      MMP_HIP_TRY(hipMemcpy(mm.data(), samp_m.p, ns * 6 * sizeof(double), hipMemcpyDeviceToHost));
+      for (int i = 0; i < ns; ++i) {
+        if (o->sample_t) o->sample_t[i] = tt[i];
+        if (o->sample_m)
+          for (int q = 0; q < 3 * p.nsub; ++q) o->sample_m[i * 3 * p.nsub + q] = mm[i * 3 * p.nsub + q];
+      }
+    }
+    if (c.status) {
+      set_error(c.status == MMP_E_DT_UNDERFLOW ? "time step underflow" : "non-finite state");
+      return c.status;
+    }
+    return 0;
+  }
+
+  int eval(uint32_t mask, double* b, double* e) override {
+    int rc = ensure_ready();
+    if (rc) return rc;
+    const size_t nm = (size_t)p.nsub * 3 * N;
+    Buf<T> bout;
+    if (b && bout.alloc(nm)) { set_error("device allocation failed"); return MMP_E_NOMEM; }
+    if (p.elastic) {
+      ElasticArgs<T> ee = ea;
+      ee.stage = 1;
+      ee.ctrl = nullptr;
+      launch_strain(ee, stream, &prof);
+    }
+    if (p.demag)
+      demag_field<T>(plan, db, dtbl.p, 1, nullptr, (T)p.sub[0].Ms,
+                     (T)(p.nsub == 2 ? p.sub[1].Ms : 0.0), p.nsub, stream, &prof);
+    FieldArgs<T> a = fa;
+    a.ctrl = nullptr;
+    a.stage = 1;
+    a.mask = mask & MMP_T_ALL;
+    a.add_zl = (mask & MMP_T_ZL) ? 1 : 0;
+    a.out_torque = (mask & MMP_OUT_TORQUE) ? 1 : 0;
+    a.bout = b ? bout.p : nullptr;
+    a.epart = epart.p;
+    launch_field<T>(a, true, stream, &prof);
+    launch_energy_final(epart.p, nblk, eout.p, stream);
+    double el = 0.0;
+    if (p.elastic) {
+      ElasticArgs<T> ee = ea;
+      ee.stage = 1;
+      ee.ctrl = nullptr;
+      launch_elastic_stage<T>(ee, true, stream, &prof);
+    }
+    MMP_HIP_TRY(hipGetLastError());
+    MMP_HIP_TRY(hipStreamSynchronize(stream));
+    if (b) {
+      std::vector<T> tmp(nm);
+      MMP_HIP_TRY(hipMemcpy(tmp.data(), bout.p, nm * sizeof(T), hipMemcpyDeviceToHost));
+      for (size_t i = 0; i < nm; ++i) b[i] = (double)tmp[i];
+      bout.release();
+    }
+    if (e) {
+      MMP_HIP_TRY(hipMemcpy(e, eout.p, kNE * sizeof(double), hipMemcpyDeviceToHost));
+      if (p.elastic) {
+        const size_t nb = (N + 255) / 256;
+        std::vector<double> part(nb);
+        MMP_HIP_TRY(hipMemcpy(part.data(), elpart.p, nb * sizeof(double), hipMemcpyDeviceToHost));
+        for (double v : part) el += v;
+      }
+      e[kNE - 1] = el;
+    }
+    return 0;
+  }
+
+  hipEvent_t chunk_ev = nullptr;
+
+  int run_begin(double t_end) override {
+    int rc = ensure_ready();
+    if (rc) return rc;
+    Ctrl cur{};
+    if ((rc = read_ctrl(&cur))) return rc;
+    Ctrl init{};
+    init.fixed = 0;
+    init.t_end = t_end;
+    init.t_next = t_end;
+    init.tol = p.tol > 0 ? p.tol : 1e-5;
+    init.dt_min = p.dt_min > 0 ? p.dt_min : 1e-20;
+    if ((rc = begin_segment(init))) return rc;
+    if (!chunk_ev) MMP_HIP_TRY(hipEventCreateWithFlags(&chunk_ev, hipEventDisableTiming));
+    return 0;
+  }
+
+  int run_chunk(int attempts) override {
+    for (int i = 0; i < attempts; ++i) attempt(false, false);
+    MMP_HIP_TRY(hipMemcpyAsync(hctrl, dctrl.p, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
+    MMP_HIP_TRY(hipEventRecord(chunk_ev, stream));
+    return 0;
+  }
+
+  int run_poll(bool* finished, int* status, long long* steps, long long* rejects) override {
+    const hipError_t q = hipEventQuery(chunk_ev);
+    if (q == hipErrorNotReady) { *finished = false; return MMP_PENDING; }
+    if (q != hipSuccess) { set_error(hipGetErrorString(q)); return MMP_E_HIP; }
+    const Ctrl c = *hctrl;
+    *finished = (c.done || c.status) != 0;
+    *status = c.status;
+    *steps = c.steps;
+    *rejects = c.rejects;
+    return 0;
+  }
+
+  int tensor(double* n6) override {
+    double* d6 = nullptr;
+    MMP_HIP_TRY(hipMalloc(&d6, 6 * (size_t)N * sizeof(double)));
+    const int rc = demag_tensor_only(nx, ny, nz, d[0], d[1], d[2], d6, stream);
+    hipError_t e = hipStreamSynchronize(stream);
+    if (rc == 0 && e == hipSuccess)
+      e = hipMemcpy(n6, d6, 6 * (size_t)N * sizeof(double), hipMemcpyDeviceToHost);
+    (void)hipFree(d6);
+    if (rc || e != hipSuccess) { set_error("tensor build failed"); return MMP_E_HIP; }
+    return 0;
+  }
+};
+
+GridBase* make_grid(int precision) {
+  if (precision == MMP_FP64) return new Grid<double>();
+  return new Grid<float>();
+}
+
+}  // namespace mmp

@@ -1,0 +1,276 @@
+// Request server: continuous batching of relaxation solves on one GPU.
+//
+// Requests arrive on any thread (mmp_submit) and wait in a FIFO queue.  A
+// worker thread admits the queue head whenever a slot is free and its
+// device footprint fits the remaining HBM budget, builds its grid (own
+// stream, own demag kernel), and then round-robins over the active
+// requests: each gets a chunk of Dormand-Prince attempts enqueued on its
+// stream, so the kernels of different requests overlap on the device while
+// every request keeps its own device-side step control.  A request that
+// finishes is reduced (average m, total energy), its memory returned, and
+// the next queued request is admitted at once.  Results are read with
+// mmp_poll.  Each request runs exactly the kernels it would run alone, so
+// its result does not depend on what else is in flight.
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "grid.h"
+
+using namespace mmp;
+
+namespace {
+
+struct Req {
+  uint64_t ticket;
+  mmp_request r;
+  std::vector<double> m0;
+  std::vector<uint16_t> grain;
+  std::vector<double> gaxes;
+  double t_submit;
+  double t_admit = 0;
+  int64_t footprint = 0;
+  mmp_grid g = nullptr;
+  int chunk = 8;
+};
+
+int64_t estimate_bytes(const mmp_request& r, int precision) {
+  const int64_t N = (int64_t)r.nx * r.ny * r.nz;
+  const int64_t rb = precision == MMP_FP64 ? 8 : 4;
+  const int ns = r.params.nsub;
+  int64_t b = (4 + 7) * (int64_t)ns * 3 * N * rb;  // state, stages, k
+  if (r.params.demag) {
+    DemagPlan p;
+    if (demag_plan(r.nx, r.ny, r.nz, (int)rb, &p) == 0)
+      b += (int64_t)(p.s1_elems + p.s2_elems) * 2 * rb + (int64_t)p.k_elems * rb + 3 * N * rb +
+           6 * N * 8 /* FP64 tensor during the build */ +
+           (int64_t)6 * r.nz * (r.ny + p.Hy) * p.Hx * 8;
+  }
+  return b + (1 << 20);
+}
+
+}  // namespace
+
+struct mmp_server_s {
+  mmp_server_opts o{};
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<Req*> queue;
+  std::vector<Req*> active;
+  std::map<uint64_t, mmp_result> done;
+  std::map<uint64_t, int> known;
+  std::atomic<bool> stop{false};
+  uint64_t next_ticket = 1;
+  int64_t used = 0;
+  std::thread worker;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+
+  void finish(Req* q, int status) {
+    mmp_result res{};
+    res.status = status;
+    res.nsub = q->r.params.nsub;
+    res.t_submit = q->t_submit;
+    res.t_admit = q->t_admit;
+    if (q->g && status == MMP_OK) {
+      mmp_step_info info{};
+      (void)info;
+      const int64_t N = (int64_t)q->r.nx * q->r.ny * q->r.nz;
+      std::vector<double> m((size_t)res.nsub * 3 * N);
+      double t = 0, dt = 0;
+      int rc = mmp_get_state(q->g, m.data(), nullptr, nullptr, &t, &dt);
+      double e[MMP_NENERGY] = {};
+      if (rc == MMP_OK) rc = mmp_eval_heff(q->g, 0, nullptr, e);
+      if (rc == MMP_OK) {
+        for (int s = 0; s < res.nsub; ++s)
+          for (int c = 0; c < 3; ++c) {
+            double acc = 0;
+            const double* p = m.data() + ((size_t)s * 3 + c) * N;
+            for (int64_t i = 0; i < N; ++i) acc += p[i];
+            res.m_avg[s][c] = acc / (double)N;
+          }
+        double et = 0;
+        for (int k = 0; k < MMP_NENERGY; ++k) et += e[k];
+        res.energy = et;
+      } else {
+        res.status = rc;
+      }
+      long long steps = 0, rejects = 0;
+      bool fin = false;
+      int st = 0;
+      if (q->g->impl) q->g->impl->run_poll(&fin, &st, &steps, &rejects);
+      res.steps = steps;
+      res.rejects = rejects;
+    }
+    if (q->g) mmp_grid_destroy(q->g);
+    q->g = nullptr;
+    res.t_done = now();
+    std::lock_guard<std::mutex> lk(mu);
+    used -= q->footprint;
+    done[q->ticket] = res;
+    delete q;
+  }
+
+  int start_request(Req* q) {
+    mmp_grid g = nullptr;
+    int rc = mmp_grid_create(q->r.nx, q->r.ny, q->r.nz, q->r.cellsize, &g);
+    if (rc) return rc;
+    q->g = g;
+    mmp_params p = q->r.params;
+    p.struct_size = sizeof(mmp_params);
+    p.precision = o.precision;
+    p.grain = q->grain.empty() ? nullptr : q->grain.data();
+    p.grain_axes = q->gaxes.empty() ? nullptr : q->gaxes.data();
+    if ((rc = mmp_set_params(g, &p))) return rc;
+    if ((rc = mmp_set_state(g, q->m0.data(), nullptr, nullptr, 0.0))) return rc;
+    if ((rc = g->impl->run_begin(q->r.t_relax))) return rc;
+    const int64_t N = (int64_t)q->r.nx * q->r.ny * q->r.nz;
+    q->chunk = N >= 65536 ? 4 : (N >= 4096 ? 16 : 32);
+    return g->impl->run_chunk(q->chunk);
+  }
+
+  void loop() {
+    while (!stop.load()) {
+      // admission
+      while (true) {
+        Req* q = nullptr;
+        {
+          std::lock_guard<std::mutex> lk(mu);
+          if (queue.empty() || (int)active.size() >= o.max_active) break;
+          Req* h = queue.front();
+          if (used + h->footprint > o.hbm_budget && !active.empty()) break;
+          queue.pop_front();
+          used += h->footprint;
+          q = h;
+        }
+        q->t_admit = now();
+        const int rc = start_request(q);
+        if (rc) finish(q, rc);
+        else active.push_back(q);
+      }
+      // progress
+      bool any = false;
+      for (size_t i = 0; i < active.size();) {
+        Req* q = active[i];
+        bool fin = false;
+        int st = 0;
+        long long steps = 0, rejects = 0;
+        const int rc = q->g->impl->run_poll(&fin, &st, &steps, &rejects);
+        if (rc == MMP_PENDING) { ++i; continue; }
+        any = true;
+        if (rc != 0 || fin) {
+          active.erase(active.begin() + i);
+          finish(q, rc != 0 ? rc : st);
+          continue;
+        }
+        (void)q->g->impl->run_chunk(q->chunk);
+        ++i;
+      }
+      if (!any) {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait_for(lk, std::chrono::microseconds(200));
+      }
+    }
+    for (Req* q : active) finish(q, MMP_E_STATE);
+    active.clear();
+  }
+};
+
+extern "C" {
+
+mmp_status mmp_server_create(const mmp_server_opts* o, mmp_server* out) {
+  try {
+    if (!o || !out || o->struct_size != sizeof(mmp_server_opts)) {
+      set_error("bad server options");
+      return MMP_E_ARG;
+    }
+    if (o->hbm_budget <= 0 || o->max_active < 1 ||
+        (o->precision != MMP_FP32 && o->precision != MMP_FP64)) {
+      set_error("bad server options");
+      return MMP_E_ARG;
+    }
+    mmp_server s = new mmp_server_s();
+    s->o = *o;
+    s->worker = std::thread([s] { s->loop(); });
+    *out = s;
+    return MMP_OK;
+  } catch (...) {
+    set_error("server creation failed");
+    return MMP_E_NOMEM;
+  }
+}
+
+mmp_status mmp_submit(mmp_server s, const mmp_request* r, uint64_t* ticket) {
+  try {
+    if (!s || !r || !ticket || r->struct_size != sizeof(mmp_request)) {
+      set_error("bad request");
+      return MMP_E_ARG;
+    }
+    if (r->nx < 1 || r->ny < 1 || r->nz < 1 || !r->m0 || !(r->t_relax > 0) ||
+        (r->params.nsub != 1 && r->params.nsub != 2)) {
+      set_error("bad request");
+      return MMP_E_ARG;
+    }
+    const int64_t N = (int64_t)r->nx * r->ny * r->nz;
+    Req* q = new Req();
+    q->r = *r;
+    q->m0.assign(r->m0, r->m0 + (size_t)r->params.nsub * 3 * N);
+    q->r.m0 = nullptr;
+    if (r->params.ngrains > 0 && r->params.grain && r->params.grain_axes) {
+      q->grain.assign(r->params.grain, r->params.grain + N);
+      q->gaxes.assign(r->params.grain_axes, r->params.grain_axes + 3 * r->params.ngrains);
+    }
+    q->footprint = estimate_bytes(*r, s->o.precision);
+    if (q->footprint > s->o.hbm_budget) {
+      delete q;
+      set_error("request exceeds the HBM budget");
+      return MMP_E_TOO_LARGE;
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    q->ticket = s->next_ticket++;
+    q->t_submit = s->now();
+    s->known[q->ticket] = 1;
+    s->queue.push_back(q);
+    *ticket = q->ticket;
+    s->cv.notify_all();
+    return MMP_OK;
+  } catch (...) {
+    set_error("submit failed");
+    return MMP_E_NOMEM;
+  }
+}
+
+mmp_status mmp_poll(mmp_server s, uint64_t ticket, mmp_result* out) {
+  if (!s || !out) { set_error("bad argument"); return MMP_E_ARG; }
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->done.find(ticket);
+  if (it != s->done.end()) {
+    *out = it->second;
+    return MMP_OK;
+  }
+  if (s->known.count(ticket)) return MMP_PENDING;
+  set_error("unknown ticket");
+  return MMP_E_TICKET;
+}
+
+mmp_status mmp_server_destroy(mmp_server s) {
+  if (!s) return MMP_OK;
+  s->stop.store(true);
+  s->cv.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  for (Req* q : s->queue) delete q;
+  delete s;
+  return MMP_OK;
+}
+
+double mmp_server_clock(mmp_server s) { return s ? s->now() : 0.0; }
+
+}  // extern "C"
