@@ -1,0 +1,215 @@
+"""Benchmark: cell-field-evals/s of the micromagnetic hot path on one MI355X.
+
+Workload: 512x512x16 ferromagnetic film of 2 nm cubes (demag, exchange,
+interfacial DMI on the bottom layer, uniaxial anisotropy, Zeeman), fixed
+Dormand-Prince 5(4) steps of 0.1 ns/1667.  One step = 6 new effective-field
+evaluations (the 7-stage pair is first-same-as-last) over every cell; the
+value is cells * 6 * steps / seconds for the FP32 path, with the FP64 path
+timed the same way beside it.  The state is resident in HBM before the timed
+region; nothing is copied to or from the host inside it.
+
+Also reported: the dominant kernel's algorithmic bytes per launch over its
+average HIP-event duration during the timed region (roofline vs 8 TB/s), the
+HBM traffic the rocprofv3 counters measured for that kernel (when the
+committed counter summary matches the current kernel source), and the FP64
+CPU oracle timed on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-fp64]
+       [--no-cpu-baseline] [--profile-steps K]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("cell-field-evals/s 512x512x16 FP32 vs FP64; batched solves/s with p50/p99 "
+          "latency")
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("paper_2411_18194_amd/csrc/demag.hip", "paper_2411_18194_amd/csrc/fft_engine.h",
+                  "paper_2411_18194_amd/csrc/field.hip")
+COUNTERS = os.path.join(ROOT, "profiles", "counters_c2_fp32.json")
+
+
+def smooth_pad(n):
+    if n == 1:
+        return 1
+    p = 2 * n - 1
+    while True:
+        if p % 2 == 0:
+            q = p
+            for f in (2, 3, 5, 7):
+                while q % f == 0:
+                    q //= f
+            if q == 1:
+                return p
+        p += 1
+
+
+def algorithmic_bytes(n, rb, nsub=1):
+    """Bytes each kernel class must move per launch (operands read once)."""
+    nx, ny, nz = n
+    N = nx * ny * nz
+    cb = 2 * rb
+    Px, Py, Pz = smooth_pad(nx), smooth_pad(ny), smooth_pad(nz)
+    Hx, Hy, Hz = Px // 2 + 1, Py // 2 + 1, Pz // 2 + 1
+    s1 = cb * 3 * nz * Hx * ny
+    out = {"fftx_fwd": rb * nsub * 3 * N + s1, "fftx_inv": s1 + rb * 3 * N}
+    if nz > 1:
+        s2 = cb * 3 * nz * Hx * Py
+        out["ffty_fwd"] = s1 + s2
+        out["fftz_mul"] = 2 * s2 + rb * 6 * Hz * Hx * Hy
+        out["ffty_inv"] = s2 + s1
+    else:
+        out["ffty_mul2d"] = 2 * s1 + rb * 4 * Hx * Hy
+    # field kernel, fixed-step stages s = 2..7.  s < 7 reads the stage input,
+    # B_d, y_n and k_1..k_{s-1} and writes k_s and the next stage input; s = 7
+    # reads its input and B_d and writes k_7 and the next step's stage-2 input.
+    v = rb * 3 * nsub * N
+    bd = rb * 3 * N
+    per_stage = [(s + 3) * v + bd for s in range(2, 7)] + [3 * v + bd]
+    out["field"] = sum(per_stage) / len(per_stage)
+    return out
+
+
+def src_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def run_gpu(precision, steps, warmup, prof=True):
+    import torch
+
+    from paper_2411_18194_amd import inputs, mmp
+
+    p, m0 = inputs.config_c2()
+    g = mmp.Grid(p, precision)
+    stream = torch.cuda.current_stream()
+    g.set_stream(stream.cuda_stream)
+    g.set_state(m0)
+    dt = inputs.c2_fixed_dt()
+    g.run_fixed(dt, warmup)
+    torch.cuda.synchronize()
+    g.prof_reset()
+    g.prof_enable(prof)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.run_fixed(dt, steps, sync=False)
+    g.synchronize()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g.prof_enable(False)
+    kern = g.prof_read()
+    m = g.get_state()[0]
+    finite = bool(np.isfinite(m).all())
+    norm_err = float(np.abs(np.linalg.norm(m, axis=1) - 1).max())
+    g.close()
+    N = p["n"][0] * p["n"][1] * p["n"][2]
+    sec = t1 - t0
+    return dict(value=N * 6 * steps / sec, ms_per_step=1e3 * sec / steps, kernels=kern,
+                finite=finite, norm_err=norm_err, n=p["n"])
+
+
+def roofline(res, rb):
+    ab = algorithmic_bytes(res["n"], rb)
+    kern = res["kernels"]
+    tot = {k: v[0] for k, v in kern.items() if v[1] > 0}
+    dom = max((k for k in tot if k in ab), key=lambda k: tot[k])
+    ms, cnt = kern[dom]
+    avg_s = ms / cnt / 1e3
+    ach = ab[dom] / avg_s / 1e9
+    traffic = None
+    if os.path.exists(COUNTERS):
+        with open(COUNTERS) as fh:
+            c = json.load(fh)
+        if c.get("source_hash") == src_hash() and dom in c.get("kernels", {}):
+            traffic = c["kernels"][dom]["bytes_per_launch"]
+    share = {k: round(v / sum(tot.values()), 4) for k, v in tot.items()}
+    return {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "algorithmic_bytes_per_launch": ab[dom], "avg_launch_ms": round(avg_s * 1e3, 4),
+            "time_share": share}
+
+
+def cpu_baseline():
+    """FP64 oracle on a 256x256x16 block of the same film (1/4 of the cells)."""
+    from oracle.system import Problem
+    from paper_2411_18194_amd import inputs
+
+    cores = len(os.sched_getaffinity(0))
+    n = (256, 256, 16)
+    p = inputs.base_params(n, (2e-9,) * 3)
+    full, _ = inputs.config_c2(n=(8, 8, 16))
+    for k in ("Ms", "A11", "alpha", "Ku1", "anis_u", "Dint", "dmi_layer", "B_ext", "demag"):
+        p[k] = full[k]
+    m = inputs.smoothed_random_unit(inputs.rng(2), 1, n)
+    P = Problem(p, demag_workers=cores)
+    dt = inputs.c2_fixed_dt()
+    y = P.initial_state(m)
+    y, _ = P.run_fixed(y, 0.0, dt, 1)          # warm-up (also fills the FSAL stage)
+    t0 = time.perf_counter()
+    nsteps = 2
+    y, _ = P.run_fixed(y, 0.0, dt, nsteps)
+    sec = time.perf_counter() - t0
+    N = n[0] * n[1] * n[2]
+    return {"value": N * 6 * nsteps / sec, "unit": "cell-field-evals/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{n[0]}x{n[1]}x{n[2]} block of the 512x512x16 film (same material, "
+                      f"own open-boundary demag), {nsteps} fixed DP45 steps = {6 * nsteps} "
+                      f"field evaluations, FP64 numpy/scipy (FFT on {cores} threads, "
+                      f"element-wise work on 1)", "seconds": round(sec, 2)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-prof", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the method has no multi-GPU path here "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    from paper_2411_18194_amd import mmp
+    r32 = run_gpu(mmp.FP32, args.steps, args.warmup, prof=not args.no_prof)
+    out = {
+        "metric": METRIC, "value": round(r32["value"], 1), "unit": "cell-field-evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(r32["ms_per_step"], 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "512x512x16 film, 2 nm cells, demag + exchange + interfacial "
+                               "DMI (bottom layer) + uniaxial + Zeeman, fixed-step DP45 "
+                               "(0.1 ns / 1667)",
+                   "cells": 512 * 512 * 16, "field_evals_per_step": 6,
+                   "demag_pad": [1024, 1024, 32]},
+        "state_finite": r32["finite"], "max_norm_error": r32["norm_err"],
+    }
+    if not args.no_prof:
+        out["roofline"] = roofline(r32, 4)
+    if not args.no_fp64:
+        r64 = run_gpu(mmp.FP64, max(3, args.steps // 3), args.warmup, prof=False)
+        out["fp64"] = {"value": round(r64["value"], 1), "unit": "cell-field-evals/s",
+                       "ms_per_step": round(r64["ms_per_step"], 4),
+                       "fp32_speedup": round(r32["value"] / r64["value"], 3)}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

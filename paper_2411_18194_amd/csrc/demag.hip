@@ -47,7 +47,7 @@ struct XArgs {
   Rad rad;
 };
 
-template <typename T>
+template <typename T, bool P2>
 __global__ void k_fftx_fwd(XArgs<T> a) {
   using V = cpx<T>;
   if (ctrl_stopped(a.ctrl)) return;
@@ -77,7 +77,7 @@ __global__ void k_fftx_fwd(XArgs<T> a) {
     buf[q * a.Px + x] = cmk<T>(re, im);
   }
   __syncthreads();
-  lds_fft<T, false>(buf, a.tw, a.Px, nl, a.Px, a.rad, tid, nthr);
+  lds_fft<T, false, P2>(buf, a.tw, a.Px, nl, a.Px, a.rad.n, a.rad.code, tid, nthr);
   // unpack the two real spectra and store them transposed
   V* out = a.S1 + ((long)(c * a.nz + z) * a.Hx) * a.ldy + y0;
   for (int idx = tid; idx < nl * a.Hx; idx += nthr) {
@@ -94,7 +94,7 @@ __global__ void k_fftx_fwd(XArgs<T> a) {
   }
 }
 
-template <typename T>
+template <typename T, bool P2>
 __global__ void k_fftx_inv(XArgs<T> a) {
   using V = cpx<T>;
   if (ctrl_stopped(a.ctrl)) return;
@@ -113,7 +113,7 @@ __global__ void k_fftx_inv(XArgs<T> a) {
       buf[q * a.Px + a.Px - kx] = cmk<T>(xa.x + xb.y, xb.x - xa.y);
   }
   __syncthreads();
-  lds_fft<T, true>(buf, a.tw, a.Px, nl, a.Px, a.rad, tid, nthr);
+  lds_fft<T, true, P2>(buf, a.tw, a.Px, nl, a.Px, a.rad.n, a.rad.code, tid, nthr);
   const long N = (long)a.nx * a.ny * a.nz;
   T* out = a.Bd + (long)c * N + (long)z * a.ny * a.nx;
   for (int idx = tid; idx < nl * a.nx; idx += nthr) {
@@ -136,7 +136,7 @@ struct YArgs {
   Rad rad;
 };
 
-template <typename T, bool INV>
+template <typename T, bool INV, bool P2>
 __global__ void k_ffty(YArgs<T> a) {
   using V = cpx<T>;
   if (ctrl_stopped(a.ctrl)) return;
@@ -152,7 +152,7 @@ __global__ void k_ffty(YArgs<T> a) {
     buf[q * a.L + e] = v;
   }
   __syncthreads();
-  lds_fft<T, INV>(buf, a.tw, a.L, a.nl, a.L, a.rad, tid, nthr);
+  lds_fft<T, INV, P2>(buf, a.tw, a.L, a.nl, a.L, a.rad.n, a.rad.code, tid, nthr);
   for (int idx = tid; idx < a.nl * a.nvalid_out; idx += nthr) {
     const int q = idx / a.nvalid_out, e = idx - q * a.nvalid_out;
     const int gl = l0 + q;
@@ -190,7 +190,7 @@ struct M2Args {
   Rad rad;
 };
 
-template <typename T>
+template <typename T, bool P2>
 __global__ void k_ffty_mul2d(M2Args<T> a) {
   using V = cpx<T>;
   if (ctrl_stopped(a.ctrl)) return;
@@ -209,7 +209,7 @@ __global__ void k_ffty_mul2d(M2Args<T> a) {
     buf[line * L + e] = v;
   }
   __syncthreads();
-  lds_fft<T, false>(buf, a.tw, L, nl, L, a.rad, tid, nthr);
+  lds_fft<T, false, P2>(buf, a.tw, L, nl, L, a.rad.n, a.rad.code, tid, nthr);
   const long kstride = (long)a.Hx * a.Hy;
   for (int idx = tid; idx < a.nk * L; idx += nthr) {
     const int j = idx / L, ky = idx - j * L;
@@ -226,7 +226,7 @@ __global__ void k_ffty_mul2d(M2Args<T> a) {
     buf[(2 * a.nk + j) * L + ky] = mz;
   }
   __syncthreads();
-  lds_fft<T, true>(buf, a.tw, L, nl, L, a.rad, tid, nthr);
+  lds_fft<T, true, P2>(buf, a.tw, L, nl, L, a.rad.n, a.rad.code, tid, nthr);
   for (int idx = tid; idx < nl * a.ny; idx += nthr) {
     const int line = idx / a.ny, e = idx - line * a.ny;
     const int c = line / a.nk, j = line - c * a.nk;
@@ -246,7 +246,7 @@ struct ZArgs {
   Rad rad;
 };
 
-template <typename T>
+template <typename T, bool P2>
 __global__ void k_fftz_mul(ZArgs<T> a) {
   using V = cpx<T>;
   if (ctrl_stopped(a.ctrl)) return;
@@ -268,7 +268,7 @@ __global__ void k_fftz_mul(ZArgs<T> a) {
     buf[(c * a.tk + j) * a.ls + z] = v;
   }
   __syncthreads();
-  lds_fft<T, false>(buf, a.tw, L, nl, a.ls, a.rad, tid, nthr);
+  lds_fft<T, false, P2>(buf, a.tw, L, nl, a.ls, a.rad.n, a.rad.code, tid, nthr);
   const long kstride = (long)a.Hz * a.Hx * a.Hy;
   for (int idx = tid; idx < a.tk * L; idx += nthr) {
     const int j = idx % a.tk, kz = idx / a.tk;
@@ -287,7 +287,7 @@ __global__ void k_fftz_mul(ZArgs<T> a) {
     buf[(2 * a.tk + j) * a.ls + kz] = mz;
   }
   __syncthreads();
-  lds_fft<T, true>(buf, a.tw, L, nl, a.ls, a.rad, tid, nthr);
+  lds_fft<T, true, P2>(buf, a.tw, L, nl, a.ls, a.rad.n, a.rad.code, tid, nthr);
   V* obase = a.S2 + (long)kx * a.Py + ky0;
   for (int idx = tid; idx < 3 * a.tk * a.nz; idx += nthr) {
     const int j = idx % a.tk;
@@ -311,10 +311,14 @@ int demag_plan(int nx, int ny, int nz, int real_bytes, DemagPlan* p) {
   d.Px = smooth_pad(nx); d.Py = smooth_pad(ny); d.Pz = smooth_pad(nz);
   if (d.Px > 4096 || d.Py > 4096 || d.Pz > 4096) return -1;
   d.Hx = d.Px / 2 + 1; d.Hy = d.Py / 2 + 1; d.Hz = d.Pz / 2 + 1;
-  d.rx.n = fft_radices(d.Px, d.rx.r);
-  d.ry.n = fft_radices(d.Py, d.ry.r);
-  d.rz.n = fft_radices(d.Pz, d.rz.r);
-  if (d.rx.n < 0 || d.ry.n < 0 || d.rz.n < 0) return -1;
+  int rr[3][16];
+  const int nrx = fft_radices(d.Px, rr[0]);
+  const int nry = fft_radices(d.Py, rr[1]);
+  const int nrz = fft_radices(d.Pz, rr[2]);
+  if (nrx < 0 || nry < 0 || nrz < 0 || nrx > 15 || nry > 15 || nrz > 15) return -1;
+  d.rx = make_rad(rr[0], nrx);
+  d.ry = make_rad(rr[1], nry);
+  d.rz = make_rad(rr[2], nrz);
   // complex elements one block may hold in LDS (64 KiB)
   const long cap = 65536 / (2 * real_bytes);
   // x passes: ty rows (pairs) per block
@@ -363,7 +367,8 @@ void demag_field(const DemagPlan& p, const DemagBufs<T>& b, const Table<T>* tbl,
   const size_t lds_x = (size_t)(p.ty / 2) * p.Px * sizeof(V);
   {
     ProfScope ps(prof, P_FFTX_FWD, st);
-    hipLaunchKernelGGL(k_fftx_fwd<T>, gx, dim3(p.thr_x), lds_x, st, xa);
+    if (is_pow2(p.Px)) hipLaunchKernelGGL((k_fftx_fwd<T, true>), gx, dim3(p.thr_x), lds_x, st, xa);
+    else hipLaunchKernelGGL((k_fftx_fwd<T, false>), gx, dim3(p.thr_x), lds_x, st, xa);
   }
   if (p.nz == 1) {
     M2Args<T> ma;
@@ -371,8 +376,10 @@ void demag_field(const DemagPlan& p, const DemagBufs<T>& b, const Table<T>* tbl,
     ma.ny = p.ny; ma.Py = p.Py; ma.Hx = p.Hx; ma.Hy = p.Hy; ma.ldy = p.ldy; ma.nk = p.nk2;
     ma.rad = p.ry;
     ProfScope ps(prof, P_FFTY_MUL2D, st);
-    hipLaunchKernelGGL(k_ffty_mul2d<T>, dim3((p.Hx + p.nk2 - 1) / p.nk2), dim3(p.thr_m2),
-                       (size_t)3 * p.nk2 * p.Py * sizeof(V), st, ma);
+    const dim3 gm((p.Hx + p.nk2 - 1) / p.nk2);
+    const size_t lds_m = (size_t)3 * p.nk2 * p.Py * sizeof(V);
+    if (is_pow2(p.Py)) hipLaunchKernelGGL((k_ffty_mul2d<T, true>), gm, dim3(p.thr_m2), lds_m, st, ma);
+    else hipLaunchKernelGGL((k_ffty_mul2d<T, false>), gm, dim3(p.thr_m2), lds_m, st, ma);
   } else {
     const int nlines = 3 * p.nz * p.Hx;
     YArgs<T> ya;
@@ -383,7 +390,8 @@ void demag_field(const DemagPlan& p, const DemagBufs<T>& b, const Table<T>* tbl,
     const size_t lds_y = (size_t)p.nly * p.Py * sizeof(V);
     {
       ProfScope ps(prof, P_FFTY_FWD, st);
-      hipLaunchKernelGGL((k_ffty<T, false>), gy, dim3(p.thr_y), lds_y, st, ya);
+      if (is_pow2(p.Py)) hipLaunchKernelGGL((k_ffty<T, false, true>), gy, dim3(p.thr_y), lds_y, st, ya);
+      else hipLaunchKernelGGL((k_ffty<T, false, false>), gy, dim3(p.thr_y), lds_y, st, ya);
     }
     ZArgs<T> za;
     za.ctrl = ctrl; za.S2 = b.S2; za.K = b.K; za.tw = b.twz;
@@ -391,20 +399,24 @@ void demag_field(const DemagPlan& p, const DemagBufs<T>& b, const Table<T>* tbl,
     za.tk = p.tk; za.ls = p.lsz; za.rad = p.rz;
     {
       ProfScope ps(prof, P_FFTZ_MUL, st);
-      hipLaunchKernelGGL(k_fftz_mul<T>, dim3((p.Py + p.tk - 1) / p.tk, p.Hx), dim3(p.thr_z),
-                         (size_t)3 * p.tk * p.lsz * sizeof(V), st, za);
+      const dim3 gz((p.Py + p.tk - 1) / p.tk, p.Hx);
+      const size_t lds_z = (size_t)3 * p.tk * p.lsz * sizeof(V);
+      if (is_pow2(p.Pz)) hipLaunchKernelGGL((k_fftz_mul<T, true>), gz, dim3(p.thr_z), lds_z, st, za);
+      else hipLaunchKernelGGL((k_fftz_mul<T, false>), gz, dim3(p.thr_z), lds_z, st, za);
     }
     YArgs<T> yi = ya;
     yi.in = b.S2; yi.out = b.S1; yi.nvalid_in = p.Py; yi.ld_in = p.Py;
     yi.nvalid_out = p.ny; yi.ld_out = p.ldy;
     {
       ProfScope ps(prof, P_FFTY_INV, st);
-      hipLaunchKernelGGL((k_ffty<T, true>), gy, dim3(p.thr_y), lds_y, st, yi);
+      if (is_pow2(p.Py)) hipLaunchKernelGGL((k_ffty<T, true, true>), gy, dim3(p.thr_y), lds_y, st, yi);
+      else hipLaunchKernelGGL((k_ffty<T, true, false>), gy, dim3(p.thr_y), lds_y, st, yi);
     }
   }
   {
     ProfScope ps(prof, P_FFTX_INV, st);
-    hipLaunchKernelGGL(k_fftx_inv<T>, gx, dim3(p.thr_x), lds_x, st, xa);
+    if (is_pow2(p.Px)) hipLaunchKernelGGL((k_fftx_inv<T, true>), gx, dim3(p.thr_x), lds_x, st, xa);
+    else hipLaunchKernelGGL((k_fftx_inv<T, false>), gx, dim3(p.thr_x), lds_x, st, xa);
   }
 }
 

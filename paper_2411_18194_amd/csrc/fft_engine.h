@@ -15,10 +15,21 @@ namespace mmp {
 
 constexpr int kMaxE = 16;  // elements per thread per stage (register budget)
 
+// Radix plan packed in one integer (4 bits per stage, first stage in the low
+// bits) so kernels decode it with scalar shifts instead of indexing an array
+// (which would put the argument struct in private memory).
 struct Rad {
   int n;
-  int r[15];
+  uint64_t code;
 };
+
+inline Rad make_rad(const int* r, int n) {
+  Rad d;
+  d.n = n;
+  d.code = 0;
+  for (int i = 0; i < n; ++i) d.code |= (uint64_t)r[i] << (4 * i);
+  return d;
+}
 
 // cos/sin(2 pi j / R) for the odd radices, as exact-to-double literals
 template <int R> struct RootTable;
@@ -150,22 +161,27 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, const cpx<T>* __restrict_
   __syncthreads();
 }
 
-template <typename T, bool INV>
+// P2: the plan has only radices 8/4/2 (power-of-two length); the odd-radix
+// stages are then not compiled into the kernel, which keeps its register
+// footprint small enough to avoid spilling.
+template <typename T, bool INV, bool P2>
 __device__ void lds_fft(cpx<T>* buf, const cpx<T>* __restrict__ tw, int L, int nlines,
-                        int ls, const Rad& rad, int tid, int nthr) {
+                        int ls, const int nstages, const uint64_t code, int tid, int nthr) {
   int Ns = 1;
-  for (int s = 0; s < rad.n; ++s) {
-    const int R = rad.r[s];
-    switch (R) {
-      case 8: fft_stage<T, 8, INV>(buf, tw, L, nlines, ls, Ns, tid, nthr); break;
-      case 4: fft_stage<T, 4, INV>(buf, tw, L, nlines, ls, Ns, tid, nthr); break;
-      case 2: fft_stage<T, 2, INV>(buf, tw, L, nlines, ls, Ns, tid, nthr); break;
-      case 7: fft_stage<T, 7, INV>(buf, tw, L, nlines, ls, Ns, tid, nthr); break;
-      case 5: fft_stage<T, 5, INV>(buf, tw, L, nlines, ls, Ns, tid, nthr); break;
-      default: fft_stage<T, 3, INV>(buf, tw, L, nlines, ls, Ns, tid, nthr); break;
+  for (int s = 0; s < nstages; ++s) {
+    const int R = (int)((code >> (4 * s)) & 15u);
+    if (R == 8) fft_stage<T, 8, INV>(buf, tw, L, nlines, ls, Ns, tid, nthr);
+    else if (R == 4) fft_stage<T, 4, INV>(buf, tw, L, nlines, ls, Ns, tid, nthr);
+    else if (R == 2) fft_stage<T, 2, INV>(buf, tw, L, nlines, ls, Ns, tid, nthr);
+    else if constexpr (!P2) {
+      if (R == 7) fft_stage<T, 7, INV>(buf, tw, L, nlines, ls, Ns, tid, nthr);
+      else if (R == 5) fft_stage<T, 5, INV>(buf, tw, L, nlines, ls, Ns, tid, nthr);
+      else fft_stage<T, 3, INV>(buf, tw, L, nlines, ls, Ns, tid, nthr);
     }
     Ns *= R;
   }
 }
+
+inline bool is_pow2(int L) { return L > 0 && (L & (L - 1)) == 0; }
 
 }  // namespace mmp

@@ -26,6 +26,23 @@ __device__ __forceinline__ void cross3(const T* a, const T* b, T* o) {
   o[2] = a[0] * b[1] - a[1] * b[0];
 }
 
+// a*b - c*d with one rounding error (Kahan's difference of products)
+template <typename T>
+__device__ __forceinline__ T dop(T a, T b, T c, T d) {
+  const T w = c * d;
+  const T e = fma(-c, d, w);
+  const T f = fma(a, b, -w);
+  return f + e;
+}
+
+// m x m' accurate to a few ulp of the result even when m' ~ -m
+template <typename T>
+__device__ __forceinline__ void cross3_acc(const T* a, const T* b, T* o) {
+  o[0] = dop(a[1], b[2], a[2], b[1]);
+  o[1] = dop(a[2], b[0], a[0], b[2]);
+  o[2] = dop(a[0], b[1], a[1], b[0]);
+}
+
 template <typename T>
 __device__ __forceinline__ double dot3d(const T* a, const T* b) {
   return (double)a[0] * b[0] + (double)a[1] * b[1] + (double)a[2] * b[2];
@@ -144,7 +161,9 @@ __global__ __launch_bounds__(256) void k_field(const FieldArgs<T> a) {
             gyp[0] = mm[0]; gyp[1] = mm[1] + a.dy * k * mm[2]; gyp[2] = mm[2] - a.dy * k * mm[1];
           }
         }
-        T B[3] = {0, 0, 0};
+        T B[3] = {0, 0, 0};     // field driving the torque (all but A0)
+        T Bout[3] = {0, 0, 0};  // extra output-only part (A0, eval mode)
+        bool a0_on = false;
         T bt[3];
         auto add = [&](int term, const T* b) {
           if (!EVAL || (a.mask & (1u << term))) {
@@ -184,7 +203,15 @@ __global__ __launch_bounds__(256) void k_field(const FieldArgs<T> a) {
           if (EVAL) eacc[2] += -0.5 * C.Ms_d * dot3d(mm, bt);
 #pragma unroll
           for (int c = 0; c < 3; ++c) bt[c] = C.ccell * cur[o][c];
-          add(3, bt);
+          // The homogeneous inter-sublattice field is ~1000x larger than the
+          // torque it leaves when m' ~ -m, so its torque is formed from an
+          // accurate m x m' (tau is linear in B) instead of from B.
+          if (!EVAL || (a.mask & (1u << 3))) {
+            a0_on = true;
+            if (EVAL) {
+              Bout[0] += bt[0]; Bout[1] += bt[1]; Bout[2] += bt[2];
+            }
+          }
           if (EVAL) eacc[3] += -0.5 * C.Ms_d * dot3d(mm, bt);
         }
         // demag
@@ -243,6 +270,13 @@ __global__ __launch_bounds__(256) void k_field(const FieldArgs<T> a) {
         cross3(mm, mxB, mxmxB);
 #pragma unroll
         for (int c = 0; c < 3; ++c) tau[c] = -C.gl * (mxB[c] + C.alpha * mxmxB[c]);
+        if (NSUB == 2 && a0_on) {
+          T w[3], mxw[3];
+          cross3_acc(mm, cur[1 - s], w);
+          cross3(mm, w, mxw);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) tau[c] -= C.gl * C.ccell * (w[c] + C.alpha * mxw[c]);
+        }
         const bool zl = EVAL ? (a.add_zl && C.has_zl) : C.has_zl;
         if (zl) {
           T dm[3], mxdm[3], mxmxdm[3];
@@ -259,10 +293,15 @@ __global__ __launch_bounds__(256) void k_field(const FieldArgs<T> a) {
         const long base = s * N3 + i;
         if (EVAL) {
           if (a.bout) {
-            const T* o = a.out_torque ? tau : B;
-            a.bout[base] = o[0];
-            a.bout[base + N] = o[1];
-            a.bout[base + 2 * N] = o[2];
+            if (a.out_torque) {
+              a.bout[base] = tau[0];
+              a.bout[base + N] = tau[1];
+              a.bout[base + 2 * N] = tau[2];
+            } else {
+              a.bout[base] = B[0] + Bout[0];
+              a.bout[base + N] = B[1] + Bout[1];
+              a.bout[base + 2 * N] = B[2] + Bout[2];
+            }
           }
         } else {
           if (!(isfinite(tau[0]) && isfinite(tau[1]) && isfinite(tau[2])))
