@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmmp.so")
 ARCH = os.environ.get("MMP_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["abi.hip", "grid.hip", "field.hip", "demag.hip", "tensor.hip", "elastic.hip",
+SOURCES = ["abi.hip", "grid.hip", "field.hip", "demag.hip", "demag4.hip", "tensor.hip", "elastic.hip",
            "server.hip"]
 
 FLAGS = [

@@ -22,6 +22,9 @@ struct DemagPlan {
   int nly = 0, thr_y = 0;           // y passes: lines per block, threads
   int tk = 0, lsz = 0, thr_z = 0;   // z pass: ky per block, LDS line stride
   int nk2 = 0, thr_m2 = 0;          // 2-D fused y pass: kx columns per block
+  // power-of-two axes use the register four-step kernels
+  bool p2x = false, p2y = false, p2z = false;
+  int nly4 = 0, nk4 = 0, tk4 = 0;
   size_t s1_elems = 0, s2_elems = 0, k_elems = 0;
 };
 
@@ -35,6 +38,8 @@ struct DemagBufs {
   cpx<T>* twx = nullptr;    // exp(-2 pi i j/P) tables
   cpx<T>* twy = nullptr;
   cpx<T>* twz = nullptr;
+  cpx<T>* tw4x = nullptr;   // four-step tables [k1][t] = exp(-2 pi i t k1/L)
+  cpx<T>* tw4y = nullptr;
   T* Bd = nullptr;          // output field [3][N]
 };
 
@@ -56,5 +61,8 @@ int demag_tensor_only(int nx, int ny, int nz, double dx, double dy, double dz, d
 
 template <typename T>
 void build_twiddles(cpx<T>* tw, int L, hipStream_t st);
+template <typename T>
+void build_twiddles4(cpx<T>* tw, int L, hipStream_t st);
+int split_l2(int L);
 
 }  // namespace mmp

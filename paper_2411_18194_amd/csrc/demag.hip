@@ -12,6 +12,7 @@
 // A 2-D grid (nz == 1) fuses y forward, multiply and y inverse in one pass.
 // Zero padding is never materialised in memory: the pads exist only in LDS.
 #include "demag.h"
+#include "demag4.h"
 
 namespace mmp {
 
@@ -346,6 +347,29 @@ int demag_plan(int nx, int ny, int nz, int real_bytes, DemagPlan* p) {
   d.tk = tk;
   d.thr_z = threads_for((long)3 * tk * d.Pz);
   if (d.thr_x > 1024 || d.thr_y > 1024 || d.thr_m2 > 1024 || d.thr_z > 1024) return -1;
+  // power-of-two axes: register four-step kernels (FP64 only up to 2048
+  // points per line, the z column up to 32 points)
+  const int lmax = real_bytes == 8 ? 2048 : 4096;
+  d.p2x = is_pow2(d.Px) && d.Px <= lmax;
+  d.p2y = is_pow2(d.Py) && d.Py <= lmax;
+  d.p2z = is_pow2(d.Pz) && d.Pz <= 32;
+  {
+    const int l2 = split_l2(d.Py);
+    int n = 1;
+    while (n < 64 && (long)(2 * n) * d.Py <= cap && 2 * n * l2 <= 256) n *= 2;
+    d.nly4 = n;
+    int k = 1;
+    while (k < 64 && (long)3 * (2 * k) * d.Py <= cap && 3 * (2 * k) * l2 <= 256) k *= 2;
+    d.nk4 = k;
+    int tk4 = 1;
+    while (tk4 < 64 && (long)3 * d.Pz * (2 * tk4) <= cap && 3 * (2 * tk4) <= 256) tk4 *= 2;
+    d.tk4 = tk4;
+    // the x rows per block also bound the four-step block to 256 threads
+    if (d.p2x)
+      while ((d.ty / 2) * split_l2(d.Px) > 256) d.ty /= 2;
+    d.ldy = round_up(ny, d.ty);
+    if (3 * d.nk4 * l2 > 256 || d.nly4 * l2 > 256 || 3 * d.tk4 > 256) return -1;
+  }
   d.s1_elems = (size_t)3 * nz * d.Hx * d.ldy;
   d.s2_elems = nz > 1 ? (size_t)3 * nz * d.Hx * d.Py : 0;
   d.k_elems = (size_t)6 * d.Hz * d.Hx * d.Hy;
@@ -358,28 +382,39 @@ template <typename T>
 void demag_field(const DemagPlan& p, const DemagBufs<T>& b, const Table<T>* tbl, int stage,
                  const Ctrl* ctrl, T ms0, T ms1, int nsub, hipStream_t st, Prof* prof) {
   using V = cpx<T>;
+  const dim3 gx((p.ny + p.ty - 1) / p.ty, p.nz, 3);
+  const size_t lds_x = (size_t)(p.ty / 2) * p.Px * sizeof(V);
   XArgs<T> xa;
   xa.tbl = tbl; xa.ctrl = ctrl; xa.stage = stage; xa.ms0 = ms0; xa.ms1 = ms1; xa.nsub = nsub;
   xa.S1 = b.S1; xa.Bd = b.Bd; xa.tw = b.twx;
   xa.nx = p.nx; xa.ny = p.ny; xa.nz = p.nz; xa.Px = p.Px; xa.Hx = p.Hx; xa.ldy = p.ldy;
   xa.ty = p.ty; xa.rad = p.rx;
-  const dim3 gx((p.ny + p.ty - 1) / p.ty, p.nz, 3);
-  const size_t lds_x = (size_t)(p.ty / 2) * p.Px * sizeof(V);
+  X4Args<T> x4;
+  x4.tbl = tbl; x4.ctrl = ctrl; x4.stage = stage; x4.ms0 = ms0; x4.ms1 = ms1; x4.nsub = nsub;
+  x4.S1 = b.S1; x4.Bd = b.Bd; x4.tw4 = b.tw4x;
+  x4.nx = p.nx; x4.ny = p.ny; x4.nz = p.nz; x4.Hx = p.Hx; x4.ldy = p.ldy; x4.ty = p.ty;
+  const int thr_x4 = (p.ty / 2) * split_l2(p.Px);
   {
     ProfScope ps(prof, P_FFTX_FWD, st);
-    if (is_pow2(p.Px)) hipLaunchKernelGGL((k_fftx_fwd<T, true>), gx, dim3(p.thr_x), lds_x, st, xa);
+    if (p.p2x) launch_x4<T>(p.Px, false, gx, thr_x4, lds_x, st, x4);
     else hipLaunchKernelGGL((k_fftx_fwd<T, false>), gx, dim3(p.thr_x), lds_x, st, xa);
   }
   if (p.nz == 1) {
-    M2Args<T> ma;
-    ma.ctrl = ctrl; ma.S1 = b.S1; ma.K = b.K; ma.tw = b.twy;
-    ma.ny = p.ny; ma.Py = p.Py; ma.Hx = p.Hx; ma.Hy = p.Hy; ma.ldy = p.ldy; ma.nk = p.nk2;
-    ma.rad = p.ry;
     ProfScope ps(prof, P_FFTY_MUL2D, st);
-    const dim3 gm((p.Hx + p.nk2 - 1) / p.nk2);
-    const size_t lds_m = (size_t)3 * p.nk2 * p.Py * sizeof(V);
-    if (is_pow2(p.Py)) hipLaunchKernelGGL((k_ffty_mul2d<T, true>), gm, dim3(p.thr_m2), lds_m, st, ma);
-    else hipLaunchKernelGGL((k_ffty_mul2d<T, false>), gm, dim3(p.thr_m2), lds_m, st, ma);
+    if (p.p2y) {
+      M4Args<T> m4;
+      m4.ctrl = ctrl; m4.S1 = b.S1; m4.K = b.K; m4.tw4 = b.tw4y;
+      m4.ny = p.ny; m4.Hx = p.Hx; m4.Hy = p.Hy; m4.ldy = p.ldy; m4.nk = p.nk4;
+      launch_m4<T>(p.Py, dim3((p.Hx + p.nk4 - 1) / p.nk4), 3 * p.nk4 * split_l2(p.Py),
+                   (size_t)3 * p.nk4 * p.Py * sizeof(V), st, m4);
+    } else {
+      M2Args<T> ma;
+      ma.ctrl = ctrl; ma.S1 = b.S1; ma.K = b.K; ma.tw = b.twy;
+      ma.ny = p.ny; ma.Py = p.Py; ma.Hx = p.Hx; ma.Hy = p.Hy; ma.ldy = p.ldy; ma.nk = p.nk2;
+      ma.rad = p.ry;
+      hipLaunchKernelGGL((k_ffty_mul2d<T, false>), dim3((p.Hx + p.nk2 - 1) / p.nk2),
+                         dim3(p.thr_m2), (size_t)3 * p.nk2 * p.Py * sizeof(V), st, ma);
+    }
   } else {
     const int nlines = 3 * p.nz * p.Hx;
     YArgs<T> ya;
@@ -388,34 +423,53 @@ void demag_field(const DemagPlan& p, const DemagBufs<T>& b, const Table<T>* tbl,
     ya.ld_out = p.Py; ya.L = p.Py; ya.nl = p.nly; ya.rad = p.ry;
     const dim3 gy((nlines + p.nly - 1) / p.nly);
     const size_t lds_y = (size_t)p.nly * p.Py * sizeof(V);
+    Y4Args<T> y4;
+    y4.ctrl = ctrl; y4.in = b.S1; y4.out = b.S2; y4.tw4 = b.tw4y;
+    y4.nlines = nlines; y4.nvalid_in = p.ny; y4.ld_in = p.ldy; y4.nvalid_out = p.Py;
+    y4.ld_out = p.Py; y4.nl = p.nly4;
+    const dim3 gy4((nlines + p.nly4 - 1) / p.nly4);
+    const int thr_y4 = p.nly4 * split_l2(p.Py);
+    const size_t lds_y4 = (size_t)p.nly4 * p.Py * sizeof(V);
     {
       ProfScope ps(prof, P_FFTY_FWD, st);
-      if (is_pow2(p.Py)) hipLaunchKernelGGL((k_ffty<T, false, true>), gy, dim3(p.thr_y), lds_y, st, ya);
+      if (p.p2y) launch_y4<T>(p.Py, false, gy4, thr_y4, lds_y4, st, y4);
       else hipLaunchKernelGGL((k_ffty<T, false, false>), gy, dim3(p.thr_y), lds_y, st, ya);
     }
-    ZArgs<T> za;
-    za.ctrl = ctrl; za.S2 = b.S2; za.K = b.K; za.tw = b.twz;
-    za.nz = p.nz; za.Pz = p.Pz; za.Hx = p.Hx; za.Py = p.Py; za.Hy = p.Hy; za.Hz = p.Hz;
-    za.tk = p.tk; za.ls = p.lsz; za.rad = p.rz;
     {
       ProfScope ps(prof, P_FFTZ_MUL, st);
-      const dim3 gz((p.Py + p.tk - 1) / p.tk, p.Hx);
-      const size_t lds_z = (size_t)3 * p.tk * p.lsz * sizeof(V);
-      if (is_pow2(p.Pz)) hipLaunchKernelGGL((k_fftz_mul<T, true>), gz, dim3(p.thr_z), lds_z, st, za);
-      else hipLaunchKernelGGL((k_fftz_mul<T, false>), gz, dim3(p.thr_z), lds_z, st, za);
+      if (p.p2z) {
+        Z4Args<T> z4;
+        z4.ctrl = ctrl; z4.S2 = b.S2; z4.K = b.K;
+        z4.nz = p.nz; z4.Hx = p.Hx; z4.Py = p.Py; z4.Hy = p.Hy; z4.Hz = p.Hz; z4.tk = p.tk4;
+        launch_z4<T>(p.Pz, dim3((p.Py + p.tk4 - 1) / p.tk4, p.Hx), 3 * p.tk4,
+                     (size_t)3 * p.Pz * p.tk4 * sizeof(V), st, z4);
+      } else {
+        ZArgs<T> za;
+        za.ctrl = ctrl; za.S2 = b.S2; za.K = b.K; za.tw = b.twz;
+        za.nz = p.nz; za.Pz = p.Pz; za.Hx = p.Hx; za.Py = p.Py; za.Hy = p.Hy; za.Hz = p.Hz;
+        za.tk = p.tk; za.ls = p.lsz; za.rad = p.rz;
+        hipLaunchKernelGGL((k_fftz_mul<T, false>), dim3((p.Py + p.tk - 1) / p.tk, p.Hx),
+                           dim3(p.thr_z), (size_t)3 * p.tk * p.lsz * sizeof(V), st, za);
+      }
     }
-    YArgs<T> yi = ya;
-    yi.in = b.S2; yi.out = b.S1; yi.nvalid_in = p.Py; yi.ld_in = p.Py;
-    yi.nvalid_out = p.ny; yi.ld_out = p.ldy;
     {
       ProfScope ps(prof, P_FFTY_INV, st);
-      if (is_pow2(p.Py)) hipLaunchKernelGGL((k_ffty<T, true, true>), gy, dim3(p.thr_y), lds_y, st, yi);
-      else hipLaunchKernelGGL((k_ffty<T, true, false>), gy, dim3(p.thr_y), lds_y, st, yi);
+      if (p.p2y) {
+        Y4Args<T> yi = y4;
+        yi.in = b.S2; yi.out = b.S1; yi.nvalid_in = p.Py; yi.ld_in = p.Py;
+        yi.nvalid_out = p.ny; yi.ld_out = p.ldy;
+        launch_y4<T>(p.Py, true, gy4, thr_y4, lds_y4, st, yi);
+      } else {
+        YArgs<T> yi = ya;
+        yi.in = b.S2; yi.out = b.S1; yi.nvalid_in = p.Py; yi.ld_in = p.Py;
+        yi.nvalid_out = p.ny; yi.ld_out = p.ldy;
+        hipLaunchKernelGGL((k_ffty<T, true, false>), gy, dim3(p.thr_y), lds_y, st, yi);
+      }
     }
   }
   {
     ProfScope ps(prof, P_FFTX_INV, st);
-    if (is_pow2(p.Px)) hipLaunchKernelGGL((k_fftx_inv<T, true>), gx, dim3(p.thr_x), lds_x, st, xa);
+    if (p.p2x) launch_x4<T>(p.Px, true, gx, thr_x4, lds_x, st, x4);
     else hipLaunchKernelGGL((k_fftx_inv<T, false>), gx, dim3(p.thr_x), lds_x, st, xa);
   }
 }

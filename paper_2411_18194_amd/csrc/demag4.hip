@@ -1,0 +1,399 @@
+// Power-of-two demag passes built on register FFTs (see fft4.h).
+//
+// Same pass structure and memory layout as the mixed-radix passes in
+// demag.hip; only the in-block transform differs: each line is a four-step
+// transform (two register FFTs and one swizzled LDS transpose) and the z
+// pass holds a whole column per thread.  Loads and stores of lines are
+// coalesced across the L2 threads of a line.
+#include "demag4.h"
+#include "fft4.h"
+
+namespace mmp {
+
+template <typename T>
+__global__ void k_twiddles4(cpx<T>* tw, int L1, int L2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L1 * L2) return;
+  const int k1 = i / L2, t = i - k1 * L2;
+  double s, c;
+  sincospi(-2.0 * (double)(t * k1) / (double)(L1 * L2), &s, &c);
+  tw[i] = cmk<T>((T)c, (T)s);
+}
+
+int split_l2(int L) {
+  int lg = 0;
+  while ((1 << lg) < L) ++lg;
+  return 1 << (lg / 2);
+}
+
+template <typename T>
+void build_twiddles4(cpx<T>* tw, int L, hipStream_t st) {
+  const int L2 = split_l2(L), L1 = L / L2;
+  hipLaunchKernelGGL(k_twiddles4<T>, dim3((L + 255) / 256), dim3(256), 0, st, tw, L1, L2);
+}
+template void build_twiddles4<float>(cpx<float>*, int, hipStream_t);
+template void build_twiddles4<double>(cpx<double>*, int, hipStream_t);
+
+// step 1: L1-point register FFT, inter-step twiddle, swizzled LDS row store
+template <typename T, int L1, int L2, bool INV>
+__device__ __forceinline__ void fs_step1(cpx<T>* v, cpx<T>* line, const cpx<T>* __restrict__ tw4,
+                                         int t) {
+  reg_fft<T, L1, INV>(v);
+#pragma unroll
+  for (int k1 = 0; k1 < L1; ++k1) {
+    cpx<T> x = v[bitrev<L1>(k1)];
+    if (k1 > 0) {
+      cpx<T> w = tw4[k1 * L2 + t];
+      if (INV) w.y = -w.y;
+      x = cmul(x, w);
+    }
+    line[k1 * L2 + (t ^ (k1 & (L2 - 1)))] = x;
+  }
+}
+
+// step 3: L2-point register FFTs of the swizzled columns owned by thread t;
+// u[i][bitrev<L2>(k2)] = X[t + L2 i + L1 k2]
+template <typename T, int L1, int L2, bool INV>
+__device__ __forceinline__ void fs_step3(cpx<T> (*u)[L2], const cpx<T>* line, int t) {
+#pragma unroll
+  for (int i = 0; i < L1 / L2; ++i) {
+    const int k1 = t + L2 * i;
+#pragma unroll
+    for (int n2 = 0; n2 < L2; ++n2) u[i][n2] = line[k1 * L2 + (n2 ^ (k1 & (L2 - 1)))];
+    reg_fft<T, L2, INV>(u[i]);
+  }
+}
+
+// ------------------------------------------------------------ y lines --
+template <typename T, int L1, int L2, bool INV>
+__global__ __launch_bounds__(256) void k4_ffty(Y4Args<T> a) {
+  using V = cpx<T>;
+  if (ctrl_stopped(a.ctrl)) return;
+  constexpr int L = L1 * L2;
+  extern __shared__ char smem_raw[];
+  V* lds = reinterpret_cast<V*>(smem_raw);
+  const int t = threadIdx.x % L2, q = threadIdx.x / L2;
+  const int gl = blockIdx.x * a.nl + q;
+  const bool valid = gl < a.nlines;
+  V* line = lds + q * L;
+  const V* in = a.in + (long)gl * a.ld_in;
+  V v[L1];
+#pragma unroll
+  for (int n1 = 0; n1 < L1; ++n1) {
+    const int idx = L2 * n1 + t;
+    v[n1] = (valid && idx < a.nvalid_in) ? in[idx] : cmk<T>(0, 0);
+  }
+  fs_step1<T, L1, L2, INV>(v, line, a.tw4, t);
+  __syncthreads();
+  V u[L1 / L2][L2];
+  fs_step3<T, L1, L2, INV>(u, line, t);
+  if (valid) {
+    V* out = a.out + (long)gl * a.ld_out;
+#pragma unroll
+    for (int i = 0; i < L1 / L2; ++i)
+#pragma unroll
+      for (int k2 = 0; k2 < L2; ++k2) {
+        const int k = t + L2 * i + L1 * k2;
+        if (k < a.nvalid_out) out[k] = u[i][bitrev<L2>(k2)];
+      }
+  }
+}
+
+// ------------------------------------------------------------- x rows --
+template <typename T, int L1, int L2>
+__global__ __launch_bounds__(256) void k4_fftx_fwd(X4Args<T> a) {
+  using V = cpx<T>;
+  if (ctrl_stopped(a.ctrl)) return;
+  constexpr int L = L1 * L2;
+  extern __shared__ char smem_raw[];
+  V* lds = reinterpret_cast<V*>(smem_raw);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int t = tid % L2, q = tid / L2;
+  const int c = blockIdx.z, z = blockIdx.y, y0 = blockIdx.x * a.ty;
+  const int nl = a.ty >> 1;
+  const long N = (long)a.nx * a.ny * a.nz;
+  const T* m = stage_in(a.tbl, a.stage);
+  const T* m0 = m + (long)c * N + (long)z * a.ny * a.nx;
+  const T* m1 = m0 + 3 * N;
+  const int ya = y0 + 2 * q, yb = ya + 1;
+  V* line = lds + q * L;
+  V v[L1];
+#pragma unroll
+  for (int n1 = 0; n1 < L1; ++n1) {
+    const int x = L2 * n1 + t;
+    T re = 0, im = 0;
+    if (x < a.nx) {
+      if (ya < a.ny) {
+        re = a.ms0 * m0[(long)ya * a.nx + x];
+        if (a.nsub == 2) re += a.ms1 * m1[(long)ya * a.nx + x];
+      }
+      if (yb < a.ny) {
+        im = a.ms0 * m0[(long)yb * a.nx + x];
+        if (a.nsub == 2) im += a.ms1 * m1[(long)yb * a.nx + x];
+      }
+    }
+    v[n1] = cmk<T>(re, im);
+  }
+  fs_step1<T, L1, L2, false>(v, line, a.tw4, t);
+  __syncthreads();
+  V u[L1 / L2][L2];
+  fs_step3<T, L1, L2, false>(u, line, t);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < L1 / L2; ++i)
+#pragma unroll
+    for (int k2 = 0; k2 < L2; ++k2) line[t + L2 * i + L1 * k2] = u[i][bitrev<L2>(k2)];
+  __syncthreads();
+  // unpack the two real spectra and store them transposed (y contiguous)
+  V* out = a.S1 + ((long)(c * a.nz + z) * a.Hx) * a.ldy + y0;
+  for (int idx = tid; idx < nl * a.Hx; idx += nthr) {
+    const int qq = idx % nl, kx = idx / nl;
+    const V zk = lds[qq * L + kx];
+    const V zm = lds[qq * L + ((L - kx) & (L - 1))];
+    const T h = T(0.5);
+    V* o = out + (long)kx * a.ldy + 2 * qq;
+    o[0] = cmk<T>(h * (zk.x + zm.x), h * (zk.y - zm.y));
+    o[1] = cmk<T>(h * (zk.y + zm.y), h * (zm.x - zk.x));
+  }
+}
+
+template <typename T, int L1, int L2>
+__global__ __launch_bounds__(256) void k4_fftx_inv(X4Args<T> a) {
+  using V = cpx<T>;
+  if (ctrl_stopped(a.ctrl)) return;
+  constexpr int L = L1 * L2;
+  extern __shared__ char smem_raw[];
+  V* lds = reinterpret_cast<V*>(smem_raw);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int t = tid % L2, q = tid / L2;
+  const int c = blockIdx.z, z = blockIdx.y, y0 = blockIdx.x * a.ty;
+  const int nl = a.ty >> 1;
+  const V* in = a.S1 + ((long)(c * a.nz + z) * a.Hx) * a.ldy + y0;
+  for (int idx = tid; idx < nl * a.Hx; idx += nthr) {
+    const int qq = idx % nl, kx = idx / nl;
+    const V* ip = in + (long)kx * a.ldy + 2 * qq;
+    const V xa = ip[0], xb = ip[1];
+    lds[qq * L + kx] = cmk<T>(xa.x - xb.y, xa.y + xb.x);
+    if (kx > 0 && 2 * kx < L) lds[qq * L + L - kx] = cmk<T>(xa.x + xb.y, xb.x - xa.y);
+  }
+  __syncthreads();
+  V* line = lds + q * L;
+  V v[L1];
+#pragma unroll
+  for (int n1 = 0; n1 < L1; ++n1) v[n1] = line[L2 * n1 + t];
+  __syncthreads();
+  fs_step1<T, L1, L2, true>(v, line, a.tw4, t);
+  __syncthreads();
+  V u[L1 / L2][L2];
+  fs_step3<T, L1, L2, true>(u, line, t);
+  const long N = (long)a.nx * a.ny * a.nz;
+  T* out = a.Bd + (long)c * N + (long)z * a.ny * a.nx;
+  const int ya = y0 + 2 * q;
+#pragma unroll
+  for (int i = 0; i < L1 / L2; ++i)
+#pragma unroll
+    for (int k2 = 0; k2 < L2; ++k2) {
+      const int x = t + L2 * i + L1 * k2;
+      if (x < a.nx) {
+        const cpx<T> r = u[i][bitrev<L2>(k2)];
+        if (ya < a.ny) out[(long)ya * a.nx + x] = r.x;
+        if (ya + 1 < a.ny) out[(long)(ya + 1) * a.nx + x] = r.y;
+      }
+    }
+}
+
+// row c of the symmetric kernel applied to (Mx, My, Mz)
+template <typename T>
+__device__ __forceinline__ cpx<T> krow(int c, cpx<T> mx, cpx<T> my, cpx<T> mz,
+                                       const T* __restrict__ K, long kidx, long ks, T sy, T sz,
+                                       bool three_d) {
+  T k0, k1, k2;
+  if (c == 0) {
+    k0 = K[kidx];
+    k1 = sy * K[kidx + 3 * ks];
+    k2 = three_d ? sz * K[kidx + 4 * ks] : T(0);
+  } else if (c == 1) {
+    k0 = sy * K[kidx + 3 * ks];
+    k1 = K[kidx + ks];
+    k2 = three_d ? sy * sz * K[kidx + 5 * ks] : T(0);
+  } else {
+    k0 = three_d ? sz * K[kidx + 4 * ks] : T(0);
+    k1 = three_d ? sy * sz * K[kidx + 5 * ks] : T(0);
+    k2 = K[kidx + 2 * ks];
+  }
+  return cmk<T>(k0 * mx.x + k1 * my.x + k2 * mz.x, k0 * mx.y + k1 * my.y + k2 * mz.y);
+}
+
+// ---------------------------------------------- 2-D fused y + multiply --
+template <typename T, int L1, int L2>
+__global__ __launch_bounds__(256) void k4_ffty_mul2d(M4Args<T> a) {
+  using V = cpx<T>;
+  if (ctrl_stopped(a.ctrl)) return;
+  constexpr int L = L1 * L2;
+  extern __shared__ char smem_raw[];
+  V* lds = reinterpret_cast<V*>(smem_raw);
+  const int t = threadIdx.x % L2, ln = threadIdx.x / L2;
+  const int c = ln / a.nk, j = ln - c * a.nk;
+  const int kx = blockIdx.x * a.nk + j;
+  const bool valid = kx < a.Hx;
+  V* line = lds + ln * L;
+  V* io = a.S1 + ((long)c * a.Hx + kx) * a.ldy;
+  V v[L1];
+#pragma unroll
+  for (int n1 = 0; n1 < L1; ++n1) {
+    const int y = L2 * n1 + t;
+    v[n1] = (valid && y < a.ny) ? io[y] : cmk<T>(0, 0);
+  }
+  fs_step1<T, L1, L2, false>(v, line, a.tw4, t);
+  __syncthreads();
+  V u[L1 / L2][L2];
+  fs_step3<T, L1, L2, false>(u, line, t);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < L1 / L2; ++i)
+#pragma unroll
+    for (int k2 = 0; k2 < L2; ++k2) line[t + L2 * i + L1 * k2] = u[i][bitrev<L2>(k2)];
+  __syncthreads();
+  // inverse step 1 loads B_c = sum_j K_cj M_j at ky = L2 n1 + t
+  const V* lx = lds + (0 * a.nk + j) * L;
+  const V* ly = lds + (1 * a.nk + j) * L;
+  const V* lz = lds + (2 * a.nk + j) * L;
+  const long ks = (long)a.Hx * a.Hy;
+#pragma unroll
+  for (int n1 = 0; n1 < L1; ++n1) {
+    const int ky = L2 * n1 + t;
+    const int kyo = ky <= L / 2 ? ky : L - ky;
+    const T sy = ky <= L / 2 ? T(1) : T(-1);
+    v[n1] = valid ? krow<T>(c, lx[ky], ly[ky], lz[ky], a.K, (long)kx * a.Hy + kyo, ks, sy, T(1),
+                            false)
+                  : cmk<T>(0, 0);
+  }
+  __syncthreads();
+  fs_step1<T, L1, L2, true>(v, line, a.tw4, t);
+  __syncthreads();
+  fs_step3<T, L1, L2, true>(u, line, t);
+  if (valid) {
+#pragma unroll
+    for (int i = 0; i < L1 / L2; ++i)
+#pragma unroll
+      for (int k2 = 0; k2 < L2; ++k2) {
+        const int y = t + L2 * i + L1 * k2;
+        if (y < a.ny) io[y] = u[i][bitrev<L2>(k2)];
+      }
+  }
+}
+
+// ------------------------------------------ 3-D z columns + multiply ----
+template <typename T, int PZ>
+__global__ __launch_bounds__(256) void k4_fftz_mul(Z4Args<T> a) {
+  using V = cpx<T>;
+  if (ctrl_stopped(a.ctrl)) return;
+  extern __shared__ char smem_raw[];
+  V* lds = reinterpret_cast<V*>(smem_raw);
+  const int c = threadIdx.x / a.tk, j = threadIdx.x - c * a.tk;
+  const int kx = blockIdx.y, ky = blockIdx.x * a.tk + j;
+  const bool valid = ky < a.Py;
+  const long zs = (long)a.Hx * a.Py;
+  V* col = a.S2 + ((long)c * a.nz * a.Hx + kx) * a.Py + ky;
+  V v[PZ];
+#pragma unroll
+  for (int z = 0; z < PZ; ++z) v[z] = (valid && z < a.nz) ? col[z * zs] : cmk<T>(0, 0);
+  reg_fft<T, PZ, false>(v);
+#pragma unroll
+  for (int kz = 0; kz < PZ; ++kz) lds[(c * PZ + kz) * a.tk + j] = v[bitrev<PZ>(kz)];
+  __syncthreads();
+  const int kyo = ky <= a.Py / 2 ? ky : a.Py - ky;
+  const T sy = ky <= a.Py / 2 ? T(1) : T(-1);
+  const long ks = (long)a.Hz * a.Hx * a.Hy;
+#pragma unroll
+  for (int kz = 0; kz < PZ; ++kz) {
+    const int kzo = kz <= PZ / 2 ? kz : PZ - kz;
+    const T sz = kz <= PZ / 2 ? T(1) : T(-1);
+    const V mx = lds[(0 * PZ + kz) * a.tk + j];
+    const V my = lds[(1 * PZ + kz) * a.tk + j];
+    const V mz = lds[(2 * PZ + kz) * a.tk + j];
+    v[kz] = valid ? krow<T>(c, mx, my, mz, a.K, ((long)kzo * a.Hx + kx) * a.Hy + kyo, ks, sy, sz,
+                            true)
+                  : cmk<T>(0, 0);
+  }
+  reg_fft<T, PZ, true>(v);
+  if (valid) {
+#pragma unroll
+    for (int z = 0; z < PZ; ++z)
+      if (z < a.nz) col[z * zs] = v[bitrev<PZ>(z)];
+  }
+}
+
+// ------------------------------------------------------------ dispatch --
+#define MMP_L_CASES(X) \
+  X(1) X(2) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
+
+template <typename T, int L>
+static void ly(bool inv, dim3 g, int thr, size_t lds, hipStream_t st, const Y4Args<T>& a) {
+  constexpr int L1 = Split<L>::L1, L2 = Split<L>::L2;
+  if (inv) hipLaunchKernelGGL((k4_ffty<T, L1, L2, true>), g, dim3(thr), lds, st, a);
+  else hipLaunchKernelGGL((k4_ffty<T, L1, L2, false>), g, dim3(thr), lds, st, a);
+}
+
+template <typename T>
+void launch_y4(int L, bool inv, dim3 g, int thr, size_t lds, hipStream_t st,
+               const Y4Args<T>& a) {
+  switch (L) {
+#define X(n) case n: ly<T, n>(inv, g, thr, lds, st, a); break;
+    MMP_L_CASES(X)
+#undef X
+  }
+}
+
+template <typename T, int L>
+static void lx(bool inv, dim3 g, int thr, size_t lds, hipStream_t st, const X4Args<T>& a) {
+  constexpr int L1 = Split<L>::L1, L2 = Split<L>::L2;
+  if (inv) hipLaunchKernelGGL((k4_fftx_inv<T, L1, L2>), g, dim3(thr), lds, st, a);
+  else hipLaunchKernelGGL((k4_fftx_fwd<T, L1, L2>), g, dim3(thr), lds, st, a);
+}
+
+template <typename T>
+void launch_x4(int L, bool inv, dim3 g, int thr, size_t lds, hipStream_t st,
+               const X4Args<T>& a) {
+  switch (L) {
+#define X(n) case n: lx<T, n>(inv, g, thr, lds, st, a); break;
+    MMP_L_CASES(X)
+#undef X
+  }
+}
+
+template <typename T, int L>
+static void lm(dim3 g, int thr, size_t lds, hipStream_t st, const M4Args<T>& a) {
+  constexpr int L1 = Split<L>::L1, L2 = Split<L>::L2;
+  hipLaunchKernelGGL((k4_ffty_mul2d<T, L1, L2>), g, dim3(thr), lds, st, a);
+}
+
+template <typename T>
+void launch_m4(int L, dim3 g, int thr, size_t lds, hipStream_t st, const M4Args<T>& a) {
+  switch (L) {
+#define X(n) case n: lm<T, n>(g, thr, lds, st, a); break;
+    MMP_L_CASES(X)
+#undef X
+  }
+}
+
+template <typename T>
+void launch_z4(int PZ, dim3 g, int thr, size_t lds, hipStream_t st, const Z4Args<T>& a) {
+  switch (PZ) {
+    case 2: hipLaunchKernelGGL((k4_fftz_mul<T, 2>), g, dim3(thr), lds, st, a); break;
+    case 4: hipLaunchKernelGGL((k4_fftz_mul<T, 4>), g, dim3(thr), lds, st, a); break;
+    case 8: hipLaunchKernelGGL((k4_fftz_mul<T, 8>), g, dim3(thr), lds, st, a); break;
+    case 16: hipLaunchKernelGGL((k4_fftz_mul<T, 16>), g, dim3(thr), lds, st, a); break;
+    case 32: hipLaunchKernelGGL((k4_fftz_mul<T, 32>), g, dim3(thr), lds, st, a); break;
+  }
+}
+
+#define INST(T)                                                                              \
+  template void launch_y4<T>(int, bool, dim3, int, size_t, hipStream_t, const Y4Args<T>&);  \
+  template void launch_x4<T>(int, bool, dim3, int, size_t, hipStream_t, const X4Args<T>&);  \
+  template void launch_m4<T>(int, dim3, int, size_t, hipStream_t, const M4Args<T>&);        \
+  template void launch_z4<T>(int, dim3, int, size_t, hipStream_t, const Z4Args<T>&);
+INST(float)
+INST(double)
+
+}  // namespace mmp

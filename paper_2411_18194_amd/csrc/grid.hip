@@ -116,9 +116,10 @@ struct Grid final : GridBase {
       rc |= S1.alloc(plan.s1_elems);
       rc |= S2.alloc(plan.s2_elems);
       rc |= K.alloc(plan.k_elems);
-      rc |= tw.alloc((size_t)plan.Px + plan.Py + plan.Pz);
+      rc |= tw.alloc((size_t)2 * (plan.Px + plan.Py) + plan.Pz);
       db.S1 = S1.p; db.S2 = S2.p; db.K = K.p; db.Bd = Bd.p;
       db.twx = tw.p; db.twy = tw.p + plan.Px; db.twz = tw.p + plan.Px + plan.Py;
+      db.tw4x = db.twz + plan.Pz; db.tw4y = db.tw4x + plan.Px;
     }
     if (rc) {
       set_error("device allocation failed");
@@ -217,6 +218,8 @@ struct Grid final : GridBase {
       build_twiddles<T>(db.twx, plan.Px, stream);
       build_twiddles<T>(db.twy, plan.Py, stream);
       build_twiddles<T>(db.twz, plan.Pz, stream);
+      build_twiddles4<T>(db.tw4x, plan.Px, stream);
+      build_twiddles4<T>(db.tw4y, plan.Py, stream);
       const int rc = demag_kernel_build<T>(plan, d[0], d[1], d[2], n6, db.K, stream);
       (void)hipFree(n6);
       if (rc) {

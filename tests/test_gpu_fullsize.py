@@ -1,0 +1,107 @@
+"""Full-size checks on the 512x512x16 film (the benchmark workload).
+
+The oracle cannot evaluate the 4.2M-cell convolution in a test, so at full
+size the GPU path is checked against what holds at any size:
+* the FP64 tensor at sampled offsets of every regime equals the oracle's;
+* a uniformly magnetised prism along x, y, z has demag energy
+  1/2 mu0 Ms^2 V_prism N_prism, N_prism the analytic self-term of the whole
+  1024 x 1024 x 32 nm prism; the error is stated in units of
+  1/2 mu0 Ms^2 V_prism (the three components sum to one, and the small
+  in-plane ones would otherwise magnify it): FP64 <= 1e-12, FP32 <= 2e-6.
+  (The 4th-moment far field is itself accurate to ~2e-11 per entry at its
+  cutoff, which bounds the agreement with the exact prism value);
+* FP32 and FP64 effective fields of the seeded initial state agree to 2e-6
+  (max-norm relative, the parity norm), and a fixed-step FP32 trajectory of
+  the benchmark stays within 1e-4 of the FP64 one.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import tensor as OT
+from oracle.constants import MU0
+from paper_2411_18194_amd import inputs, mmp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return inputs.config_c2()
+
+
+def relerr(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def test_tensor_samples_fullsize(c2):
+    p, _ = c2
+    g = mmp.Grid(p, mmp.FP64)
+    n6 = g.demag_tensor()
+    g.close()
+    rng = np.random.default_rng(5)
+    nx, ny, nz = p["n"]
+    pts = [(0, 0, 0), (1, 0, 0), (2, 1, 1), (5, 3, 2), (20, 30, 7), (39, 2, 15),
+           (40, 0, 0), (100, 50, 3), (511, 511, 15), (300, 7, 0)]
+    pts += [tuple(int(v) for v in rng.integers(0, (nx, ny, nz))) for _ in range(40)]
+    d = p["cell"]
+    X = np.array([q[0] for q in pts]) * d[0]
+    Y = np.array([q[1] for q in pts]) * d[1]
+    Z = np.array([q[2] for q in pts]) * d[2]
+    ref = OT.tensor_at(X, Y, Z, d)
+    got = np.stack([n6[:, q[2], q[1], q[0]] for q in pts], axis=1)
+    assert np.abs(got - ref).max() < 2e-14
+
+
+@pytest.mark.parametrize("prec,tol", [(mmp.FP64, 1e-12), (mmp.FP32, 2e-6)])
+def test_uniform_prism_energy_fullsize(c2, prec, tol):
+    p, _ = c2
+    nx, ny, nz = p["n"]
+    d = p["cell"]
+    q = dict(p)
+    q.update(Ku1=[0.0], Dint=[0.0], B_ext=(0.0, 0.0, 0.0), A11=[0.0])
+    g = mmp.Grid(q, prec)
+    big = OT.newell_tensor(0, 0, 0, (nx * d[0], ny * d[1], nz * d[2])).ravel()
+    Ms = q["Ms"][0]
+    V = nx * ny * nz * d[0] * d[1] * d[2]
+    for axis in range(3):
+        m = np.zeros((1, 3, nz, ny, nx))
+        m[0, axis] = 1.0
+        g.set_state(m)
+        _, e = g.eval_heff(mmp.T_DEMAG, want_b=False)
+        unit = 0.5 * MU0 * Ms * Ms * V
+        ref = unit * big[axis]
+        assert abs(e["demag"] - ref) <= tol * unit, (axis, e["demag"], ref)
+    g.close()
+
+
+def test_fp32_vs_fp64_field_fullsize(c2):
+    p, m0 = c2
+    g64 = mmp.Grid(p, mmp.FP64)
+    g64.set_state(m0)
+    b64, e64 = g64.eval_heff(mmp.T_ALL)
+    d64, _ = g64.eval_heff(mmp.T_DEMAG)
+    g64.close()
+    g32 = mmp.Grid(p, mmp.FP32)
+    g32.set_state(np.asarray(m0, dtype=np.float32).astype(np.float64))
+    b32, e32 = g32.eval_heff(mmp.T_ALL)
+    d32, _ = g32.eval_heff(mmp.T_DEMAG)
+    g32.close()
+    assert relerr(d32, d64) <= 2e-6
+    assert relerr(b32, b64) <= 2e-6
+
+
+def test_fp32_trajectory_fullsize(c2):
+    """200 benchmark steps (12 ps) in FP32 vs FP64: max |dm| <= 1e-4."""
+    p, m0 = c2
+    dt = inputs.c2_fixed_dt()
+    out = []
+    for prec in (mmp.FP64, mmp.FP32):
+        g = mmp.Grid(p, prec)
+        g.set_state(m0)
+        g.run_fixed(dt, 200)
+        out.append(g.get_state()[0])
+        g.close()
+    assert np.abs(out[0] - out[1]).max() <= 1e-4
+    assert np.abs(np.linalg.norm(out[1], axis=1) - 1).max() < 1e-6

@@ -64,6 +64,26 @@ def _tiny(n):
     return p, inputs.random_unit(inputs.rng(sum(n)), 1, n)
 
 
+def _pow2_3d():
+    p = inputs.base_params((32, 32, 16), (2e-9, 2e-9, 2e-9))
+    p.update(Ms=[1.1e6], A11=[1.5e-11], alpha=[0.1], Ku1=[5e5], anis_u=[(0, 0, 1)],
+             Dint=[3e-3], dmi_layer=0, B_ext=(0.0, 0.0, 0.05), demag=True)
+    return p, inputs.smoothed_random_unit(inputs.rng(21), 1, p["n"])
+
+
+def _pow2_2d():
+    p = inputs.base_params((256, 64, 1), (3e-9, 3e-9, 2e-9))
+    p.update(Ms=[8e5], A11=[1.3e-11], alpha=[0.02], B_ext=(-0.02, 0.004, 0.0), demag=True)
+    return p, inputs.smoothed_random_unit(inputs.rng(22), 1, p["n"])
+
+
+def _pow2_afm():
+    p = inputs.base_params((16, 8, 4), (1e-9, 1e-9, 1e-9), nsub=2)
+    p.update(Ms=[4e5, 3.5e5], A11=[1e-11, 1e-11], alpha=[0.01, 0.01], A0=-2.5e-11,
+             A12=-5e-12, latcon=0.35e-9, Ku1=[6e4, 6e4], demag=True)
+    return p, inputs.random_unit(inputs.rng(23), 2, p["n"])
+
+
 CASES = {
     "c1": lambda: inputs.config_c1(),
     "c2crop": lambda: inputs.config_c2_crop(),
@@ -74,6 +94,10 @@ CASES = {
     "tiny111": lambda: _tiny((1, 1, 1)),
     "tiny213": lambda: _tiny((2, 1, 3)),
     "tiny171": lambda: _tiny((1, 7, 1)),
+    "tiny2x2": lambda: _tiny((2, 2, 2)),
+    "pow2_3d": _pow2_3d,
+    "pow2_2d": _pow2_2d,
+    "pow2_afm": _pow2_afm,
 }
 
 _oracles = {}
