@@ -352,7 +352,9 @@ int demag_plan(int nx, int ny, int nz, int real_bytes, DemagPlan* p) {
   const int lmax = real_bytes == 8 ? 2048 : 4096;
   d.p2x = is_pow2(d.Px) && d.Px <= lmax;
   d.p2y = is_pow2(d.Py) && d.Py <= lmax;
-  d.p2z = is_pow2(d.Pz) && d.Pz <= 32;
+  // the register z pass holds three columns per thread: up to 32 points in
+  // FP32, 16 in FP64
+  d.p2z = is_pow2(d.Pz) && d.Pz <= (real_bytes == 8 ? 16 : 32);
   {
     const int l2 = split_l2(d.Py);
     int n = 1;
@@ -361,14 +363,13 @@ int demag_plan(int nx, int ny, int nz, int real_bytes, DemagPlan* p) {
     int k = 1;
     while (k < 64 && (long)3 * (2 * k) * d.Py <= cap && 3 * (2 * k) * l2 <= 256) k *= 2;
     d.nk4 = k;
-    int tk4 = 1;
-    while (tk4 < 64 && (long)3 * d.Pz * (2 * tk4) <= cap && 3 * (2 * tk4) <= 256) tk4 *= 2;
-    d.tk4 = tk4;
+    // z pass: threads (ky columns) per block
+    d.tk4 = real_bytes == 8 ? 64 : 128;
     // the x rows per block also bound the four-step block to 256 threads
     if (d.p2x)
       while ((d.ty / 2) * split_l2(d.Px) > 256) d.ty /= 2;
     d.ldy = round_up(ny, d.ty);
-    if (3 * d.nk4 * l2 > 256 || d.nly4 * l2 > 256 || 3 * d.tk4 > 256) return -1;
+    if (3 * d.nk4 * l2 > 256 || d.nly4 * l2 > 256 || d.tk4 > 256) return -1;
   }
   d.s1_elems = (size_t)3 * nz * d.Hx * d.ldy;
   d.s2_elems = nz > 1 ? (size_t)3 * nz * d.Hx * d.Py : 0;
@@ -441,8 +442,10 @@ void demag_field(const DemagPlan& p, const DemagBufs<T>& b, const Table<T>* tbl,
         Z4Args<T> z4;
         z4.ctrl = ctrl; z4.S2 = b.S2; z4.K = b.K;
         z4.nz = p.nz; z4.Hx = p.Hx; z4.Py = p.Py; z4.Hy = p.Hy; z4.Hz = p.Hz; z4.tk = p.tk4;
-        launch_z4<T>(p.Pz, dim3((p.Py + p.tk4 - 1) / p.tk4, p.Hx), 3 * p.tk4,
-                     (size_t)3 * p.Pz * p.tk4 * sizeof(V), st, z4);
+        const int zthr = p.tk4;
+        const int nblk = ((p.Py + zthr - 1) / zthr) * p.Hx;
+        z4.nb_pad = round_up(nblk, 8);
+        launch_z4<T>(p.Pz, dim3(z4.nb_pad), zthr, 0, st, z4);
       } else {
         ZArgs<T> za;
         za.ctrl = ctrl; za.S2 = b.S2; za.K = b.K; za.tw = b.twz;

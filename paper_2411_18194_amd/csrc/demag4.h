@@ -42,7 +42,7 @@ struct Z4Args {
   const Ctrl* ctrl;
   cpx<T>* S2;
   const T* K;
-  int nz, Hx, Py, Hy, Hz, tk;
+  int nz, Hx, Py, Hy, Hz, tk, nb_pad;
 };
 
 template <typename T>

@@ -34,11 +34,14 @@ void build_twiddles4(cpx<T>* tw, int L, hipStream_t st) {
 template void build_twiddles4<float>(cpx<float>*, int, hipStream_t);
 template void build_twiddles4<double>(cpx<double>*, int, hipStream_t);
 
-// step 1: L1-point register FFT, inter-step twiddle, swizzled LDS row store
-template <typename T, int L1, int L2, bool INV>
+// step 1: L1-point register FFT, inter-step twiddle, swizzled LDS row store.
+// HZ: the line is zero-padded to at least twice its data (every pow-2 pad
+// P >= 2n - 1 is even, so P >= 2n), so v[L1/2 ..) is zero and not read.
+template <typename T, int L1, int L2, bool INV, bool HZ = false>
 __device__ __forceinline__ void fs_step1(cpx<T>* v, cpx<T>* line, const cpx<T>* __restrict__ tw4,
                                          int t) {
-  reg_fft<T, L1, INV>(v);
+  if constexpr (HZ && L1 >= 2) reg_fft_hz<T, L1, INV>(v);
+  else reg_fft<T, L1, INV>(v);
 #pragma unroll
   for (int k1 = 0; k1 < L1; ++k1) {
     cpx<T> x = v[bitrev<L1>(k1)];
@@ -78,12 +81,13 @@ __global__ __launch_bounds__(256) void k4_ffty(Y4Args<T> a) {
   V* line = lds + q * L;
   const V* in = a.in + (long)gl * a.ld_in;
   V v[L1];
+  constexpr int NLOAD = (!INV && L1 >= 2) ? L1 / 2 : L1;
 #pragma unroll
-  for (int n1 = 0; n1 < L1; ++n1) {
+  for (int n1 = 0; n1 < NLOAD; ++n1) {
     const int idx = L2 * n1 + t;
     v[n1] = (valid && idx < a.nvalid_in) ? in[idx] : cmk<T>(0, 0);
   }
-  fs_step1<T, L1, L2, INV>(v, line, a.tw4, t);
+  fs_step1<T, L1, L2, INV, !INV>(v, line, a.tw4, t);
   __syncthreads();
   V u[L1 / L2][L2];
   fs_step3<T, L1, L2, INV>(u, line, t);
@@ -118,8 +122,9 @@ __global__ __launch_bounds__(256) void k4_fftx_fwd(X4Args<T> a) {
   const int ya = y0 + 2 * q, yb = ya + 1;
   V* line = lds + q * L;
   V v[L1];
+  constexpr int NLOAD = L1 >= 2 ? L1 / 2 : L1;
 #pragma unroll
-  for (int n1 = 0; n1 < L1; ++n1) {
+  for (int n1 = 0; n1 < NLOAD; ++n1) {
     const int x = L2 * n1 + t;
     T re = 0, im = 0;
     if (x < a.nx) {
@@ -134,7 +139,7 @@ __global__ __launch_bounds__(256) void k4_fftx_fwd(X4Args<T> a) {
     }
     v[n1] = cmk<T>(re, im);
   }
-  fs_step1<T, L1, L2, false>(v, line, a.tw4, t);
+  fs_step1<T, L1, L2, false, true>(v, line, a.tw4, t);
   __syncthreads();
   V u[L1 / L2][L2];
   fs_step3<T, L1, L2, false>(u, line, t);
@@ -239,12 +244,13 @@ __global__ __launch_bounds__(256) void k4_ffty_mul2d(M4Args<T> a) {
   V* line = lds + ln * L;
   V* io = a.S1 + ((long)c * a.Hx + kx) * a.ldy;
   V v[L1];
+  constexpr int NLOAD = L1 >= 2 ? L1 / 2 : L1;
 #pragma unroll
-  for (int n1 = 0; n1 < L1; ++n1) {
+  for (int n1 = 0; n1 < NLOAD; ++n1) {
     const int y = L2 * n1 + t;
     v[n1] = (valid && y < a.ny) ? io[y] : cmk<T>(0, 0);
   }
-  fs_step1<T, L1, L2, false>(v, line, a.tw4, t);
+  fs_step1<T, L1, L2, false, true>(v, line, a.tw4, t);
   __syncthreads();
   V u[L1 / L2][L2];
   fs_step3<T, L1, L2, false>(u, line, t);
@@ -284,44 +290,74 @@ __global__ __launch_bounds__(256) void k4_ffty_mul2d(M4Args<T> a) {
 }
 
 // ------------------------------------------ 3-D z columns + multiply ----
+// One thread carries the three components of one (kx, ky) column through
+// forward FFT, kernel multiply and inverse FFT in registers: no LDS and no
+// barriers, so the pass streams like a copy.  Blocks are ordered so that all
+// ky tiles of one kx run back to back on one XCD, which keeps that kx slice
+// of the kernel (read for ky and its mirror Py - ky) in the XCD's L2.
 template <typename T, int PZ>
 __global__ __launch_bounds__(256) void k4_fftz_mul(Z4Args<T> a) {
   using V = cpx<T>;
   if (ctrl_stopped(a.ctrl)) return;
-  extern __shared__ char smem_raw[];
-  V* lds = reinterpret_cast<V*>(smem_raw);
-  const int c = threadIdx.x / a.tk, j = threadIdx.x - c * a.tk;
-  const int kx = blockIdx.y, ky = blockIdx.x * a.tk + j;
-  const bool valid = ky < a.Py;
+  const int ntile = (a.Py + blockDim.x - 1) / blockDim.x;
+  const int w = xcd_remap(blockIdx.x, a.nb_pad);
+  if (w >= ntile * a.Hx) return;
+  const int kx = w / ntile, ky = (w - kx * ntile) * blockDim.x + threadIdx.x;
+  if (ky >= a.Py) return;
   const long zs = (long)a.Hx * a.Py;
-  V* col = a.S2 + ((long)c * a.nz * a.Hx + kx) * a.Py + ky;
-  V v[PZ];
+  const long cs = (long)a.nz * zs;
+  V* col = a.S2 + (long)kx * a.Py + ky;
+  V vx[PZ], vy[PZ], vz[PZ];
+  // nz <= PZ/2 for every power-of-two pad, so the upper halves are zero
 #pragma unroll
-  for (int z = 0; z < PZ; ++z) v[z] = (valid && z < a.nz) ? col[z * zs] : cmk<T>(0, 0);
-  reg_fft<T, PZ, false>(v);
-#pragma unroll
-  for (int kz = 0; kz < PZ; ++kz) lds[(c * PZ + kz) * a.tk + j] = v[bitrev<PZ>(kz)];
-  __syncthreads();
+  for (int z = 0; z < PZ / 2; ++z) {
+    const bool in = z < a.nz;
+    vx[z] = in ? col[z * zs] : cmk<T>(0, 0);
+    vy[z] = in ? col[cs + z * zs] : cmk<T>(0, 0);
+    vz[z] = in ? col[2 * cs + z * zs] : cmk<T>(0, 0);
+  }
+  reg_fft_hz<T, PZ, false>(vx);
+  reg_fft_hz<T, PZ, false>(vy);
+  reg_fft_hz<T, PZ, false>(vz);
   const int kyo = ky <= a.Py / 2 ? ky : a.Py - ky;
   const T sy = ky <= a.Py / 2 ? T(1) : T(-1);
   const long ks = (long)a.Hz * a.Hx * a.Hy;
+  const T* K = a.K + (long)kx * a.Hy + kyo;
+  const long kzs = (long)a.Hx * a.Hy;
+  // B(kz) = K(kz) M(kz); spectra sit at bit-reversed register positions
 #pragma unroll
   for (int kz = 0; kz < PZ; ++kz) {
     const int kzo = kz <= PZ / 2 ? kz : PZ - kz;
     const T sz = kz <= PZ / 2 ? T(1) : T(-1);
-    const V mx = lds[(0 * PZ + kz) * a.tk + j];
-    const V my = lds[(1 * PZ + kz) * a.tk + j];
-    const V mz = lds[(2 * PZ + kz) * a.tk + j];
-    v[kz] = valid ? krow<T>(c, mx, my, mz, a.K, ((long)kzo * a.Hx + kx) * a.Hy + kyo, ks, sy, sz,
-                            true)
-                  : cmk<T>(0, 0);
+    const T* kr = K + kzo * kzs;
+    const T kxx = kr[0], kyy = kr[ks], kzz = kr[2 * ks];
+    const T kxy = sy * kr[3 * ks], kxz = sz * kr[4 * ks], kyz = sy * sz * kr[5 * ks];
+    const int r = bitrev<PZ>(kz);
+    const V mx = vx[r], my = vy[r], mz = vz[r];
+    vx[r] = cmk<T>(kxx * mx.x + kxy * my.x + kxz * mz.x, kxx * mx.y + kxy * my.y + kxz * mz.y);
+    vy[r] = cmk<T>(kxy * mx.x + kyy * my.x + kyz * mz.x, kxy * mx.y + kyy * my.y + kyz * mz.y);
+    vz[r] = cmk<T>(kxz * mx.x + kyz * my.x + kzz * mz.x, kxz * mx.y + kyz * my.y + kzz * mz.y);
   }
-  reg_fft<T, PZ, true>(v);
-  if (valid) {
+  // the inverse transform reads natural order: undo the bit reversal
+  V t[PZ];
 #pragma unroll
-    for (int z = 0; z < PZ; ++z)
-      if (z < a.nz) col[z * zs] = v[bitrev<PZ>(z)];
-  }
+  for (int k = 0; k < PZ; ++k) t[k] = vx[bitrev<PZ>(k)];
+  reg_fft<T, PZ, true>(t);
+#pragma unroll
+  for (int z = 0; z < PZ / 2; ++z)
+    if (z < a.nz) col[z * zs] = t[bitrev<PZ>(z)];
+#pragma unroll
+  for (int k = 0; k < PZ; ++k) t[k] = vy[bitrev<PZ>(k)];
+  reg_fft<T, PZ, true>(t);
+#pragma unroll
+  for (int z = 0; z < PZ / 2; ++z)
+    if (z < a.nz) col[cs + z * zs] = t[bitrev<PZ>(z)];
+#pragma unroll
+  for (int k = 0; k < PZ; ++k) t[k] = vz[bitrev<PZ>(k)];
+  reg_fft<T, PZ, true>(t);
+#pragma unroll
+  for (int z = 0; z < PZ / 2; ++z)
+    if (z < a.nz) col[2 * cs + z * zs] = t[bitrev<PZ>(z)];
 }
 
 // ------------------------------------------------------------ dispatch --

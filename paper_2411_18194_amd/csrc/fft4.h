@@ -164,6 +164,24 @@ __device__ __forceinline__ void dif_levels(cpx<T>* v) {
   }
 }
 
+template <typename T, int N, bool INV, int I>
+__device__ __forceinline__ void dif_first_halfzero(cpx<T>* v) {
+  if constexpr (I < N / 2) {
+    v[I + N / 2] = twiddle_c<T, I, N, INV>(v[I]);
+    dif_first_halfzero<T, N, INV, I + 1>(v);
+  }
+}
+
+// As reg_fft, for an input whose upper half v[N/2 .. N) is zero (it is not
+// read): a zero-padded line whose pad is at least as long as its data.
+template <typename T, int N, bool INV>
+__device__ __forceinline__ void reg_fft_hz(cpx<T>* v) {
+  if constexpr (N > 1) {
+    dif_first_halfzero<T, N, INV, 0>(v);
+    dif_levels<T, N, N / 4, INV>(v);
+  }
+}
+
 // In-register N-point FFT in place (N power of two <= 64): on return the
 // transform value X[k] sits in v[bitrev<N>(k)].  Only a couple of complex
 // temporaries are live besides v.
