@@ -14,8 +14,12 @@ HBM traffic the rocprofv3 counters measured for that kernel (when the
 committed counter summary matches the current kernel source), and the FP64
 CPU oracle timed on a bounded sample of the same workload.
 
+Before the warm-up the demag plan is autotuned (candidate pads and launch
+shapes timed on the device, the fastest installed), as a caller would do
+once per shape; --no-autotune keeps the default plan.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-fp64]
-       [--no-cpu-baseline] [--profile-steps K]
+       [--no-cpu-baseline] [--no-prof] [--no-autotune]
 """
 from __future__ import annotations
 
@@ -34,8 +38,8 @@ sys.path.insert(0, ROOT)
 METRIC = ("cell-field-evals/s 512x512x16 FP32 vs FP64; batched solves/s with p50/p99 "
           "latency")
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ("paper_2411_18194_amd/csrc/demag.hip", "paper_2411_18194_amd/csrc/fft_engine.h",
-                  "paper_2411_18194_amd/csrc/field.hip")
+KERNEL_SOURCES = tuple("paper_2411_18194_amd/csrc/" + f for f in (
+    "demag.hip", "demag4.hip", "fft4.h", "fft_engine.h", "field.hip", "field.h", "common.h"))
 COUNTERS = os.path.join(ROOT, "profiles", "counters_c2_fp32.json")
 
 
@@ -54,12 +58,12 @@ def smooth_pad(n):
         p += 1
 
 
-def algorithmic_bytes(n, rb, nsub=1):
+def algorithmic_bytes(n, rb, nsub=1, pads=None):
     """Bytes each kernel class must move per launch (operands read once)."""
     nx, ny, nz = n
     N = nx * ny * nz
     cb = 2 * rb
-    Px, Py, Pz = smooth_pad(nx), smooth_pad(ny), smooth_pad(nz)
+    Px, Py, Pz = pads or (smooth_pad(nx), smooth_pad(ny), smooth_pad(nz))
     Hx, Hy, Hz = Px // 2 + 1, Py // 2 + 1, Pz // 2 + 1
     s1 = cb * 3 * nz * Hx * ny
     out = {"fftx_fwd": rb * nsub * 3 * N + s1, "fftx_inv": s1 + rb * 3 * N}
@@ -88,7 +92,7 @@ def src_hash():
     return h.hexdigest()[:16]
 
 
-def run_gpu(precision, steps, warmup, prof=True):
+def run_gpu(precision, steps, warmup, prof=True, tune=True):
     import torch
 
     from paper_2411_18194_amd import inputs, mmp
@@ -98,6 +102,9 @@ def run_gpu(precision, steps, warmup, prof=True):
     stream = torch.cuda.current_stream()
     g.set_stream(stream.cuda_stream)
     g.set_state(m0)
+    t_tune = time.perf_counter()
+    plan = g.autotune() if tune else g.plan()
+    t_tune = time.perf_counter() - t_tune
     dt = inputs.c2_fixed_dt()
     g.run_fixed(dt, warmup)
     torch.cuda.synchronize()
@@ -118,11 +125,12 @@ def run_gpu(precision, steps, warmup, prof=True):
     N = p["n"][0] * p["n"][1] * p["n"][2]
     sec = t1 - t0
     return dict(value=N * 6 * steps / sec, ms_per_step=1e3 * sec / steps, kernels=kern,
-                finite=finite, norm_err=norm_err, n=p["n"])
+                finite=finite, norm_err=norm_err, n=p["n"], plan=plan,
+                tune_s=t_tune if tune else None)
 
 
 def roofline(res, rb):
-    ab = algorithmic_bytes(res["n"], rb)
+    ab = algorithmic_bytes(res["n"], rb, pads=tuple(res["plan"]["pad"]))
     kern = res["kernels"]
     tot = {k: v[0] for k, v in kern.items() if v[1] > 0}
     dom = max((k for k in tot if k in ab), key=lambda k: tot[k])
@@ -171,6 +179,63 @@ def cpu_baseline():
                       f"element-wise work on 1)", "seconds": round(sec, 2)}
 
 
+def _percentiles(lat):
+    lat = np.sort(np.asarray(lat))
+    return (float(np.percentile(lat, 50)), float(np.percentile(lat, 99)))
+
+
+def _serve_pass(reqs, states, precision, rate_scale, max_active):
+    """Open-loop replay of the request stream through the server.
+
+    Request i is submitted at t_arrive[i] * rate_scale after the start (a
+    scale above 1 slows the arrivals down).  Latency = t_done - t_submit on
+    the server's clock."""
+    from paper_2411_18194_amd import mmp
+
+    srv = mmp.Server(hbm_budget=64 << 30, max_active=max_active, precision=precision)
+    t0 = srv.clock()
+    tickets = []
+    for r, m in zip(reqs, states):
+        while srv.clock() - t0 < r["t_arrive"] * rate_scale:
+            time.sleep(2e-4)
+        tickets.append(srv.submit(r["params"], m, r["t_relax"], tol=r["tol"]))
+    res = [srv.wait(t, timeout=900.0) for t in tickets]
+    srv.close()
+    bad = [x.status for x in res if x.status != 0]
+    if bad:
+        raise RuntimeError(f"serving: {len(bad)} requests failed: {bad[:5]}")
+    lat = [x.t_done - x.t_submit for x in res]
+    span = max(x.t_done for x in res) - min(x.t_submit for x in res)
+    p50, p99 = _percentiles(lat)
+    cells = sum(r["params"]["n"][0] * r["params"]["n"][1] * r["params"]["n"][2] for r in reqs)
+    steps = sum(x.steps + x.rejects for x in res)
+    return {"solves_per_s": len(res) / span, "p50_s": p50, "p99_s": p99, "makespan_s": span,
+            "requests": len(res), "attempts": int(steps), "cells": int(cells)}
+
+
+def run_serve(count, max_active=8):
+    """Relaxation requests (a seeded prefix of the 4000-request stream at
+    200/s: 70 % FM with demag, 30 % two-sublattice AFM, 0.5 ns each) served
+    by the library's server in FP32; then the same requests re-timed with
+    arrivals slowed to 0.8 x the measured capacity."""
+    from paper_2411_18194_amd import inputs, mmp
+
+    reqs = inputs.request_stream(seed=5, count=count)
+    states = [inputs.request_state(r) for r in reqs]
+    full = _serve_pass(reqs, states, mmp.FP32, 1.0, max_active)
+    # arrivals at 0.8 x capacity: scale the stream's mean rate (200/s) down
+    scale = 200.0 / (0.8 * full["solves_per_s"])
+    sus = _serve_pass(reqs, states, mmp.FP32, scale, max_active)
+    return {"workload": f"first {count} requests of the seeded c5 stream (Poisson 200/s, "
+                        "nx, ny log-uniform 32..512, nz log-uniform 1..8, 70 % FM with "
+                        "demag / 30 % AFM, 0.5 ns DP45 relaxation each, tol 1e-5)",
+            "precision": "f32", "max_active": max_active,
+            "offered": {k: round(v, 4) if isinstance(v, float) else v for k, v in full.items()},
+            "at_0.8_capacity": {k: round(v, 4) if isinstance(v, float) else v
+                                for k, v in sus.items()},
+            "arrival_rate_0.8_capacity_per_s": round(200.0 / scale, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,6 +244,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-prof", action="store_true")
+    ap.add_argument("--serve", type=int, default=24,
+                    help="requests in the serving measurement (0 = skip)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default demag plan instead of timing candidates first")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -198,7 +267,8 @@ def main():
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     from paper_2411_18194_amd import mmp
-    r32 = run_gpu(mmp.FP32, args.steps, args.warmup, prof=not args.no_prof)
+    tune = not args.no_autotune
+    r32 = run_gpu(mmp.FP32, args.steps, args.warmup, prof=not args.no_prof, tune=tune)
     out = {
         "metric": METRIC, "value": round(r32["value"], 1), "unit": "cell-field-evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -208,16 +278,21 @@ def main():
                                "DMI (bottom layer) + uniaxial + Zeeman, fixed-step DP45 "
                                "(0.1 ns / 1667)",
                    "cells": 512 * 512 * 16, "field_evals_per_step": 6,
-                   "demag_pad": [1024, 1024, 32]},
+                   "demag_pad": r32["plan"]["pad"]},
         "state_finite": r32["finite"], "max_norm_error": r32["norm_err"],
+        "plan": {k: v for k, v in r32["plan"].items() if k != "demag_ms"},
+        "autotune_s": None if r32["tune_s"] is None else round(r32["tune_s"], 3),
     }
     if not args.no_prof:
         out["roofline"] = roofline(r32, 4)
     if not args.no_fp64:
-        r64 = run_gpu(mmp.FP64, max(3, args.steps // 3), args.warmup, prof=False)
+        r64 = run_gpu(mmp.FP64, max(3, args.steps // 3), args.warmup, prof=False, tune=tune)
         out["fp64"] = {"value": round(r64["value"], 1), "unit": "cell-field-evals/s",
                        "ms_per_step": round(r64["ms_per_step"], 4),
-                       "fp32_speedup": round(r32["value"] / r64["value"], 3)}
+                       "fp32_speedup": round(r32["value"] / r64["value"], 3),
+                       "plan": {k: v for k, v in r64["plan"].items() if k != "demag_ms"}}
+    if args.serve > 0:
+        out["serving"] = run_serve(args.serve)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

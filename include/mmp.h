@@ -195,12 +195,81 @@ mmp_status mmp_run(mmp_grid g, double t_end, const mmp_run_opts* opts,
 mmp_status mmp_set_stream(mmp_grid g, void* hip_stream);
 mmp_status mmp_synchronize(mmp_grid g);
 
+/* HIP graphs for the step loops (default on).  When on, mmp_run_fixed,
+ * mmp_run and the server enqueue the kernels of 8 step attempts as one
+ * captured graph: every kernel reads the step controller and the stage
+ * buffer table from device memory, so one capture serves every replay.
+ * Graphs are not used while profiling (mmp_prof_enable) and are recaptured
+ * after any change of parameters, plan or sample buffers.  Results are
+ * bitwise identical either way. */
+mmp_status mmp_set_graphs(mmp_grid g, int32_t on);
+
 /* Device footprint of the grid in bytes (state, stages, FFT buffers, kernel). */
 mmp_status mmp_grid_bytes(mmp_grid g, int64_t* bytes);
 
 /* FP64 demagnetising tensor on non-negative offsets, 6*N values ordered
  * (xx, yy, zz, xy, xz, yz)[z][y][x] (offset (x dx, y dy, z dz)). */
 mmp_status mmp_get_demag_tensor(mmp_grid g, double* n6);
+
+/* ------------------------------------------------------------- plan -- */
+
+/* Launch plan of a grid.
+ *
+ * Demag part: how the demagnetising convolution (zero-padded FFT
+ * convolution with the cell-averaged tensor, paper Methods "Magnetostatic
+ * field") is laid out and launched.  pad[] are the FFT lengths per axis: 1
+ * for an axis of one cell, else even, 7-smooth, >= 2n-1 and <= 4096.  Any
+ * such pads give the same field up to rounding, because the padding removes
+ * the circular wrap-around.  The launch shapes only regroup the per-line
+ * transforms over blocks and lanes; z_lanes > 1 also refactors the z
+ * transform (same result up to rounding).  Every count is a power of two.
+ * With demag off these fields read 0 and are ignored on input.
+ *
+ * Stencil part: field_zplanes, the cells of an (x, y) column that one
+ * thread of the fused field kernel marches through (1..nz; results are
+ * bitwise independent of it). */
+typedef struct {
+  uint32_t struct_size;
+  int32_t pad[3];         /* Px, Py, Pz                                    */
+  int32_t x_rows[2];      /* rows per block, forward / inverse x pass:
+                             2..16                                         */
+  int32_t y_lines[2];     /* lines per block, forward / inverse y pass:
+                             1..64 (3-D grids)                             */
+  int32_t xy_cols;        /* kx columns per block of the fused y pass of
+                             2-D grids: 1..64                              */
+  int32_t z_cols;         /* ky columns per block, mixed-radix z pass      */
+  int32_t z_lanes;        /* lanes per (kx, ky) column, register z pass
+                             (power-of-two Pz <= 64): 1, 2 or 4            */
+  int32_t z_waves;        /* waves-per-SIMD hint of that pass: 1, 2 or 4   */
+  int32_t z_threads;      /* threads per block of that pass: 64, 128, 256  */
+  int32_t field_zplanes;  /* z cells per thread of the field kernel        */
+  uint32_t kinds;         /* out: bits 0/1/2 set when the x/y/z passes use
+                             the power-of-two register kernels             */
+  int32_t reserved;       /* 0                                             */
+  double demag_ms;        /* out: time of one demag evaluation measured by
+                             mmp_autotune for this plan, 0 if not tuned    */
+  double field_ms;        /* out: time of one field-kernel stage measured
+                             by mmp_autotune, 0 if not tuned               */
+} mmp_plan;
+
+/* The grid's current plan.  MMP_E_STATE before mmp_set_params. */
+mmp_status mmp_get_plan(mmp_grid g, mmp_plan* out);
+/* Install a plan.  MMP_E_ARG if a pad or launch shape is outside the
+ * limits above or the kernels' LDS and block-size limits (the grid keeps
+ * its plan); a change of pads reallocates the FFT buffers and rebuilds the
+ * kernel spectrum.  Output-only fields are ignored.  Synchronous. */
+mmp_status mmp_set_plan(mmp_grid g, const mmp_plan* p);
+/* Autotuner.  For every pad set built from the smallest even 7-smooth pad
+ * and the smallest power-of-two pad of each axis, times the candidate
+ * launch shapes of each demag pass on the grid's stream (HIP events, real
+ * buffers; pad sets that do not fit in free device memory are skipped),
+ * then the field kernel's z march lengths; installs the fastest plan and
+ * keeps it for grids of the same (nx, ny, nz, precision, demag on/off) on
+ * this device that later calls of mmp_set_params set up in this process.
+ * The magnetic state, time and step size are untouched (the timed launches
+ * write only FFT buffers, B_d and stage scratch).  Synchronous; out may be
+ * NULL. */
+mmp_status mmp_autotune(mmp_grid g, mmp_plan* out);
 
 /* Kernel timing with HIP events on the grid's stream.  While enabled every
  * launch of the hot path is bracketed by events; mmp_prof_read returns,

@@ -210,13 +210,21 @@ class Problem:
         """Adaptive DP45 from t0 to t_end; returns (y, t, info, samples).
 
         A step that would pass the next output time (t0 + k*sample_every,
-        or t_end) is shortened to land on it exactly.
+        or t_end) is shortened to land on it exactly.  An output time closer
+        to t_end than 1e-9 of the run length is t_end itself: k*sample_every
+        can fall a few ulp short of t_end, and landing on both would take a
+        step of ~1e-26 s that the step-size floor rejects.
         """
         t = t0
         dt = dt0
         samples = [] if sample is None else [(t, sample(y))]
         k = 1
-        next_out = t0 + sample_every if sample_every else t_end
+
+        def out_time(k):
+            o = t0 + k * sample_every
+            return t_end if o >= t_end - 1e-9 * (t_end - t0) else o
+
+        next_out = out_time(1) if sample_every else t_end
         steps = rejects = 0
         while t < t_end and steps + rejects < max_steps:
             target = min(next_out, t_end)
@@ -233,7 +241,7 @@ class Problem:
                     if sample is not None:
                         samples.append((t, sample(y)))
                     k += 1
-                    next_out = t0 + k * sample_every
+                    next_out = out_time(k)
             else:
                 rejects += 1
             dt = new_dt(h, err, tol)

@@ -252,6 +252,14 @@ mmp_status mmp_set_stream(mmp_grid g, void* s) {
   MMP_GUARD_END
 }
 
+mmp_status mmp_set_graphs(mmp_grid g, int32_t on) {
+  MMP_GUARD_BEGIN
+  if (int rc = check_grid(g)) return rc;
+  (void)hipStreamSynchronize(g->impl->stream);
+  return g->impl->set_graphs(on != 0);
+  MMP_GUARD_END
+}
+
 mmp_status mmp_synchronize(mmp_grid g) {
   MMP_GUARD_BEGIN
   int rc = check_grid(g);
@@ -277,6 +285,39 @@ mmp_status mmp_get_demag_tensor(mmp_grid g, double* n6) {
   if (rc) return rc;
   if (!n6) { set_error("null output"); return MMP_E_ARG; }
   return g->impl->tensor(n6);
+  MMP_GUARD_END
+}
+
+mmp_status mmp_get_plan(mmp_grid g, mmp_plan* out) {
+  MMP_GUARD_BEGIN
+  if (int rc = check_grid(g)) return rc;
+  if (!out || out->struct_size != sizeof(mmp_plan)) {
+    set_error("mmp_plan: null or struct_size mismatch");
+    return MMP_E_ARG;
+  }
+  return g->impl->get_plan(out);
+  MMP_GUARD_END
+}
+
+mmp_status mmp_set_plan(mmp_grid g, const mmp_plan* p) {
+  MMP_GUARD_BEGIN
+  if (int rc = check_grid(g)) return rc;
+  if (!p || p->struct_size != sizeof(mmp_plan)) {
+    set_error("mmp_plan: null or struct_size mismatch");
+    return MMP_E_ARG;
+  }
+  return g->impl->set_plan(p);
+  MMP_GUARD_END
+}
+
+mmp_status mmp_autotune(mmp_grid g, mmp_plan* out) {
+  MMP_GUARD_BEGIN
+  if (int rc = check_grid(g)) return rc;
+  if (out && out->struct_size != sizeof(mmp_plan)) {
+    set_error("mmp_plan: struct_size mismatch");
+    return MMP_E_ARG;
+  }
+  return g->impl->autotune(out);
   MMP_GUARD_END
 }
 

@@ -12,23 +12,34 @@ namespace mmp {
 // S2[c][z][kx][ky] (ky < Py) after the forward y pass (3-D grids only).
 // The kernel spectrum is real and stored on one octant:
 // K[comp][kz <= Pz/2][kx < Hx][ky <= Py/2], comp = xx, yy, zz, xy, xz, yz.
+//
+// The pads and the launch shapes below are the tunable part of the plan;
+// every valid choice computes the same convolution (the launch shapes only
+// regroup identical per-line transforms, except zq, which changes the
+// factorisation of the z transform).
 struct DemagPlan {
   int nx = 0, ny = 0, nz = 0;
   int Px = 0, Py = 0, Pz = 0, Hx = 0, Hy = 0, Hz = 0;
-  int ldy = 0;
+  int ldy = 0;                      // multiple of 16, so any x block shape fits
   Rad rx{}, ry{}, rz{};
-  // launch shapes
-  int ty = 0, thr_x = 0;            // x passes: rows per block (even), threads
-  int nly = 0, thr_y = 0;           // y passes: lines per block, threads
-  int tk = 0, lsz = 0, thr_z = 0;   // z pass: ky per block, LDS line stride
-  int nk2 = 0, thr_m2 = 0;          // 2-D fused y pass: kx columns per block
   // power-of-two axes use the register four-step kernels
   bool p2x = false, p2y = false, p2z = false;
-  int nly4 = 0, nk4 = 0, tk4 = 0;
+  // launch shapes
+  int tyf = 0, tyi = 0;             // x passes: rows (even, <= 16) per block, fwd / inv
+  int nlyf = 0, nlyi = 0;           // y passes: lines per block, fwd / inv
+  int nk = 0;                       // 2-D fused y pass: kx columns per block
+  int tk = 0;                       // mixed-radix z pass: ky columns per block
+  int zq = 1, zw = 1, zt = 0;       // register z pass: lanes per column, waves hint, threads
   size_t s1_elems = 0, s2_elems = 0, k_elems = 0;
 };
 
-int demag_plan(int nx, int ny, int nz, int real_bytes, DemagPlan* p);
+// Plan with the default launch shapes for the given pads (nullptr: the
+// smallest even 7-smooth pads).  Returns 0, or -1 for an unsupported pad.
+int demag_plan(int nx, int ny, int nz, int real_bytes, const int* pads, DemagPlan* p);
+// 0 if every launch shape of p is within the kernels' limits.
+int demag_plan_check(const DemagPlan& p, int real_bytes);
+
+enum DemagPass { DP_XF = 0, DP_YF, DP_Z, DP_YI, DP_XI, DP_M2, DP_COUNT };
 
 template <typename T>
 struct DemagBufs {
@@ -48,6 +59,18 @@ struct DemagBufs {
 template <typename T>
 void demag_field(const DemagPlan& p, const DemagBufs<T>& b, const Table<T>* tbl, int stage,
                  const Ctrl* ctrl, T ms0, T ms1, int nsub, hipStream_t st, Prof* prof);
+
+// One pass of demag_field on its own (the autotuner times them one by one).
+template <typename T>
+void demag_pass(int pass, const DemagPlan& p, const DemagBufs<T>& b, const Table<T>* tbl,
+                int stage, const Ctrl* ctrl, T ms0, T ms1, int nsub, hipStream_t st);
+
+// Times the candidate launch shapes of every pass for the pads of *p on the
+// buffers b and keeps the fastest in *p.  Returns the time of one demag
+// evaluation with the chosen shapes in ms (< 0 on a HIP error).
+template <typename T>
+double demag_tune(DemagPlan* p, const DemagBufs<T>& b, const Table<T>* tbl, T ms0, T ms1,
+                  int nsub, hipStream_t st);
 
 // FP64 tensor on the non-negative offsets and its transformed octant
 // spectrum.  n6 (6*N doubles, device) receives the tensor; kout the scaled

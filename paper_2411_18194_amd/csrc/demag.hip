@@ -14,6 +14,8 @@
 #include "demag.h"
 #include "demag4.h"
 
+#include <vector>
+
 namespace mmp {
 
 // ------------------------------------------------------------- twiddles --
@@ -306,181 +308,371 @@ static int threads_for(long elems) {
   return (int)t;
 }
 
-int demag_plan(int nx, int ny, int nz, int real_bytes, DemagPlan* p) {
+// complex elements one block may hold in LDS (64 KiB)
+static long lds_cap(int real_bytes) { return 65536 / (2 * real_bytes); }
+
+static bool pad_ok(int n, int P) {
+  if (n == 1) return P == 1;
+  if (P < 2 * n - 1 || (P & 1) || P > 4096) return false;
+  int r[16];
+  const int nr = fft_radices(P, r);
+  return nr >= 0 && nr <= 15;
+}
+
+// threads and LDS bytes of each pass for the plan's shapes
+static int x_threads(const DemagPlan& p, int ty) {
+  return p.p2x ? (ty / 2) * split_l2(p.Px) : threads_for((long)(ty / 2) * p.Px);
+}
+static int y_threads(const DemagPlan& p, int nl) {
+  return p.p2y ? nl * split_l2(p.Py) : threads_for((long)nl * p.Py);
+}
+static int m2_threads(const DemagPlan& p) {
+  return p.p2y ? 3 * p.nk * split_l2(p.Py) : threads_for((long)3 * p.nk * p.Py);
+}
+static int z_threads(const DemagPlan& p) { return threads_for((long)3 * p.tk * p.Pz); }
+
+static bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && is_pow2(v); }
+
+int demag_plan_check(const DemagPlan& p, int real_bytes) {
+  const long cap = lds_cap(real_bytes);
+  for (int ty : {p.tyf, p.tyi}) {
+    if (!pow2_in(ty, 2, 16) || (long)(ty / 2) * p.Px > cap) return -1;
+    if (x_threads(p, ty) > (p.p2x ? 256 : 1024)) return -1;
+  }
+  if (p.nz == 1) {
+    if (!pow2_in(p.nk, 1, 64) || (long)3 * p.nk * p.Py > cap) return -1;
+    if (m2_threads(p) > (p.p2y ? 256 : 1024)) return -1;
+  } else {
+    for (int nl : {p.nlyf, p.nlyi}) {
+      if (!pow2_in(nl, 1, 64) || (long)nl * p.Py > cap) return -1;
+      if (y_threads(p, nl) > (p.p2y ? 256 : 1024)) return -1;
+    }
+    if (p.p2z) {
+      if (!zreg_waves_ok(real_bytes, p.Pz, p.zq, p.zw)) return -1;
+      if (p.zt != 64 && p.zt != 128 && p.zt != 256) return -1;
+    } else {
+      if (!pow2_in(p.tk, 1, 64) || (long)3 * p.tk * (p.Pz + 1) > cap) return -1;
+      if (z_threads(p) > 1024) return -1;
+    }
+  }
+  return 0;
+}
+
+int demag_plan(int nx, int ny, int nz, int real_bytes, const int* pads, DemagPlan* p) {
   DemagPlan d;
   d.nx = nx; d.ny = ny; d.nz = nz;
-  d.Px = smooth_pad(nx); d.Py = smooth_pad(ny); d.Pz = smooth_pad(nz);
-  if (d.Px > 4096 || d.Py > 4096 || d.Pz > 4096) return -1;
+  if (pads) {
+    if (!pad_ok(nx, pads[0]) || !pad_ok(ny, pads[1]) || !pad_ok(nz, pads[2])) return -1;
+    d.Px = pads[0]; d.Py = pads[1]; d.Pz = pads[2];
+  } else {
+    d.Px = smooth_pad(nx); d.Py = smooth_pad(ny); d.Pz = smooth_pad(nz);
+    if (!pad_ok(nx, d.Px) || !pad_ok(ny, d.Py) || !pad_ok(nz, d.Pz)) return -1;
+  }
   d.Hx = d.Px / 2 + 1; d.Hy = d.Py / 2 + 1; d.Hz = d.Pz / 2 + 1;
   int rr[3][16];
-  const int nrx = fft_radices(d.Px, rr[0]);
-  const int nry = fft_radices(d.Py, rr[1]);
-  const int nrz = fft_radices(d.Pz, rr[2]);
-  if (nrx < 0 || nry < 0 || nrz < 0 || nrx > 15 || nry > 15 || nrz > 15) return -1;
-  d.rx = make_rad(rr[0], nrx);
-  d.ry = make_rad(rr[1], nry);
-  d.rz = make_rad(rr[2], nrz);
-  // complex elements one block may hold in LDS (64 KiB)
-  const long cap = 65536 / (2 * real_bytes);
-  // x passes: ty rows (pairs) per block
-  int ty = 2;
-  while (ty < 16 && (long)(ty) * d.Px <= cap && ty < ny + (ny & 1)) ty *= 2;
-  if ((long)(ty / 2) * d.Px > cap) ty /= 2;
-  if (ty < 2) ty = 2;
-  d.ty = ty;
-  d.thr_x = threads_for((long)(ty / 2) * d.Px);
-  d.ldy = round_up(ny, ty);
-  // y passes: lines per block
-  int nl = 1;
-  while (nl < 8 && (long)(2 * nl) * d.Py <= cap && (long)(2 * nl) * d.Py <= 4096) nl *= 2;
-  d.nly = nl;
-  d.thr_y = threads_for((long)nl * d.Py);
-  // 2-D fused pass: kx columns per block
-  int nk = 1;
-  while (nk < 64 && (long)3 * (2 * nk) * d.Py <= cap && (long)3 * (2 * nk) * d.Py <= 6144) nk *= 2;
-  d.nk2 = nk;
-  d.thr_m2 = threads_for((long)3 * nk * d.Py);
-  // z pass: ky per block, padded line stride against bank conflicts
-  d.lsz = d.Pz + 1;
-  int tk = 64;
-  while (tk > 1 && (long)3 * tk * d.lsz > cap) tk /= 2;
-  d.tk = tk;
-  d.thr_z = threads_for((long)3 * tk * d.Pz);
-  if (d.thr_x > 1024 || d.thr_y > 1024 || d.thr_m2 > 1024 || d.thr_z > 1024) return -1;
-  // power-of-two axes: register four-step kernels (FP64 only up to 2048
-  // points per line, the z column up to 32 points)
+  d.rx = make_rad(rr[0], fft_radices(d.Px, rr[0]));
+  d.ry = make_rad(rr[1], fft_radices(d.Py, rr[1]));
+  d.rz = make_rad(rr[2], fft_radices(d.Pz, rr[2]));
+  // power-of-two axes: register four-step kernels (FP64 lines up to 2048
+  // points); the register z pass spreads a column over zq lanes
   const int lmax = real_bytes == 8 ? 2048 : 4096;
   d.p2x = is_pow2(d.Px) && d.Px <= lmax;
   d.p2y = is_pow2(d.Py) && d.Py <= lmax;
-  // the register z pass holds three columns per thread: up to 32 points in
-  // FP32, 16 in FP64
-  d.p2z = is_pow2(d.Pz) && d.Pz <= (real_bytes == 8 ? 16 : 32);
+  d.p2z = is_pow2(d.Pz) && d.Pz <= 64;
+  d.ldy = round_up(ny, 16);
+  const long cap = lds_cap(real_bytes);
+  // x passes: the most rows per block that the LDS, the block size and the
+  // grid (no more rows than it has) allow
+  int ty = 2;
+  while (ty < 16 && (long)ty * d.Px <= cap && ty < ny + (ny & 1)) ty *= 2;
+  while (ty > 2 && ((long)(ty / 2) * d.Px > cap || x_threads(d, ty) > (d.p2x ? 256 : 1024)))
+    ty /= 2;
+  d.tyf = d.tyi = ty;
+  // y passes: lines per block
   {
-    const int l2 = split_l2(d.Py);
     int n = 1;
-    while (n < 64 && (long)(2 * n) * d.Py <= cap && 2 * n * l2 <= 256) n *= 2;
-    d.nly4 = n;
+    if (d.p2y) {
+      const int l2 = split_l2(d.Py);
+      while (n < 64 && (long)(2 * n) * d.Py <= cap && 2 * n * l2 <= 256) n *= 2;
+    } else {
+      while (n < 8 && (long)(2 * n) * d.Py <= cap && (long)(2 * n) * d.Py <= 4096) n *= 2;
+    }
+    d.nlyf = d.nlyi = n;
+  }
+  // 2-D fused pass: kx columns per block
+  {
     int k = 1;
-    while (k < 64 && (long)3 * (2 * k) * d.Py <= cap && 3 * (2 * k) * l2 <= 256) k *= 2;
-    d.nk4 = k;
-    // z pass: threads (ky columns) per block
-    d.tk4 = real_bytes == 8 ? 64 : 128;
-    // the x rows per block also bound the four-step block to 256 threads
-    if (d.p2x)
-      while ((d.ty / 2) * split_l2(d.Px) > 256) d.ty /= 2;
-    d.ldy = round_up(ny, d.ty);
-    if (3 * d.nk4 * l2 > 256 || d.nly4 * l2 > 256 || d.tk4 > 256) return -1;
+    if (d.p2y) {
+      const int l2 = split_l2(d.Py);
+      while (k < 64 && (long)3 * (2 * k) * d.Py <= cap && 3 * (2 * k) * l2 <= 256) k *= 2;
+    } else {
+      while (k < 64 && (long)3 * (2 * k) * d.Py <= cap && (long)3 * (2 * k) * d.Py <= 6144) k *= 2;
+    }
+    d.nk = k;
+  }
+  // z pass: mixed-radix ky per block; register lanes per column
+  {
+    int tk = 64;
+    while (tk > 1 && (long)3 * tk * (d.Pz + 1) > cap) tk /= 2;
+    d.tk = tk;
+    int q = 1;
+    while (q < 4 && (!zreg_ok(real_bytes, d.Pz, q) || zreg_data_vgprs(real_bytes, d.Pz, q) > 96))
+      q *= 2;
+    if (!zreg_ok(real_bytes, d.Pz, q)) q = 1;
+    d.zq = q;
+    d.zw = 1;
+    d.zt = 128;
+    if (d.p2z && !zreg_ok(real_bytes, d.Pz, d.zq)) d.p2z = false;
   }
   d.s1_elems = (size_t)3 * nz * d.Hx * d.ldy;
   d.s2_elems = nz > 1 ? (size_t)3 * nz * d.Hx * d.Py : 0;
   d.k_elems = (size_t)6 * d.Hz * d.Hx * d.Hy;
+  if (demag_plan_check(d, real_bytes) != 0) return -1;
   *p = d;
   return 0;
+}
+
+// --------------------------------------------------------------- passes --
+template <typename T>
+void demag_pass(int pass, const DemagPlan& p, const DemagBufs<T>& b, const Table<T>* tbl,
+                int stage, const Ctrl* ctrl, T ms0, T ms1, int nsub, hipStream_t st) {
+  using V = cpx<T>;
+  switch (pass) {
+    case DP_XF:
+    case DP_XI: {
+      const bool inv = pass == DP_XI;
+      const int ty = inv ? p.tyi : p.tyf;
+      const dim3 g((p.ny + ty - 1) / ty, p.nz, 3);
+      const size_t lds = (size_t)(ty / 2) * p.Px * sizeof(V);
+      if (p.p2x) {
+        X4Args<T> a;
+        a.tbl = tbl; a.ctrl = ctrl; a.stage = stage; a.ms0 = ms0; a.ms1 = ms1; a.nsub = nsub;
+        a.S1 = b.S1; a.Bd = b.Bd; a.tw4 = b.tw4x;
+        a.nx = p.nx; a.ny = p.ny; a.nz = p.nz; a.Hx = p.Hx; a.ldy = p.ldy; a.ty = ty;
+        a.lnl = 0;
+        while ((2 << a.lnl) < ty) ++a.lnl;
+        a.swm = 32 / ty;
+        launch_x4<T>(p.Px, inv, g, x_threads(p, ty), lds, st, a);
+      } else {
+        XArgs<T> a;
+        a.tbl = tbl; a.ctrl = ctrl; a.stage = stage; a.ms0 = ms0; a.ms1 = ms1; a.nsub = nsub;
+        a.S1 = b.S1; a.Bd = b.Bd; a.tw = b.twx;
+        a.nx = p.nx; a.ny = p.ny; a.nz = p.nz; a.Px = p.Px; a.Hx = p.Hx; a.ldy = p.ldy;
+        a.ty = ty; a.rad = p.rx;
+        if (inv)
+          hipLaunchKernelGGL((k_fftx_inv<T, false>), g, dim3(x_threads(p, ty)), lds, st, a);
+        else
+          hipLaunchKernelGGL((k_fftx_fwd<T, false>), g, dim3(x_threads(p, ty)), lds, st, a);
+      }
+      break;
+    }
+    case DP_M2: {
+      const size_t lds = (size_t)3 * p.nk * p.Py * sizeof(V);
+      const dim3 g((p.Hx + p.nk - 1) / p.nk);
+      if (p.p2y) {
+        M4Args<T> a;
+        a.ctrl = ctrl; a.S1 = b.S1; a.K = b.K; a.tw4 = b.tw4y;
+        a.ny = p.ny; a.Hx = p.Hx; a.Hy = p.Hy; a.ldy = p.ldy; a.nk = p.nk;
+        launch_m4<T>(p.Py, g, m2_threads(p), lds, st, a);
+      } else {
+        M2Args<T> a;
+        a.ctrl = ctrl; a.S1 = b.S1; a.K = b.K; a.tw = b.twy;
+        a.ny = p.ny; a.Py = p.Py; a.Hx = p.Hx; a.Hy = p.Hy; a.ldy = p.ldy; a.nk = p.nk;
+        a.rad = p.ry;
+        hipLaunchKernelGGL((k_ffty_mul2d<T, false>), g, dim3(m2_threads(p)), lds, st, a);
+      }
+      break;
+    }
+    case DP_YF:
+    case DP_YI: {
+      const bool inv = pass == DP_YI;
+      const int nl = inv ? p.nlyi : p.nlyf;
+      const int nlines = 3 * p.nz * p.Hx;
+      const dim3 g((nlines + nl - 1) / nl);
+      const size_t lds = (size_t)nl * p.Py * sizeof(V);
+      const cpx<T>* in = inv ? b.S2 : b.S1;
+      cpx<T>* out = inv ? b.S1 : b.S2;
+      const int nvi = inv ? p.Py : p.ny, ldi = inv ? p.Py : p.ldy;
+      const int nvo = inv ? p.ny : p.Py, ldo = inv ? p.ldy : p.Py;
+      if (p.p2y) {
+        Y4Args<T> a;
+        a.ctrl = ctrl; a.in = in; a.out = out; a.tw4 = b.tw4y;
+        a.nlines = nlines; a.nvalid_in = nvi; a.ld_in = ldi; a.nvalid_out = nvo; a.ld_out = ldo;
+        a.nl = nl;
+        launch_y4<T>(p.Py, inv, g, y_threads(p, nl), lds, st, a);
+      } else {
+        YArgs<T> a;
+        a.ctrl = ctrl; a.in = in; a.out = out; a.tw = b.twy;
+        a.nlines = nlines; a.nvalid_in = nvi; a.ld_in = ldi; a.nvalid_out = nvo; a.ld_out = ldo;
+        a.L = p.Py; a.nl = nl; a.rad = p.ry;
+        if (inv)
+          hipLaunchKernelGGL((k_ffty<T, true, false>), g, dim3(y_threads(p, nl)), lds, st, a);
+        else
+          hipLaunchKernelGGL((k_ffty<T, false, false>), g, dim3(y_threads(p, nl)), lds, st, a);
+      }
+      break;
+    }
+    case DP_Z: {
+      if (p.p2z) {
+        Z4Args<T> a;
+        a.ctrl = ctrl; a.S2 = b.S2; a.K = b.K;
+        a.nz = p.nz; a.Hx = p.Hx; a.Py = p.Py; a.Hy = p.Hy; a.Hz = p.Hz; a.tk = p.zt;
+        const int cpb = p.zt / p.zq;
+        const int nblk = ((p.Py + cpb - 1) / cpb) * p.Hx;
+        a.nb_pad = round_up(nblk, 8);
+        launch_z4<T>(p.Pz, p.zq, p.zw, dim3(a.nb_pad), p.zt, st, a);
+      } else {
+        ZArgs<T> a;
+        a.ctrl = ctrl; a.S2 = b.S2; a.K = b.K; a.tw = b.twz;
+        a.nz = p.nz; a.Pz = p.Pz; a.Hx = p.Hx; a.Py = p.Py; a.Hy = p.Hy; a.Hz = p.Hz;
+        a.tk = p.tk; a.ls = p.Pz + 1; a.rad = p.rz;
+        hipLaunchKernelGGL((k_fftz_mul<T, false>), dim3((p.Py + p.tk - 1) / p.tk, p.Hx),
+                           dim3(z_threads(p)), (size_t)3 * p.tk * (p.Pz + 1) * sizeof(V), st, a);
+      }
+      break;
+    }
+  }
+}
+
+static const int kPassProf[DP_COUNT] = {P_FFTX_FWD, P_FFTY_FWD, P_FFTZ_MUL,
+                                        P_FFTY_INV, P_FFTX_INV, P_FFTY_MUL2D};
+
+static int demag_passes(const DemagPlan& p, int* out) {
+  int n = 0;
+  out[n++] = DP_XF;
+  if (p.nz == 1) {
+    out[n++] = DP_M2;
+  } else {
+    out[n++] = DP_YF;
+    out[n++] = DP_Z;
+    out[n++] = DP_YI;
+  }
+  out[n++] = DP_XI;
+  return n;
 }
 
 // --------------------------------------------------------------- driver --
 template <typename T>
 void demag_field(const DemagPlan& p, const DemagBufs<T>& b, const Table<T>* tbl, int stage,
                  const Ctrl* ctrl, T ms0, T ms1, int nsub, hipStream_t st, Prof* prof) {
-  using V = cpx<T>;
-  const dim3 gx((p.ny + p.ty - 1) / p.ty, p.nz, 3);
-  const size_t lds_x = (size_t)(p.ty / 2) * p.Px * sizeof(V);
-  XArgs<T> xa;
-  xa.tbl = tbl; xa.ctrl = ctrl; xa.stage = stage; xa.ms0 = ms0; xa.ms1 = ms1; xa.nsub = nsub;
-  xa.S1 = b.S1; xa.Bd = b.Bd; xa.tw = b.twx;
-  xa.nx = p.nx; xa.ny = p.ny; xa.nz = p.nz; xa.Px = p.Px; xa.Hx = p.Hx; xa.ldy = p.ldy;
-  xa.ty = p.ty; xa.rad = p.rx;
-  X4Args<T> x4;
-  x4.tbl = tbl; x4.ctrl = ctrl; x4.stage = stage; x4.ms0 = ms0; x4.ms1 = ms1; x4.nsub = nsub;
-  x4.S1 = b.S1; x4.Bd = b.Bd; x4.tw4 = b.tw4x;
-  x4.nx = p.nx; x4.ny = p.ny; x4.nz = p.nz; x4.Hx = p.Hx; x4.ldy = p.ldy; x4.ty = p.ty;
-  const int thr_x4 = (p.ty / 2) * split_l2(p.Px);
-  {
-    ProfScope ps(prof, P_FFTX_FWD, st);
-    if (p.p2x) launch_x4<T>(p.Px, false, gx, thr_x4, lds_x, st, x4);
-    else hipLaunchKernelGGL((k_fftx_fwd<T, false>), gx, dim3(p.thr_x), lds_x, st, xa);
-  }
-  if (p.nz == 1) {
-    ProfScope ps(prof, P_FFTY_MUL2D, st);
-    if (p.p2y) {
-      M4Args<T> m4;
-      m4.ctrl = ctrl; m4.S1 = b.S1; m4.K = b.K; m4.tw4 = b.tw4y;
-      m4.ny = p.ny; m4.Hx = p.Hx; m4.Hy = p.Hy; m4.ldy = p.ldy; m4.nk = p.nk4;
-      launch_m4<T>(p.Py, dim3((p.Hx + p.nk4 - 1) / p.nk4), 3 * p.nk4 * split_l2(p.Py),
-                   (size_t)3 * p.nk4 * p.Py * sizeof(V), st, m4);
-    } else {
-      M2Args<T> ma;
-      ma.ctrl = ctrl; ma.S1 = b.S1; ma.K = b.K; ma.tw = b.twy;
-      ma.ny = p.ny; ma.Py = p.Py; ma.Hx = p.Hx; ma.Hy = p.Hy; ma.ldy = p.ldy; ma.nk = p.nk2;
-      ma.rad = p.ry;
-      hipLaunchKernelGGL((k_ffty_mul2d<T, false>), dim3((p.Hx + p.nk2 - 1) / p.nk2),
-                         dim3(p.thr_m2), (size_t)3 * p.nk2 * p.Py * sizeof(V), st, ma);
-    }
-  } else {
-    const int nlines = 3 * p.nz * p.Hx;
-    YArgs<T> ya;
-    ya.ctrl = ctrl; ya.in = b.S1; ya.out = b.S2; ya.tw = b.twy;
-    ya.nlines = nlines; ya.nvalid_in = p.ny; ya.ld_in = p.ldy; ya.nvalid_out = p.Py;
-    ya.ld_out = p.Py; ya.L = p.Py; ya.nl = p.nly; ya.rad = p.ry;
-    const dim3 gy((nlines + p.nly - 1) / p.nly);
-    const size_t lds_y = (size_t)p.nly * p.Py * sizeof(V);
-    Y4Args<T> y4;
-    y4.ctrl = ctrl; y4.in = b.S1; y4.out = b.S2; y4.tw4 = b.tw4y;
-    y4.nlines = nlines; y4.nvalid_in = p.ny; y4.ld_in = p.ldy; y4.nvalid_out = p.Py;
-    y4.ld_out = p.Py; y4.nl = p.nly4;
-    const dim3 gy4((nlines + p.nly4 - 1) / p.nly4);
-    const int thr_y4 = p.nly4 * split_l2(p.Py);
-    const size_t lds_y4 = (size_t)p.nly4 * p.Py * sizeof(V);
-    {
-      ProfScope ps(prof, P_FFTY_FWD, st);
-      if (p.p2y) launch_y4<T>(p.Py, false, gy4, thr_y4, lds_y4, st, y4);
-      else hipLaunchKernelGGL((k_ffty<T, false, false>), gy, dim3(p.thr_y), lds_y, st, ya);
-    }
-    {
-      ProfScope ps(prof, P_FFTZ_MUL, st);
-      if (p.p2z) {
-        Z4Args<T> z4;
-        z4.ctrl = ctrl; z4.S2 = b.S2; z4.K = b.K;
-        z4.nz = p.nz; z4.Hx = p.Hx; z4.Py = p.Py; z4.Hy = p.Hy; z4.Hz = p.Hz; z4.tk = p.tk4;
-        const int zthr = p.tk4;
-        const int nblk = ((p.Py + zthr - 1) / zthr) * p.Hx;
-        z4.nb_pad = round_up(nblk, 8);
-        launch_z4<T>(p.Pz, dim3(z4.nb_pad), zthr, 0, st, z4);
-      } else {
-        ZArgs<T> za;
-        za.ctrl = ctrl; za.S2 = b.S2; za.K = b.K; za.tw = b.twz;
-        za.nz = p.nz; za.Pz = p.Pz; za.Hx = p.Hx; za.Py = p.Py; za.Hy = p.Hy; za.Hz = p.Hz;
-        za.tk = p.tk; za.ls = p.lsz; za.rad = p.rz;
-        hipLaunchKernelGGL((k_fftz_mul<T, false>), dim3((p.Py + p.tk - 1) / p.tk, p.Hx),
-                           dim3(p.thr_z), (size_t)3 * p.tk * p.lsz * sizeof(V), st, za);
-      }
-    }
-    {
-      ProfScope ps(prof, P_FFTY_INV, st);
-      if (p.p2y) {
-        Y4Args<T> yi = y4;
-        yi.in = b.S2; yi.out = b.S1; yi.nvalid_in = p.Py; yi.ld_in = p.Py;
-        yi.nvalid_out = p.ny; yi.ld_out = p.ldy;
-        launch_y4<T>(p.Py, true, gy4, thr_y4, lds_y4, st, yi);
-      } else {
-        YArgs<T> yi = ya;
-        yi.in = b.S2; yi.out = b.S1; yi.nvalid_in = p.Py; yi.ld_in = p.Py;
-        yi.nvalid_out = p.ny; yi.ld_out = p.ldy;
-        hipLaunchKernelGGL((k_ffty<T, true, false>), gy, dim3(p.thr_y), lds_y, st, yi);
-      }
-    }
-  }
-  {
-    ProfScope ps(prof, P_FFTX_INV, st);
-    if (p.p2x) launch_x4<T>(p.Px, true, gx, thr_x4, lds_x, st, x4);
-    else hipLaunchKernelGGL((k_fftx_inv<T, false>), gx, dim3(p.thr_x), lds_x, st, xa);
+  int passes[DP_COUNT];
+  const int n = demag_passes(p, passes);
+  for (int i = 0; i < n; ++i) {
+    ProfScope ps(prof, kPassProf[passes[i]], st);
+    demag_pass<T>(passes[i], p, b, tbl, stage, ctrl, ms0, ms1, nsub, st);
   }
 }
 
-template void demag_field<float>(const DemagPlan&, const DemagBufs<float>&, const Table<float>*,
-                                 int, const Ctrl*, float, float, int, hipStream_t, Prof*);
-template void demag_field<double>(const DemagPlan&, const DemagBufs<double>&,
-                                  const Table<double>*, int, const Ctrl*, double, double, int,
-                                  hipStream_t, Prof*);
+// ------------------------------------------------------------ autotuner --
+// Mean time of one launch of `pass` over `reps` back-to-back launches after
+// one warm-up launch; a failed launch reads as infinitely slow.
+template <typename T>
+static double time_pass(int pass, const DemagPlan& p, const DemagBufs<T>& b, const Table<T>* tbl,
+                        T ms0, T ms1, int nsub, hipStream_t st, int reps) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return -1.0;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return -1.0;
+  }
+  double ms = -1.0;
+  demag_pass<T>(pass, p, b, tbl, 1, nullptr, ms0, ms1, nsub, st);
+  if (hipGetLastError() == hipSuccess && hipEventRecord(e0, st) == hipSuccess) {
+    for (int r = 0; r < reps; ++r) demag_pass<T>(pass, p, b, tbl, 1, nullptr, ms0, ms1, nsub, st);
+    float f = 0.f;
+    if (hipGetLastError() == hipSuccess && hipEventRecord(e1, st) == hipSuccess &&
+        hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&f, e0, e1) == hipSuccess)
+      ms = (double)f / reps;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms;
+}
+
+template <typename T>
+double demag_tune(DemagPlan* pp, const DemagBufs<T>& b, const Table<T>* tbl, T ms0, T ms1,
+                  int nsub, hipStream_t st) {
+  constexpr int rb = (int)sizeof(T);
+  DemagPlan best = *pp;
+  int passes[DP_COUNT];
+  const int n = demag_passes(best, passes);
+  // launches per timing: enough to average out launch jitter on small grids
+  const long work = (long)best.Hx * best.Py * best.Pz;
+  const int reps = work >= (1L << 22) ? 3 : work >= (1L << 16) ? 10 : 30;
+  double total = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const int pass = passes[i];
+    std::vector<DemagPlan> cand;
+    auto add = [&](DemagPlan c) {
+      if (demag_plan_check(c, rb) == 0) cand.push_back(c);
+    };
+    switch (pass) {
+      case DP_XF:
+      case DP_XI:
+        for (int ty = 2; ty <= 16; ty *= 2) {
+          DemagPlan c = best;
+          (pass == DP_XF ? c.tyf : c.tyi) = ty;
+          add(c);
+        }
+        break;
+      case DP_YF:
+      case DP_YI:
+        for (int nl = 1; nl <= 64; nl *= 2) {
+          DemagPlan c = best;
+          (pass == DP_YF ? c.nlyf : c.nlyi) = nl;
+          add(c);
+        }
+        break;
+      case DP_M2:
+        for (int k = 1; k <= 64; k *= 2) {
+          DemagPlan c = best;
+          c.nk = k;
+          add(c);
+        }
+        break;
+      case DP_Z:
+        if (best.p2z) {
+          for (int q = 1; q <= 4; q *= 2)
+            for (int w = 1; w <= 4; w *= 2)
+              for (int t = 64; t <= 256; t *= 2) {
+                DemagPlan c = best;
+                c.zq = q; c.zw = w; c.zt = t;
+                add(c);
+              }
+        } else {
+          for (int tk = 1; tk <= 64; tk *= 2) {
+            DemagPlan c = best;
+            c.tk = tk;
+            add(c);
+          }
+        }
+        break;
+    }
+    double bt = -1.0;
+    for (const DemagPlan& c : cand) {
+      const double t = time_pass<T>(pass, c, b, tbl, ms0, ms1, nsub, st, reps);
+      if (t < 0.0) continue;
+      if (bt < 0.0 || t < bt) {
+        bt = t;
+        best = c;
+      }
+    }
+    if (bt < 0.0) return -1.0;
+    total += bt;
+  }
+  *pp = best;
+  return total;
+}
+
+#define INST(T)                                                                                 \
+  template void demag_field<T>(const DemagPlan&, const DemagBufs<T>&, const Table<T>*, int,      \
+                               const Ctrl*, T, T, int, hipStream_t, Prof*);                     \
+  template void demag_pass<T>(int, const DemagPlan&, const DemagBufs<T>&, const Table<T>*, int,  \
+                              const Ctrl*, T, T, int, hipStream_t);                             \
+  template double demag_tune<T>(DemagPlan*, const DemagBufs<T>&, const Table<T>*, T, T, int,    \
+                                hipStream_t);
+INST(float)
+INST(double)
+#undef INST
 
 }  // namespace mmp

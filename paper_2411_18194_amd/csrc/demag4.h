@@ -17,6 +17,7 @@ struct X4Args {
   T* Bd;
   const cpx<T>* tw4;
   int nx, ny, nz, Hx, ldy, ty;
+  int lnl, swm;  // log2(ty / 2), 32 / ty
 };
 
 template <typename T>
@@ -45,6 +46,23 @@ struct Z4Args {
   int nz, Hx, Py, Hy, Hz, tk, nb_pad;
 };
 
+// Register z pass variants that are built: a lane holds the three
+// components of PZ/zq points, data_vgprs 32-bit registers; variants that
+// would hold more than 192 are not built, and a waves-per-SIMD hint zw > 1 is
+// built only where zw times the data still fits the 512-register file with
+// a quarter to spare.
+constexpr int zreg_data_vgprs(int real_bytes, int pz, int zq) {
+  return 3 * (pz / zq) * 2 * (real_bytes / 4);
+}
+constexpr bool zreg_ok(int real_bytes, int pz, int zq) {
+  return (zq == 1 || zq == 2 || zq == 4) && pz >= 2 && pz <= 64 && (zq == 1 || pz / zq >= 2) &&
+         zreg_data_vgprs(real_bytes, pz, zq) <= 192;
+}
+constexpr bool zreg_waves_ok(int real_bytes, int pz, int zq, int zw) {
+  return zreg_ok(real_bytes, pz, zq) &&
+         (zw == 1 || ((zw == 2 || zw == 4) && zreg_data_vgprs(real_bytes, pz, zq) * zw <= 384));
+}
+
 template <typename T>
 void launch_y4(int L, bool inv, dim3 g, int thr, size_t lds, hipStream_t st, const Y4Args<T>& a);
 template <typename T>
@@ -52,6 +70,6 @@ void launch_x4(int L, bool inv, dim3 g, int thr, size_t lds, hipStream_t st, con
 template <typename T>
 void launch_m4(int L, dim3 g, int thr, size_t lds, hipStream_t st, const M4Args<T>& a);
 template <typename T>
-void launch_z4(int PZ, dim3 g, int thr, size_t lds, hipStream_t st, const Z4Args<T>& a);
+void launch_z4(int PZ, int q, int w, dim3 g, int thr, hipStream_t st, const Z4Args<T>& a);
 
 }  // namespace mmp

@@ -8,6 +8,8 @@
 #include "demag4.h"
 #include "fft4.h"
 
+#include <type_traits>
+
 namespace mmp {
 
 template <typename T>
@@ -64,6 +66,38 @@ __device__ __forceinline__ void fs_step3(cpx<T> (*u)[L2], const cpx<T>* line, in
 #pragma unroll
     for (int n2 = 0; n2 < L2; ++n2) u[i][n2] = line[k1 * L2 + (n2 ^ (k1 & (L2 - 1)))];
     reg_fft<T, L2, INV>(u[i]);
+  }
+}
+
+// Bank swizzle of line q's natural-order spectrum in LDS for the x passes:
+// element k sits at k ^ xsw(q).  The lines of one block start on the same
+// bank (L is a multiple of the bank count), and the (un)pack loops read one
+// frequency of every line at once; the XOR spreads those lines over the
+// banks.  ty = rows per block, nl = ty/2 lines.
+// swm = 32 / ty, passed in so the loops need no division
+__device__ __forceinline__ int xsw(int q, int swm, int L) { return (q * swm) & (L - 1); }
+
+// two consecutive complex values as one 16-byte access where they fit
+template <typename T>
+__device__ __forceinline__ void store2(cpx<T>* o, cpx<T> a, cpx<T> b) {
+  if constexpr (sizeof(cpx<T>) == 8) {
+    float4 v;
+    v.x = a.x; v.y = a.y; v.z = b.x; v.w = b.y;
+    *reinterpret_cast<float4*>(o) = v;
+  } else {
+    o[0] = a;
+    o[1] = b;
+  }
+}
+template <typename T>
+__device__ __forceinline__ void load2(const cpx<T>* i, cpx<T>& a, cpx<T>& b) {
+  if constexpr (sizeof(cpx<T>) == 8) {
+    const float4 v = *reinterpret_cast<const float4*>(i);
+    a = cmk<T>(v.x, v.y);
+    b = cmk<T>(v.z, v.w);
+  } else {
+    a = i[0];
+    b = i[1];
   }
 }
 
@@ -144,21 +178,24 @@ __global__ __launch_bounds__(256) void k4_fftx_fwd(X4Args<T> a) {
   V u[L1 / L2][L2];
   fs_step3<T, L1, L2, false>(u, line, t);
   __syncthreads();
+  const int swq = xsw(q, a.swm, L);
 #pragma unroll
   for (int i = 0; i < L1 / L2; ++i)
 #pragma unroll
-    for (int k2 = 0; k2 < L2; ++k2) line[t + L2 * i + L1 * k2] = u[i][bitrev<L2>(k2)];
+    for (int k2 = 0; k2 < L2; ++k2)
+      line[(t + L2 * i + L1 * k2) ^ swq] = u[i][bitrev<L2>(k2)];
   __syncthreads();
-  // unpack the two real spectra and store them transposed (y contiguous)
+  // unpack the two real spectra and store them transposed (y contiguous,
+  // rows 2qq and 2qq+1 as one 16-byte store for FP32)
   V* out = a.S1 + ((long)(c * a.nz + z) * a.Hx) * a.ldy + y0;
   for (int idx = tid; idx < nl * a.Hx; idx += nthr) {
-    const int qq = idx % nl, kx = idx / nl;
-    const V zk = lds[qq * L + kx];
-    const V zm = lds[qq * L + ((L - kx) & (L - 1))];
+    const int qq = idx & (nl - 1), kx = idx >> a.lnl;
+    const int sw = xsw(qq, a.swm, L);
+    const V zk = lds[qq * L + (kx ^ sw)];
+    const V zm = lds[qq * L + (((L - kx) & (L - 1)) ^ sw)];
     const T h = T(0.5);
-    V* o = out + (long)kx * a.ldy + 2 * qq;
-    o[0] = cmk<T>(h * (zk.x + zm.x), h * (zk.y - zm.y));
-    o[1] = cmk<T>(h * (zk.y + zm.y), h * (zm.x - zk.x));
+    store2<T>(out + (long)kx * a.ldy + 2 * qq, cmk<T>(h * (zk.x + zm.x), h * (zk.y - zm.y)),
+              cmk<T>(h * (zk.y + zm.y), h * (zm.x - zk.x)));
   }
 }
 
@@ -175,17 +212,19 @@ __global__ __launch_bounds__(256) void k4_fftx_inv(X4Args<T> a) {
   const int nl = a.ty >> 1;
   const V* in = a.S1 + ((long)(c * a.nz + z) * a.Hx) * a.ldy + y0;
   for (int idx = tid; idx < nl * a.Hx; idx += nthr) {
-    const int qq = idx % nl, kx = idx / nl;
-    const V* ip = in + (long)kx * a.ldy + 2 * qq;
-    const V xa = ip[0], xb = ip[1];
-    lds[qq * L + kx] = cmk<T>(xa.x - xb.y, xa.y + xb.x);
-    if (kx > 0 && 2 * kx < L) lds[qq * L + L - kx] = cmk<T>(xa.x + xb.y, xb.x - xa.y);
+    const int qq = idx & (nl - 1), kx = idx >> a.lnl;
+    const int sw = xsw(qq, a.swm, L);
+    V xa, xb;
+    load2<T>(in + (long)kx * a.ldy + 2 * qq, xa, xb);
+    lds[qq * L + (kx ^ sw)] = cmk<T>(xa.x - xb.y, xa.y + xb.x);
+    if (kx > 0 && 2 * kx < L) lds[qq * L + ((L - kx) ^ sw)] = cmk<T>(xa.x + xb.y, xb.x - xa.y);
   }
   __syncthreads();
   V* line = lds + q * L;
+  const int swq = xsw(q, a.swm, L);
   V v[L1];
 #pragma unroll
-  for (int n1 = 0; n1 < L1; ++n1) v[n1] = line[L2 * n1 + t];
+  for (int n1 = 0; n1 < L1; ++n1) v[n1] = line[(L2 * n1 + t) ^ swq];
   __syncthreads();
   fs_step1<T, L1, L2, true>(v, line, a.tw4, t);
   __syncthreads();
@@ -290,74 +329,195 @@ __global__ __launch_bounds__(256) void k4_ffty_mul2d(M4Args<T> a) {
 }
 
 // ------------------------------------------ 3-D z columns + multiply ----
-// One thread carries the three components of one (kx, ky) column through
-// forward FFT, kernel multiply and inverse FFT in registers: no LDS and no
-// barriers, so the pass streams like a copy.  Blocks are ordered so that all
-// ky tiles of one kx run back to back on one XCD, which keeps that kx slice
-// of the kernel (read for ky and its mirror Py - ky) in the XCD's L2.
-template <typename T, int PZ>
-__global__ __launch_bounds__(256) void k4_fftz_mul(Z4Args<T> a) {
+// The value that lane (lane ^ X) of the same quad holds, X = 1 or 2 (DPP
+// quad permutations [1,0,3,2] and [2,3,0,1]; no LDS traffic).
+template <int X>
+__device__ __forceinline__ int quad_xor_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, X == 1 ? 0xB1 : 0x4E, 0xF, 0xF, false);
+}
+template <int X>
+__device__ __forceinline__ float quad_xor(float v) {
+  return __int_as_float(quad_xor_i<X>(__float_as_int(v)));
+}
+template <int X>
+__device__ __forceinline__ double quad_xor(double v) {
+  return __hiloint2double(quad_xor_i<X>(__double2hiint(v)), quad_xor_i<X>(__double2loint(v)));
+}
+template <int X, typename T>
+__device__ __forceinline__ cpx<T> quad_xor_c(cpx<T> v) {
+  return cmk<T>(quad_xor<X>(v.x), quad_xor<X>(v.y));
+}
+
+// f(integral_constant<int, I>) for I = B .. E-1, unrolled at compile time
+template <int I, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < E) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, E>(f);
+  }
+}
+
+// exp(-/+ 2 pi i n q / P) for compile-time n, P and a lane index q < Q
+template <typename T, int N, int P, int Q, bool INV>
+__device__ __forceinline__ cpx<T> lane_root(int q) {
+  cpx<T> w = cmk<T>(T(1), T(0));
+  if constexpr (Q >= 2)
+    if (q == 1) w = root<T, N, P, INV>();
+  if constexpr (Q >= 4) {
+    if (q == 2) w = root<T, 2 * N, P, INV>();
+    if (q == 3) w = root<T, 3 * N, P, INV>();
+  }
+  return w;
+}
+
+// Inverse transform of one component held by the Q lanes of a column and
+// store of the first nz planes.  Lane q holds B(kz = Q j + q) at register
+// bitrev<R>(j); with R = PZ/Q,
+//   b(n) = sum_q w^(-n q) IFFT_R(B(Q j + q))(n mod R),
+// so each lane forms its term for n < PZ/2 and the Q lanes sum them with a
+// recursive-halving exchange that leaves lane q owning PZ/(2Q) planes.
+template <typename T, int PZ, int Q>
+__device__ __forceinline__ void zcol_inverse_store(cpx<T>* v, cpx<T>* col, long zs, int nz,
+                                                   int q) {
   using V = cpx<T>;
+  constexpr int R = PZ / Q, NH = PZ / 2;
+  V t[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) t[k] = v[bitrev<R>(k)];
+  reg_fft<T, R, true>(t);
+  if constexpr (Q == 1) {
+#pragma unroll
+    for (int z = 0; z < NH; ++z)
+      if (z < nz) col[z * zs] = t[bitrev<PZ>(z)];
+  } else {
+    V c[NH];
+    static_for<0, NH>([&](auto nc) {
+      constexpr int n = decltype(nc)::value;
+      const V x = t[bitrev<R>(n % R)];
+      if constexpr (n == 0) c[n] = x;
+      else c[n] = cmul(x, lane_root<T, n, PZ, Q, true>(q));
+    });
+    int base = 0;
+    if constexpr (Q == 4) {
+      const bool hi = (q & 2) != 0;
+#pragma unroll
+      for (int i = 0; i < NH / 2; ++i) {
+        const V send = hi ? c[i] : c[i + NH / 2];
+        const V keep = hi ? c[i + NH / 2] : c[i];
+        c[i] = cadd(keep, quad_xor_c<2, T>(send));
+      }
+      base += hi ? NH / 2 : 0;
+    }
+    constexpr int S = 2 * NH / Q;  // planes held before the last exchange
+    const bool hi = (q & 1) != 0;
+#pragma unroll
+    for (int i = 0; i < S / 2; ++i) {
+      const V send = hi ? c[i] : c[i + S / 2];
+      const V keep = hi ? c[i + S / 2] : c[i];
+      c[i] = cadd(keep, quad_xor_c<1, T>(send));
+    }
+    base += hi ? S / 2 : 0;
+#pragma unroll
+    for (int i = 0; i < S / 2; ++i)
+      if (base + i < nz) col[(base + i) * zs] = c[i];
+  }
+}
+
+// Q adjacent lanes (Q = 1, 2 or 4, within one quad) carry the three
+// components of one (kx, ky) column through forward FFT, kernel multiply and
+// inverse FFT in registers: no LDS and no barriers, so the pass streams like
+// a copy.  Lane q computes the spectrum at kz = q mod Q: it twists the data by
+// w^(n q), folds it modulo R = PZ/Q and takes an R-point transform, so more
+// lanes per column mean fewer registers per lane.  Blocks are ordered so that
+// all ky tiles of one kx run back to back on one XCD, which keeps that kx
+// slice of the kernel (read for ky and its mirror Py - ky) in the XCD's L2.
+template <typename T, int PZ, int Q>
+__device__ __forceinline__ void fftz_mul_body(const Z4Args<T>& a) {
+  using V = cpx<T>;
+  constexpr int R = PZ / Q, NH = PZ / 2;
+  static_assert(zreg_ok((int)sizeof(T), PZ, Q), "lanes per column");
   if (ctrl_stopped(a.ctrl)) return;
-  const int ntile = (a.Py + blockDim.x - 1) / blockDim.x;
+  const int cpb = blockDim.x / Q;
+  const int ntile = (a.Py + cpb - 1) / cpb;
   const int w = xcd_remap(blockIdx.x, a.nb_pad);
   if (w >= ntile * a.Hx) return;
-  const int kx = w / ntile, ky = (w - kx * ntile) * blockDim.x + threadIdx.x;
+  const int q = threadIdx.x % Q;
+  const int kx = w / ntile, ky = (w - kx * ntile) * cpb + threadIdx.x / Q;
   if (ky >= a.Py) return;
   const long zs = (long)a.Hx * a.Py;
   const long cs = (long)a.nz * zs;
   V* col = a.S2 + (long)kx * a.Py + ky;
-  V vx[PZ], vy[PZ], vz[PZ];
-  // nz <= PZ/2 for every power-of-two pad, so the upper halves are zero
+  V vx[R], vy[R], vz[R];
+  // nz <= PZ/2 for every power-of-two pad, so the upper half is zero
+  // all planes are loaded first (a plain unrolled loop keeps the loads
+  // back to back), then lane q twists them by w^(n q) and folds mod R
+  V lx[NH], ly[NH], lz[NH];
 #pragma unroll
-  for (int z = 0; z < PZ / 2; ++z) {
-    const bool in = z < a.nz;
-    vx[z] = in ? col[z * zs] : cmk<T>(0, 0);
-    vy[z] = in ? col[cs + z * zs] : cmk<T>(0, 0);
-    vz[z] = in ? col[2 * cs + z * zs] : cmk<T>(0, 0);
+  for (int n = 0; n < NH; ++n) {
+    const bool in = n < a.nz;
+    lx[n] = in ? col[n * zs] : cmk<T>(0, 0);
+    ly[n] = in ? col[cs + n * zs] : cmk<T>(0, 0);
+    lz[n] = in ? col[2 * cs + n * zs] : cmk<T>(0, 0);
   }
-  reg_fft_hz<T, PZ, false>(vx);
-  reg_fft_hz<T, PZ, false>(vy);
-  reg_fft_hz<T, PZ, false>(vz);
+  static_for<0, NH>([&](auto nc) {
+    constexpr int n = decltype(nc)::value;
+    V x = lx[n], y = ly[n], z = lz[n];
+    if constexpr (Q > 1 && n > 0) {
+      const V wq = lane_root<T, n, PZ, Q, false>(q);
+      x = cmul(x, wq);
+      y = cmul(y, wq);
+      z = cmul(z, wq);
+    }
+    if constexpr (n < R) {
+      vx[n] = x; vy[n] = y; vz[n] = z;
+    } else {
+      vx[n % R] = cadd(vx[n % R], x); vy[n % R] = cadd(vy[n % R], y);
+      vz[n % R] = cadd(vz[n % R], z);
+    }
+  });
+  if constexpr (Q == 1) {
+    reg_fft_hz<T, PZ, false>(vx);
+    reg_fft_hz<T, PZ, false>(vy);
+    reg_fft_hz<T, PZ, false>(vz);
+  } else {
+    reg_fft<T, R, false>(vx);
+    reg_fft<T, R, false>(vy);
+    reg_fft<T, R, false>(vz);
+  }
   const int kyo = ky <= a.Py / 2 ? ky : a.Py - ky;
   const T sy = ky <= a.Py / 2 ? T(1) : T(-1);
   const long ks = (long)a.Hz * a.Hx * a.Hy;
   const T* K = a.K + (long)kx * a.Hy + kyo;
   const long kzs = (long)a.Hx * a.Hy;
-  // B(kz) = K(kz) M(kz); spectra sit at bit-reversed register positions
+  // B(kz) = K(kz) M(kz); the spectra sit at bit-reversed register positions
 #pragma unroll
-  for (int kz = 0; kz < PZ; ++kz) {
+  for (int j = 0; j < R; ++j) {
+    const int kz = Q * j + q;
     const int kzo = kz <= PZ / 2 ? kz : PZ - kz;
     const T sz = kz <= PZ / 2 ? T(1) : T(-1);
     const T* kr = K + kzo * kzs;
     const T kxx = kr[0], kyy = kr[ks], kzz = kr[2 * ks];
     const T kxy = sy * kr[3 * ks], kxz = sz * kr[4 * ks], kyz = sy * sz * kr[5 * ks];
-    const int r = bitrev<PZ>(kz);
+    const int r = bitrev<R>(j);
     const V mx = vx[r], my = vy[r], mz = vz[r];
     vx[r] = cmk<T>(kxx * mx.x + kxy * my.x + kxz * mz.x, kxx * mx.y + kxy * my.y + kxz * mz.y);
     vy[r] = cmk<T>(kxy * mx.x + kyy * my.x + kyz * mz.x, kxy * mx.y + kyy * my.y + kyz * mz.y);
     vz[r] = cmk<T>(kxz * mx.x + kyz * my.x + kzz * mz.x, kxz * mx.y + kyz * my.y + kzz * mz.y);
   }
-  // the inverse transform reads natural order: undo the bit reversal
-  V t[PZ];
-#pragma unroll
-  for (int k = 0; k < PZ; ++k) t[k] = vx[bitrev<PZ>(k)];
-  reg_fft<T, PZ, true>(t);
-#pragma unroll
-  for (int z = 0; z < PZ / 2; ++z)
-    if (z < a.nz) col[z * zs] = t[bitrev<PZ>(z)];
-#pragma unroll
-  for (int k = 0; k < PZ; ++k) t[k] = vy[bitrev<PZ>(k)];
-  reg_fft<T, PZ, true>(t);
-#pragma unroll
-  for (int z = 0; z < PZ / 2; ++z)
-    if (z < a.nz) col[cs + z * zs] = t[bitrev<PZ>(z)];
-#pragma unroll
-  for (int k = 0; k < PZ; ++k) t[k] = vz[bitrev<PZ>(k)];
-  reg_fft<T, PZ, true>(t);
-#pragma unroll
-  for (int z = 0; z < PZ / 2; ++z)
-    if (z < a.nz) col[2 * cs + z * zs] = t[bitrev<PZ>(z)];
+  zcol_inverse_store<T, PZ, Q>(vx, col, zs, a.nz, q);
+  zcol_inverse_store<T, PZ, Q>(vy, col + cs, zs, a.nz, q);
+  zcol_inverse_store<T, PZ, Q>(vz, col + 2 * cs, zs, a.nz, q);
+}
+
+// W > 1: ask the register allocator for at least W waves per SIMD
+template <typename T, int PZ, int Q, int W>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k4_fftz_mul_w(
+    Z4Args<T> a) {
+  fftz_mul_body<T, PZ, Q>(a);
+}
+template <typename T, int PZ, int Q>
+__global__ __launch_bounds__(256) void k4_fftz_mul(Z4Args<T> a) {
+  fftz_mul_body<T, PZ, Q>(a);
 }
 
 // ------------------------------------------------------------ dispatch --
@@ -413,14 +573,39 @@ void launch_m4(int L, dim3 g, int thr, size_t lds, hipStream_t st, const M4Args<
   }
 }
 
+template <typename T, int PZ, int Q, int W>
+static bool lzw(int q, int w, dim3 g, int thr, hipStream_t st, const Z4Args<T>& a) {
+  if constexpr (zreg_waves_ok((int)sizeof(T), PZ, Q, W)) {
+    if (q == Q && w == W) {
+      if constexpr (W == 1)
+        hipLaunchKernelGGL((k4_fftz_mul<T, PZ, Q>), g, dim3(thr), 0, st, a);
+      else
+        hipLaunchKernelGGL((k4_fftz_mul_w<T, PZ, Q, W>), g, dim3(thr), 0, st, a);
+      return true;
+    }
+  }
+  return false;
+}
+
+template <typename T, int PZ>
+static void lz(int q, int w, dim3 g, int thr, hipStream_t st, const Z4Args<T>& a) {
+  (void)(lzw<T, PZ, 1, 1>(q, w, g, thr, st, a) || lzw<T, PZ, 1, 2>(q, w, g, thr, st, a) ||
+         lzw<T, PZ, 1, 4>(q, w, g, thr, st, a) || lzw<T, PZ, 2, 1>(q, w, g, thr, st, a) ||
+         lzw<T, PZ, 2, 2>(q, w, g, thr, st, a) || lzw<T, PZ, 2, 4>(q, w, g, thr, st, a) ||
+         lzw<T, PZ, 4, 1>(q, w, g, thr, st, a) || lzw<T, PZ, 4, 2>(q, w, g, thr, st, a) ||
+         lzw<T, PZ, 4, 4>(q, w, g, thr, st, a));
+}
+
+// The plan admits only (PZ, q, w) with zreg_waves_ok, so a launch is made.
 template <typename T>
-void launch_z4(int PZ, dim3 g, int thr, size_t lds, hipStream_t st, const Z4Args<T>& a) {
+void launch_z4(int PZ, int q, int w, dim3 g, int thr, hipStream_t st, const Z4Args<T>& a) {
   switch (PZ) {
-    case 2: hipLaunchKernelGGL((k4_fftz_mul<T, 2>), g, dim3(thr), lds, st, a); break;
-    case 4: hipLaunchKernelGGL((k4_fftz_mul<T, 4>), g, dim3(thr), lds, st, a); break;
-    case 8: hipLaunchKernelGGL((k4_fftz_mul<T, 8>), g, dim3(thr), lds, st, a); break;
-    case 16: hipLaunchKernelGGL((k4_fftz_mul<T, 16>), g, dim3(thr), lds, st, a); break;
-    case 32: hipLaunchKernelGGL((k4_fftz_mul<T, 32>), g, dim3(thr), lds, st, a); break;
+    case 2: lz<T, 2>(q, w, g, thr, st, a); break;
+    case 4: lz<T, 4>(q, w, g, thr, st, a); break;
+    case 8: lz<T, 8>(q, w, g, thr, st, a); break;
+    case 16: lz<T, 16>(q, w, g, thr, st, a); break;
+    case 32: lz<T, 32>(q, w, g, thr, st, a); break;
+    case 64: lz<T, 64>(q, w, g, thr, st, a); break;
   }
 }
 
@@ -428,7 +613,7 @@ void launch_z4(int PZ, dim3 g, int thr, size_t lds, hipStream_t st, const Z4Args
   template void launch_y4<T>(int, bool, dim3, int, size_t, hipStream_t, const Y4Args<T>&);  \
   template void launch_x4<T>(int, bool, dim3, int, size_t, hipStream_t, const X4Args<T>&);  \
   template void launch_m4<T>(int, dim3, int, size_t, hipStream_t, const M4Args<T>&);        \
-  template void launch_z4<T>(int, dim3, int, size_t, hipStream_t, const Z4Args<T>&);
+  template void launch_z4<T>(int, int, int, dim3, int, hipStream_t, const Z4Args<T>&);
 INST(float)
 INST(double)
 

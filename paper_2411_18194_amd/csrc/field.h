@@ -49,6 +49,7 @@ struct FieldArgs {
   double* epart;
   double V;
   int nbx, nby, nb_pad;
+  int zc, nzc;                // z planes per thread, z chunks (nzc * zc >= nz)
 };
 
 template <typename T>

@@ -1,9 +1,11 @@
 // Fused effective field + torque + Runge-Kutta stage kernel.
 //
-// One thread owns an (x, y) column and marches along z with the z
-// neighbours kept in registers; x/y neighbours come from global memory
+// One thread owns zc cells of an (x, y) column and marches along z with the
+// z neighbours kept in registers; x/y neighbours come from global memory
 // through L1/L2 (a 64x4 tile per block, blocks remapped so neighbouring
-// tiles share an XCD's L2).  Per cell and sublattice it forms
+// tiles share an XCD's L2).  Shorter marches (small zc) give more waves to
+// hide the latency of the dependent loads; longer ones re-read fewer
+// z neighbours.  Per cell and sublattice it forms
 //   B = B_demag + exchange (Eq. 3: 2A11/Ms lap m, A12/Ms lap m', 4A0/(Ms a^2) m')
 //     + interfacial DMI + uniaxial/cubic anisotropy + Zeeman + B_mel (Eq. 9)
 // and the torque tau = LLG (Eq. 2) + Zhang-Li, then, in a Runge-Kutta
@@ -52,9 +54,13 @@ template <typename T, int NSUB, bool EVAL>
 __global__ __launch_bounds__(256) void k_field(const FieldArgs<T> a) {
   if (ctrl_stopped(a.ctrl)) return;
   const int w = xcd_remap(blockIdx.x, a.nb_pad);
-  if (w >= a.nbx * a.nby) return;
-  const int x = (w % a.nbx) * kTileX + (int)(threadIdx.x % kTileX);
-  const int y = (w / a.nbx) * kTileY + (int)(threadIdx.x / kTileX);
+  const int ntile = a.nbx * a.nby;
+  if (w >= ntile * a.nzc) return;
+  const int tile = w % ntile;
+  const int z0 = (w / ntile) * a.zc;
+  const int z1 = min(a.nz, z0 + a.zc);
+  const int x = (tile % a.nbx) * kTileX + (int)(threadIdx.x % kTileX);
+  const int y = (tile / a.nbx) * kTileY + (int)(threadIdx.x / kTileX);
   const bool in = x < a.nx && y < a.ny;
   const long N = a.N;
   const long N3 = 3 * N;
@@ -90,14 +96,15 @@ __global__ __launch_bounds__(256) void k_field(const FieldArgs<T> a) {
     T cur[NSUB][3], zm[NSUB][3], zp[NSUB][3];
     const long col = (long)y * a.nx + x;
     const long plane = (long)a.nx * a.ny;
+    const long i0 = (long)z0 * plane + col;
 #pragma unroll
     for (int s = 0; s < NSUB; ++s)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        cur[s][c] = m[s * N3 + c * N + col];
-        zm[s][c] = cur[s][c];
+        cur[s][c] = m[s * N3 + c * N + i0];
+        zm[s][c] = z0 > 0 ? m[s * N3 + c * N + i0 - plane] : cur[s][c];
       }
-    for (int z = 0; z < a.nz; ++z) {
+    for (int z = z0; z < z1; ++z) {
       const long i = (long)z * plane + col;
 #pragma unroll
       for (int s = 0; s < NSUB; ++s)
@@ -467,6 +474,8 @@ __global__ void k_control(Ctrl* c, Table<T>* tbl, const double* errpart, int ner
         c->sample_pending = 1;
         c->sample_k += 1;
         c->t_next = c->t0 + (double)c->sample_k * c->sample_every;
+        // an output time a few ulp short of t_end is t_end itself
+        if (c->t_next >= c->t_end - 1e-9 * (c->t_end - c->t0)) c->t_next = c->t_end;
       }
       if (c->t >= c->t_end) c->done = 1;
     }

@@ -37,6 +37,10 @@ struct GridBase {
   virtual int run(double t_end, const mmp_run_opts* o, mmp_run_info* info) = 0;
   virtual long long bytes() const = 0;
   virtual int tensor(double* n6) = 0;
+  virtual int get_plan(mmp_plan* out) = 0;
+  virtual int set_plan(const mmp_plan* in) = 0;
+  virtual int autotune(mmp_plan* out) = 0;
+  virtual int set_graphs(bool on) = 0;
   // non-blocking adaptive run used by the server: begin, enqueue chunks of
   // attempts (each followed by an async controller read-back and an event),
   // poll for completion

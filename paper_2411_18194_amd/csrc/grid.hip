@@ -2,10 +2,31 @@
 // of Dormand-Prince steps whose control lives on the device.
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "grid.h"
 
 namespace mmp {
+
+// Plans chosen by the autotuner, per (nx, ny, nz, real bytes, demag on,
+// device); new grids of a tuned shape start from the tuned plan.
+using PlanKey = std::tuple<int, int, int, int, int, int>;
+struct TunedPlan {
+  DemagPlan demag;
+  double demag_ms;
+  int field_zc;
+  double field_ms;
+};
+static std::mutex g_plan_mu;
+static std::map<PlanKey, TunedPlan> g_plans;
+
+static int current_device() {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  return dev;
+}
 
 template <typename T>
 struct Buf {
@@ -58,6 +79,7 @@ struct Grid final : GridBase {
   }
 
   void free_all() {
+    drop_graphs();
     for (auto* b : {&y[0], &y[1], &sa, &sb, &u[0], &u[1], &v[0], &v[1], &usa, &usb, &vsa, &vsb,
                     &eps, &sig, &Bd, &gax, &K})
       b->release();
@@ -67,6 +89,7 @@ struct Grid final : GridBase {
     dtbl.release();
     dctrl.release();
     S1.release(); S2.release(); tw.release();
+    plan = DemagPlan{};
     allocated = false;
     demag_built = false;
   }
@@ -96,30 +119,38 @@ struct Grid final : GridBase {
       rc |= eps.alloc(6 * (size_t)N);
       rc |= sig.alloc(6 * (size_t)N);
     }
+    // partial sums for the smallest z chunk (one plane per thread)
     const int nbx = (nx + kTileX - 1) / kTileX, nby = (ny + kTileY - 1) / kTileY;
-    nblk = nbx * nby;
-    nb_pad = round_up(nblk, 8);
-    rc |= errpart.alloc(nb_pad);
-    rc |= epart.alloc((size_t)nb_pad * kNE);
+    const int nb_max = round_up(nbx * nby * nz, 8);
+    rc |= errpart.alloc(nb_max);
+    rc |= epart.alloc((size_t)nb_max * kNE);
     rc |= eout.alloc(kNE);
     nsamp_blk = (int)std::min<long>(256, (N + 255) / 256);
     rc |= spart.alloc((size_t)nsamp_blk * 6);
     rc |= elpart.alloc((N + 255) / 256);
     rc |= dtbl.alloc(1);
     rc |= dctrl.alloc(1);
+    bool cached = false;
+    DemagPlan np;
+    {
+      std::lock_guard<std::mutex> lk(g_plan_mu);
+      auto it = g_plans.find(plan_key());
+      if (it != g_plans.end()) {
+        np = it->second.demag;
+        tuned_ms = it->second.demag_ms;
+        field_zc = it->second.field_zc;
+        field_ms = it->second.field_ms;
+        cached = true;
+      }
+    }
     if (p.demag) {
-      if (demag_plan(nx, ny, nz, (int)sizeof(T), &plan) != 0) {
+      if (!cached && demag_plan(nx, ny, nz, (int)sizeof(T), nullptr, &np) != 0) {
         set_error("demag pad exceeds 4096 along an axis");
         return MMP_E_ARG;
       }
       rc |= Bd.alloc(3 * (size_t)N);
-      rc |= S1.alloc(plan.s1_elems);
-      rc |= S2.alloc(plan.s2_elems);
-      rc |= K.alloc(plan.k_elems);
-      rc |= tw.alloc((size_t)2 * (plan.Px + plan.Py) + plan.Pz);
-      db.S1 = S1.p; db.S2 = S2.p; db.K = K.p; db.Bd = Bd.p;
-      db.twx = tw.p; db.twy = tw.p + plan.Px; db.twz = tw.p + plan.Px + plan.Py;
-      db.tw4x = db.twz + plan.Pz; db.tw4y = db.tw4x + plan.Px;
+      db.Bd = Bd.p;
+      if (!rc) rc |= install_plan(np);
     }
     if (rc) {
       set_error("device allocation failed");
@@ -185,6 +216,277 @@ struct Grid final : GridBase {
     s.Ms_d = Ms; s.Ku1_d = b.Ku1; s.Ku2_d = b.Ku2; s.Kc1_d = b.Kc1; s.B1_d = b.B1; s.B2_d = b.B2;
   }
 
+  // FFT buffers for plan np; a change of pads reallocates them and marks
+  // the kernel spectrum for a rebuild.
+  int install_plan(const DemagPlan& np) {
+    drop_graphs();
+    const bool same = S1.p && np.Px == plan.Px && np.Py == plan.Py && np.Pz == plan.Pz &&
+                      np.s1_elems == plan.s1_elems && np.s2_elems == plan.s2_elems;
+    if (!same) {
+      if (stream) MMP_HIP_TRY(hipStreamSynchronize(stream));
+      S1.release(); S2.release(); K.release(); tw.release();
+      int rc = 0;
+      rc |= S1.alloc(np.s1_elems);
+      rc |= S2.alloc(np.s2_elems);
+      rc |= K.alloc(np.k_elems);
+      rc |= tw.alloc((size_t)2 * (np.Px + np.Py) + np.Pz);
+      if (rc) {
+        S1.release(); S2.release(); K.release(); tw.release();
+        plan = DemagPlan{};
+        set_error("device allocation failed");
+        return MMP_E_NOMEM;
+      }
+      demag_built = false;
+      k1_valid = false;
+    }
+    plan = np;
+    set_demag_ptrs(db, S1.p, S2.p, K.p, tw.p, plan);
+    return 0;
+  }
+
+  static void set_demag_ptrs(DemagBufs<T>& b, cpx<T>* s1, cpx<T>* s2, T* k, cpx<T>* t,
+                             const DemagPlan& pl) {
+    b.S1 = s1; b.S2 = s2; b.K = k;
+    b.twx = t; b.twy = t + pl.Px; b.twz = t + pl.Px + pl.Py;
+    b.tw4x = b.twz + pl.Pz; b.tw4y = b.tw4x + pl.Px;
+  }
+
+  void build_all_twiddles(const DemagBufs<T>& b, const DemagPlan& pl) {
+    build_twiddles<T>(b.twx, pl.Px, stream);
+    build_twiddles<T>(b.twy, pl.Py, stream);
+    build_twiddles<T>(b.twz, pl.Pz, stream);
+    build_twiddles4<T>(b.tw4x, pl.Px, stream);
+    build_twiddles4<T>(b.tw4y, pl.Py, stream);
+  }
+
+  // twiddles and the transformed kernel for the current pads
+  int build_demag() {
+    double* n6 = nullptr;
+    MMP_HIP_TRY(hipMalloc(&n6, 6 * (size_t)N * sizeof(double)));
+    build_all_twiddles(db, plan);
+    const int rc = demag_kernel_build<T>(plan, d[0], d[1], d[2], n6, db.K, stream);
+    (void)hipFree(n6);
+    if (rc) {
+      set_error("demag kernel build failed");
+      return MMP_E_HIP;
+    }
+    demag_built = true;
+    return 0;
+  }
+
+  // ------------------------------------------------------------- plan --
+  double tuned_ms = 0.0, field_ms = 0.0;
+  int field_zc = 0;  // z planes per field-kernel thread (0: not chosen yet)
+
+  PlanKey plan_key() const {
+    return PlanKey(nx, ny, nz, (int)sizeof(T), p.demag ? 1 : 0, current_device());
+  }
+
+  // enough waves to cover the chip a few times over, but marches of at
+  // least a few planes so that z neighbours are reused
+  int default_field_zc() const {
+    const long cols = (long)((nx + kTileX - 1) / kTileX) * ((ny + kTileY - 1) / kTileY) * 4;
+    int zc = nz;
+    while (zc > 4 && cols * ((nz + zc - 1) / zc) < 8192) zc = (zc + 1) / 2;
+    return zc;
+  }
+
+  void set_field_zc(int zc) {
+    field_zc = std::max(1, std::min(zc, nz));
+    fa.zc = field_zc;
+    fa.nzc = (nz + field_zc - 1) / field_zc;
+    nblk = fa.nbx * fa.nby * fa.nzc;
+    nb_pad = round_up(nblk, 8);
+    fa.nb_pad = nb_pad;
+    drop_graphs();
+  }
+
+  int get_plan(mmp_plan* o) override {
+    if (!params_set) {
+      set_error("no plan: set parameters first");
+      return MMP_E_STATE;
+    }
+    const uint32_t ss = o->struct_size;
+    std::memset(o, 0, sizeof(*o));
+    o->struct_size = ss;
+    if (p.demag) {
+      o->pad[0] = plan.Px; o->pad[1] = plan.Py; o->pad[2] = plan.Pz;
+      o->x_rows[0] = plan.tyf; o->x_rows[1] = plan.tyi;
+      o->y_lines[0] = plan.nlyf; o->y_lines[1] = plan.nlyi;
+      o->xy_cols = plan.nk;
+      o->z_cols = plan.tk;
+      o->z_lanes = plan.zq; o->z_waves = plan.zw; o->z_threads = plan.zt;
+      o->kinds = (plan.p2x ? 1u : 0u) | (plan.p2y ? 2u : 0u) | (plan.p2z ? 4u : 0u);
+      o->demag_ms = tuned_ms;
+    }
+    o->field_zplanes = field_zc;
+    o->field_ms = field_ms;
+    return 0;
+  }
+
+  int set_plan(const mmp_plan* in) override {
+    if (!params_set) {
+      set_error("no plan: set parameters first");
+      return MMP_E_STATE;
+    }
+    if (in->field_zplanes < 1 || in->field_zplanes > nz) {
+      set_error("field_zplanes must be in 1..nz");
+      return MMP_E_ARG;
+    }
+    if (p.demag) {
+      DemagPlan np;
+      if (demag_plan(nx, ny, nz, (int)sizeof(T), in->pad, &np) != 0) {
+        set_error("unsupported pads: each must be 1 for a single cell, else even, 7-smooth, "
+                  ">= 2n-1 and <= 4096");
+        return MMP_E_ARG;
+      }
+      np.tyf = in->x_rows[0]; np.tyi = in->x_rows[1];
+      np.nlyf = in->y_lines[0]; np.nlyi = in->y_lines[1];
+      np.nk = in->xy_cols;
+      np.tk = in->z_cols;
+      if (np.p2z) { np.zq = in->z_lanes; np.zw = in->z_waves; np.zt = in->z_threads; }
+      if (demag_plan_check(np, (int)sizeof(T)) != 0) {
+        set_error("plan launch shape outside the kernels' limits");
+        return MMP_E_ARG;
+      }
+      int rc = install_plan(np);
+      if (!rc && !demag_built) rc = build_demag();
+      if (rc) return rc;
+      tuned_ms = 0.0;
+    }
+    if (in->field_zplanes != field_zc) field_ms = 0.0;
+    set_field_zc(in->field_zplanes);
+    return 0;
+  }
+
+  // mean time of one field-kernel stage (stage 2 on scratch buffers, with a
+  // controller of its own so a finished run does not skip the launches)
+  double time_field(int zc, Ctrl* tctrl, int reps) {
+    set_field_zc(zc);
+    FieldArgs<T> a = fa;
+    a.stage = 2;
+    a.fuse2 = 0;
+    a.ctrl = tctrl;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1.0;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return -1.0; }
+    double ms = -1.0;
+    launch_field<T>(a, false, stream, nullptr);
+    if (hipEventRecord(e0, stream) == hipSuccess) {
+      for (int r = 0; r < reps; ++r) launch_field<T>(a, false, stream, nullptr);
+      float f = 0.f;
+      if (hipGetLastError() == hipSuccess && hipEventRecord(e1, stream) == hipSuccess &&
+          hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&f, e0, e1) == hipSuccess)
+        ms = (double)f / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms;
+  }
+
+  int tune_field() {
+    Buf<Ctrl> tc;
+    if (tc.alloc(1)) { set_error("device allocation failed"); return MMP_E_NOMEM; }
+    Ctrl c{};
+    c.h = 1e-15;
+    MMP_HIP_TRY(hipMemcpy(tc.p, &c, sizeof(c), hipMemcpyHostToDevice));
+    const int reps = N >= (1L << 22) ? 5 : N >= (1L << 16) ? 20 : 50;
+    int best = field_zc;
+    double bt = -1.0;
+    for (int zc = 1;; zc *= 2) {
+      const int z = std::min(zc, nz);
+      const double t = time_field(z, tc.p, reps);
+      if (t > 0.0 && (bt < 0.0 || t < bt)) { bt = t; best = z; }
+      if (z == nz) break;
+    }
+    set_field_zc(best);
+    field_ms = bt > 0.0 ? bt : 0.0;
+    return 0;
+  }
+
+  int autotune(mmp_plan* out) override {
+    if (!params_set) {
+      set_error("autotune needs parameters");
+      return MMP_E_STATE;
+    }
+    if (p.demag) {
+      const int rc = tune_demag();
+      if (rc) return rc;
+    }
+    MMP_HIP_TRY(hipStreamSynchronize(stream));
+    if (int rc = tune_field()) return rc;
+    {
+      std::lock_guard<std::mutex> lk(g_plan_mu);
+      g_plans[plan_key()] = {plan, tuned_ms, field_zc, field_ms};
+    }
+    return out ? get_plan(out) : 0;
+  }
+
+  int tune_demag() {
+    auto pads_for = [](int n, int* c) {
+      int k = 0;
+      c[k++] = smooth_pad(n);
+      if (n > 1) {
+        int q = 1;
+        while (q < 2 * n - 1) q *= 2;
+        if (q != c[0] && q <= 4096) c[k++] = q;
+      }
+      return k;
+    };
+    int cx[2], cy[2], cz[2];
+    const int nxc = pads_for(nx, cx), nyc = pads_for(ny, cy), nzc = pads_for(nz, cz);
+    const T ms0 = (T)p.sub[0].Ms, ms1 = (T)(p.nsub == 2 ? p.sub[1].Ms : 0.0);
+    MMP_HIP_TRY(hipStreamSynchronize(stream));
+    DemagPlan best{};
+    double best_ms = -1.0;
+    for (int i = 0; i < nxc; ++i)
+      for (int j = 0; j < nyc; ++j)
+        for (int k = 0; k < nzc; ++k) {
+          const int pads[3] = {cx[i], cy[j], cz[k]};
+          DemagPlan c;
+          if (demag_plan(nx, ny, nz, (int)sizeof(T), pads, &c) != 0) continue;
+          const bool cur = c.Px == plan.Px && c.Py == plan.Py && c.Pz == plan.Pz;
+          DemagBufs<T> tb = db;
+          Buf<cpx<T>> s1, s2, twb;
+          Buf<T> kb;
+          if (cur) {
+            c.tyf = plan.tyf; c.tyi = plan.tyi; c.nlyf = plan.nlyf; c.nlyi = plan.nlyi;
+            c.nk = plan.nk; c.tk = plan.tk;
+            if (c.p2z == plan.p2z) { c.zq = plan.zq; c.zw = plan.zw; c.zt = plan.zt; }
+            if (demag_plan_check(c, (int)sizeof(T)) != 0) c = plan;
+          } else {
+            if (s1.alloc(c.s1_elems) || s2.alloc(c.s2_elems) || kb.alloc(c.k_elems) ||
+                twb.alloc((size_t)2 * (c.Px + c.Py) + c.Pz)) {
+              s1.release(); s2.release(); kb.release(); twb.release();
+              continue;  // this pad set does not fit next to the grid
+            }
+            set_demag_ptrs(tb, s1.p, s2.p, kb.p, twb.p, c);
+            MMP_HIP_TRY(hipMemsetAsync(kb.p, 0, c.k_elems * sizeof(T), stream));
+            build_all_twiddles(tb, c);
+          }
+          const double ms = demag_tune<T>(&c, tb, dtbl.p, ms0, ms1, p.nsub, stream);
+          const hipError_t e = hipStreamSynchronize(stream);
+          s1.release(); s2.release(); kb.release(); twb.release();
+          if (e != hipSuccess) {
+            set_error(std::string("autotune: ") + hipGetErrorString(e));
+            return MMP_E_HIP;
+          }
+          if (ms > 0.0 && (best_ms < 0.0 || ms < best_ms)) {
+            best_ms = ms;
+            best = c;
+          }
+        }
+    if (best_ms < 0.0) {
+      set_error("autotune: no candidate plan could be timed");
+      return MMP_E_HIP;
+    }
+    int rc = install_plan(best);
+    if (!rc && !demag_built) rc = build_demag();
+    if (rc) return rc;
+    tuned_ms = best_ms;
+    return 0;
+  }
+
   int apply_params() override {
     if (p.nsub == 2)
       for (int s = 0; s < 2; ++s)
@@ -213,20 +515,8 @@ struct Grid final : GridBase {
     }
     // demag kernel
     if (p.demag && !demag_built) {
-      double* n6 = nullptr;
-      MMP_HIP_TRY(hipMalloc(&n6, 6 * (size_t)N * sizeof(double)));
-      build_twiddles<T>(db.twx, plan.Px, stream);
-      build_twiddles<T>(db.twy, plan.Py, stream);
-      build_twiddles<T>(db.twz, plan.Pz, stream);
-      build_twiddles4<T>(db.tw4x, plan.Px, stream);
-      build_twiddles4<T>(db.tw4y, plan.Py, stream);
-      const int rc = demag_kernel_build<T>(plan, d[0], d[1], d[2], n6, db.K, stream);
-      (void)hipFree(n6);
-      if (rc) {
-        set_error("demag kernel build failed");
-        return MMP_E_HIP;
-      }
-      demag_built = true;
+      const int rc = build_demag();
+      if (rc) return rc;
     }
     // field kernel arguments
     FieldArgs<T> a{};
@@ -258,8 +548,8 @@ struct Grid final : GridBase {
     a.V = d[0] * d[1] * d[2];
     a.nbx = (nx + kTileX - 1) / kTileX;
     a.nby = (ny + kTileY - 1) / kTileY;
-    a.nb_pad = nb_pad;
     fa = a;
+    set_field_zc(field_zc > 0 ? field_zc : default_field_zc());
     // elastic arguments
     ElasticArgs<T> e{};
     e.nx = nx; e.ny = ny; e.nz = nz; e.nsub = p.nsub; e.N = N;
@@ -276,6 +566,7 @@ struct Grid final : GridBase {
     e.tbl = dtbl.p; e.ctrl = dctrl.p; e.eps = eps.p; e.sig = sig.p; e.epart = elpart.p;
     e.V = a.V; e.rho = p.rho;
     ea = e;
+    drop_graphs();
     k1_valid = false;
     params_set = true;
     return 0;
@@ -375,6 +666,71 @@ struct Grid final : GridBase {
     if (!fixed_mode) combine2();
   }
 
+  // ----------------------------------------------------------- graphs --
+  // kGraphAttempts attempts captured once per kind (fixed, adaptive,
+  // adaptive with sampling) and replayed; every kernel reads the step
+  // controller and the buffer table on the device, so a replay needs no
+  // new arguments.  Rebuilt whenever a kernel argument changes.
+  static constexpr int kGraphAttempts = 8;
+  hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
+  bool graphs_on = true;
+
+  void drop_graphs() {
+    for (auto& e : gexec)
+      if (e) {
+        (void)hipGraphExecDestroy(e);
+        e = nullptr;
+      }
+  }
+
+  // graphs need a capturable stream and stay out of the way of profiling
+  bool graphs_usable() const { return graphs_on && stream != nullptr && !prof.on; }
+
+  int graph_for(int kind, hipGraphExec_t* out) {
+    if (!gexec[kind]) {
+      hipGraph_t g = nullptr;
+      MMP_HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+      for (int i = 0; i < kGraphAttempts; ++i) attempt(kind == 0, kind == 2);
+      const hipError_t e = hipStreamEndCapture(stream, &g);
+      if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        set_error(std::string("graph capture: ") + hipGetErrorString(e));
+        return MMP_E_HIP;
+      }
+      const hipError_t e2 = hipGraphInstantiate(&gexec[kind], g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e2 != hipSuccess) {
+        gexec[kind] = nullptr;
+        set_error(std::string("graph instantiate: ") + hipGetErrorString(e2));
+        return MMP_E_HIP;
+      }
+    }
+    *out = gexec[kind];
+    return 0;
+  }
+
+  // n attempts: whole graphs of kGraphAttempts, the rest launched directly
+  int enqueue_attempts(bool fixed_mode, bool sampling, long long n) {
+    long long left = n;
+    if (graphs_usable() && n >= kGraphAttempts) {
+      hipGraphExec_t ge = nullptr;
+      const int kind = fixed_mode ? 0 : (sampling ? 2 : 1);
+      int rc = graph_for(kind, &ge);
+      if (rc) return rc;
+      for (; left >= kGraphAttempts; left -= kGraphAttempts)
+        MMP_HIP_TRY(hipGraphLaunch(ge, stream));
+    }
+    for (; left > 0; --left) attempt(fixed_mode, sampling);
+    MMP_HIP_TRY(hipGetLastError());
+    return 0;
+  }
+
+  int set_graphs(bool on) override {
+    graphs_on = on;
+    if (!on) drop_graphs();
+    return 0;
+  }
+
   int ensure_ready() {
     if (!params_set) { set_error("mmp_set_params has not been called"); return MMP_E_STATE; }
     if (!state_set) { set_error("mmp_set_state has not been called"); return MMP_E_STATE; }
@@ -430,8 +786,7 @@ struct Grid final : GridBase {
     init.fixed = 1; init.h = dt; init.t_end = 1e300; init.t_next = 1e300;
     init.max_attempts = n; init.tol = 0; init.dt_min = 0;
     if ((rc = begin_segment(init))) return rc;
-    for (long long i = 0; i < n; ++i) attempt(true, false);
-    MMP_HIP_TRY(hipGetLastError());
+    if ((rc = enqueue_attempts(true, false, n))) return rc;
     if (info) {
       Ctrl c{};
       if ((rc = read_ctrl(&c))) return rc;
@@ -477,6 +832,7 @@ struct Grid final : GridBase {
     const double every = o ? o->sample_every : 0.0;
     const int cap = o ? o->max_samples : 0;
     if (every > 0.0 && cap > samp_cap) {
+      drop_graphs();
       samp_t.release(); samp_m.release();
       if (samp_t.alloc(cap) || samp_m.alloc((size_t)cap * 6)) {
         set_error("device allocation failed");
@@ -489,6 +845,7 @@ struct Grid final : GridBase {
     init.t_end = t_end;
     init.sample_every = every > 0.0 ? every : 0.0;
     init.t_next = every > 0.0 ? cur.t + every : t_end;
+    if (init.t_next >= t_end - 1e-9 * (t_end - cur.t)) init.t_next = t_end;
     init.tol = p.tol > 0 ? p.tol : 1e-5;
     init.dt_min = p.dt_min > 0 ? p.dt_min : 1e-20;
     init.max_attempts = o ? o->max_steps : 0;
@@ -499,8 +856,7 @@ struct Grid final : GridBase {
     Ctrl c{};
     long long last = -1;
     while (true) {
-      for (int i = 0; i < chunk; ++i) attempt(false, sampling);
-      MMP_HIP_TRY(hipGetLastError());
+      if ((rc = enqueue_attempts(false, sampling, chunk))) return rc;
       if ((rc = read_ctrl(&c))) return rc;
       if (c.done || c.status) break;
       const long long made = c.steps + c.rejects;
@@ -604,7 +960,7 @@ struct Grid final : GridBase {
   }
 
   int run_chunk(int attempts) override {
-    for (int i = 0; i < attempts; ++i) attempt(false, false);
+    if (int rc = enqueue_attempts(false, false, attempts)) return rc;
     MMP_HIP_TRY(hipMemcpyAsync(hctrl, dctrl.p, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
     MMP_HIP_TRY(hipEventRecord(chunk_ev, stream));
     return 0;

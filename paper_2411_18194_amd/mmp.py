@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import time
 
 import numpy as np
 
@@ -89,10 +90,32 @@ class Result(C.Structure):
                 ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
 
 
+class Plan(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("pad", C.c_int32 * 3), ("x_rows", C.c_int32 * 2),
+                ("y_lines", C.c_int32 * 2), ("xy_cols", C.c_int32), ("z_cols", C.c_int32),
+                ("z_lanes", C.c_int32), ("z_waves", C.c_int32), ("z_threads", C.c_int32),
+                ("field_zplanes", C.c_int32), ("kinds", C.c_uint32), ("reserved", C.c_int32),
+                ("demag_ms", C.c_double), ("field_ms", C.c_double)]
+
+
+PLAN_KEYS = ("pad", "x_rows", "y_lines", "xy_cols", "z_cols", "z_lanes", "z_waves",
+             "z_threads", "field_zplanes")
+
+
+def _plan_dict(pl: Plan) -> dict:
+    d = {}
+    for k, _ in Plan._fields_[1:]:
+        if k == "reserved":
+            continue
+        v = getattr(pl, k)
+        d[k] = list(v) if hasattr(v, "__len__") else v
+    return d
+
+
 EXPORTS = ("mmp_grid_create", "mmp_grid_destroy", "mmp_set_params", "mmp_set_state",
            "mmp_get_state", "mmp_eval_heff", "mmp_step", "mmp_run_fixed", "mmp_run",
-           "mmp_set_stream", "mmp_synchronize", "mmp_grid_bytes", "mmp_get_demag_tensor",
-           "mmp_prof_enable", "mmp_prof_count", "mmp_prof_read", "mmp_prof_reset",
+           "mmp_set_stream", "mmp_set_graphs", "mmp_synchronize", "mmp_grid_bytes", "mmp_get_demag_tensor",
+           "mmp_get_plan", "mmp_set_plan", "mmp_autotune", "mmp_prof_enable", "mmp_prof_count", "mmp_prof_read", "mmp_prof_reset",
            "mmp_server_create", "mmp_submit", "mmp_poll", "mmp_server_destroy",
            "mmp_server_clock", "mmp_last_error")
 
@@ -120,9 +143,13 @@ def load(path: str = LIB_PATH):
         "mmp_run_fixed": ([vp, C.c_double, C.c_int64, C.POINTER(StepInfo)], C.c_int32),
         "mmp_run": ([vp, C.c_double, C.POINTER(RunOpts), C.POINTER(RunInfo)], C.c_int32),
         "mmp_set_stream": ([vp, vp], C.c_int32),
+        "mmp_set_graphs": ([vp, C.c_int32], C.c_int32),
         "mmp_synchronize": ([vp], C.c_int32),
         "mmp_grid_bytes": ([vp, C.POINTER(C.c_int64)], C.c_int32),
         "mmp_get_demag_tensor": ([vp, dp], C.c_int32),
+        "mmp_get_plan": ([vp, C.POINTER(Plan)], C.c_int32),
+        "mmp_set_plan": ([vp, C.POINTER(Plan)], C.c_int32),
+        "mmp_autotune": ([vp, C.POINTER(Plan)], C.c_int32),
         "mmp_prof_enable": ([vp, C.c_int32], C.c_int32),
         "mmp_prof_count": ([], C.c_int32),
         "mmp_prof_read": ([vp, C.c_int32, C.POINTER(C.c_char_p), dp, C.POINTER(C.c_int64)],
@@ -281,6 +308,10 @@ class Grid:
     def set_stream(self, stream_ptr):
         _check(self.lib.mmp_set_stream(self.h, C.c_void_p(stream_ptr)))
 
+    def set_graphs(self, on=True):
+        """Replay captured HIP graphs in the step loops (default on)."""
+        _check(self.lib.mmp_set_graphs(self.h, 1 if on else 0))
+
     def synchronize(self):
         _check(self.lib.mmp_synchronize(self.h))
 
@@ -294,6 +325,34 @@ class Grid:
         n6 = np.empty((6, nz, ny, nx))
         _check(self.lib.mmp_get_demag_tensor(self.h, _dptr(n6)))
         return n6
+
+    def plan(self) -> dict:
+        """The demag plan: pads and launch shapes (see mmp_plan)."""
+        pl = Plan(struct_size=C.sizeof(Plan))
+        _check(self.lib.mmp_get_plan(self.h, C.byref(pl)))
+        return _plan_dict(pl)
+
+    def set_plan(self, **changes) -> dict:
+        """Install the current plan with the given fields replaced."""
+        cur = self.plan()
+        cur.update(changes)
+        pl = Plan(struct_size=C.sizeof(Plan))
+        for k in PLAN_KEYS:
+            v = cur[k]
+            if isinstance(v, (list, tuple)):
+                arr = getattr(pl, k)
+                for i, x in enumerate(v):
+                    arr[i] = int(x)
+            else:
+                setattr(pl, k, int(v))
+        _check(self.lib.mmp_set_plan(self.h, C.byref(pl)))
+        return self.plan()
+
+    def autotune(self) -> dict:
+        """Time candidate pads and launch shapes and install the fastest."""
+        pl = Plan(struct_size=C.sizeof(Plan))
+        _check(self.lib.mmp_autotune(self.h, C.byref(pl)))
+        return _plan_dict(pl)
 
     def prof_enable(self, on=True):
         _check(self.lib.mmp_prof_enable(self.h, 1 if on else 0))
@@ -347,6 +406,17 @@ class Server:
         if rc == PENDING:
             return None
         return res
+
+    def wait(self, ticket, timeout=600.0, interval=1e-3):
+        """Poll until the request is done; returns its Result."""
+        t_end = time.monotonic() + timeout
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            if time.monotonic() > t_end:
+                raise MMPError(PENDING, f"request {ticket} not done after {timeout} s")
+            time.sleep(interval)
 
     def clock(self):
         return self.lib.mmp_server_clock(self.h)

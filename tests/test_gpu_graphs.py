@@ -1,0 +1,89 @@
+"""HIP-graph replay of the step loops against direct launches.
+
+Every kernel of an attempt reads the step controller and the stage buffer
+table from device memory, so replaying one captured graph must reproduce
+the directly launched sequence bit for bit.  Each check replays the graphs
+several times with direct work (an effective-field evaluation, host reads)
+in between and compares every replay with the direct result.
+"""
+import numpy as np
+import pytest
+
+from paper_2411_18194_amd import inputs, mmp
+
+pytestmark = pytest.mark.gpu
+
+
+def _pair(p, m, prec, u=None, v=None):
+    out = []
+    for on in (True, False):
+        g = mmp.Grid(p, prec)
+        g.set_graphs(on)
+        g.set_state(m, u, v)
+        out.append(g)
+    return out
+
+
+def _same(a, b):
+    sa, sb = a.get_state(), b.get_state()
+    for x, y in zip(sa[:3], sb[:3]):
+        assert np.array_equal(x, y)
+    assert sa[3] == sb[3] and sa[4] == sb[4]
+
+
+@pytest.mark.parametrize("prec", [mmp.FP32, mmp.FP64])
+@pytest.mark.parametrize("name", ["c2crop", "c3crop", "c4crop"])
+def test_fixed_steps_graph_replay(name, prec):
+    build = {"c2crop": inputs.config_c2_crop, "c3crop": inputs.config_c3_crop,
+             "c4crop": inputs.config_c4_crop}[name]
+    p, m = build()
+    dt = {"c2crop": inputs.c2_fixed_dt(), "c3crop": 2e-15, "c4crop": inputs.C4_FIXED_DT}[name]
+    a, b = _pair(p, m, prec)
+    for r, n in enumerate((8, 3, 17, 24)):
+        a.run_fixed(dt, n, sync=False)
+        b.run_fixed(dt, n, sync=False)
+        # direct work on the graph grid's stream between replays
+        a.eval_heff(mmp.T_ALL)
+        _same(a, b)
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("prec", [mmp.FP32, mmp.FP64])
+def test_adaptive_run_graph_replay(prec):
+    p, m = inputs.config_c1()
+    a, b = _pair(p, m, prec)
+    for t_end in (0.05e-9, 0.12e-9, 0.2e-9):
+        ia, ta, ma = a.run(t_end, sample_every=0.01e-9, max_samples=64)
+        ib, tb, mb = b.run(t_end, sample_every=0.01e-9, max_samples=64)
+        assert (ia.steps, ia.rejects) == (ib.steps, ib.rejects)
+        assert np.array_equal(ta, tb) and np.array_equal(ma, mb)
+        _same(a, b)
+        a.eval_heff(mmp.T_ALL)
+    a.close()
+    b.close()
+
+
+def test_server_matches_direct_run():
+    """Requests served concurrently (graph replay, own streams) give the same
+    result as the same relaxation run alone on a grid."""
+    reqs = [r for r in inputs.request_stream(seed=5, count=40) if
+            r["params"]["n"][0] * r["params"]["n"][1] * r["params"]["n"][2] <= 40000][:4]
+    assert len(reqs) >= 2
+    for r in reqs:
+        r["t_relax"] = 0.02e-9
+    srv = mmp.Server(hbm_budget=8 << 30, max_active=4, precision=mmp.FP32)
+    tickets = [srv.submit(r["params"], inputs.request_state(r), r["t_relax"]) for r in reqs]
+    res = [srv.wait(t) for t in tickets]
+    srv.close()
+    for r, out in zip(reqs, res):
+        assert out.status == 0
+        ns = r["params"]["nsub"]
+        g = mmp.Grid(r["params"], mmp.FP32, tol=r["tol"])
+        g.set_state(inputs.request_state(r))
+        info, _, _ = g.run(r["t_relax"])
+        m = g.get_state()[0].reshape(ns, 3, -1).mean(axis=2)
+        g.close()
+        assert out.steps == info.steps and out.rejects == info.rejects
+        got = np.array([[out.m_avg[s][c] for c in range(3)] for s in range(ns)])
+        assert np.allclose(got, m, rtol=0, atol=1e-12)

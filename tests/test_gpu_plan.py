@@ -1,0 +1,199 @@
+"""GPU parity of every demag plan variant, and the autotuner.
+
+The demag field of each plan (pads, launch shapes, z lanes) is compared with
+the oracle's demag field, same norm and bars as test_gpu_parity: max |dB|
+over max |B_ref|, FP64 <= 1e-12, FP32 <= 2e-6 on the FP32-rounded state.
+Any even 7-smooth pad >= 2n-1 gives the same linear convolution (the pad
+only has to hold the support of the tensor without wrap-around), so the
+oracle's field is the reference for all of them.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle.system import Problem
+from paper_2411_18194_amd import inputs, mmp
+
+pytestmark = pytest.mark.gpu
+
+TOL = {mmp.FP64: 1e-12, mmp.FP32: 2e-6}
+
+
+def relerr(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def _case(n, cell, seed):
+    p = inputs.base_params(n, cell)
+    p.update(Ms=[9e5], A11=[1.3e-11], alpha=[0.1], demag=True)
+    return p, inputs.smoothed_random_unit(inputs.rng(seed), 1, n, sigma=1.5)
+
+
+CASES = {
+    "pow2_z32": lambda: _case((32, 32, 16), (2e-9, 2e-9, 2e-9), 31),
+    "pow2_z64": lambda: _case((16, 8, 32), (2e-9, 3e-9, 1e-9), 32),
+    "pow2_z16": lambda: _case((8, 16, 8), (2e-9, 2e-9, 3e-9), 33),
+    "ragged3d": lambda: _case((37, 23, 5), (2e-9, 3e-9, 2.5e-9), 34),
+    "plane2d": lambda: _case((40, 32, 1), (3e-9, 3e-9, 2e-9), 35),
+}
+_ref = {}
+
+
+def reference(name):
+    if name not in _ref:
+        p, m = CASES[name]()
+        _ref[name] = (p, m, Problem(p).demag_field(m), Problem(p).demag_field(
+            np.asarray(m, np.float32).astype(np.float64)))
+    return _ref[name]
+
+
+def demag_err(g, name, prec):
+    p, m, ref64, ref32 = reference(name)
+    if prec == mmp.FP32:
+        g.set_state(np.asarray(m, np.float32).astype(np.float64))
+        ref = ref32
+    else:
+        g.set_state(m)
+        ref = ref64
+    b, _ = g.eval_heff(mmp.T_DEMAG)
+    return relerr(b, ref)
+
+
+def try_plan(g, **kw):
+    try:
+        g.set_plan(**kw)
+        return True
+    except mmp.MMPError as e:
+        assert e.code == -1, e
+        return False
+
+
+@pytest.mark.parametrize("prec", [mmp.FP32, mmp.FP64])
+@pytest.mark.parametrize("name", ["pow2_z32", "pow2_z64", "pow2_z16"])
+def test_register_z_variants(name, prec):
+    """Every built (lanes, waves, threads) variant of the register z pass."""
+    p, _, _, _ = reference(name)
+    g = mmp.Grid(p, prec)
+    assert g.plan()["kinds"] & 4
+    tried = {}
+    for q, w, t in itertools.product((1, 2, 4), (1, 2, 4), (64, 128, 256)):
+        if not try_plan(g, z_lanes=q, z_waves=w, z_threads=t):
+            continue
+        tried[(q, w, t)] = demag_err(g, name, prec)
+    g.close()
+    assert any(k[0] > 1 for k in tried), tried
+    bad = {k: v for k, v in tried.items() if not v <= TOL[prec]}
+    assert not bad, (name, prec, bad)
+
+
+@pytest.mark.parametrize("prec", [mmp.FP32, mmp.FP64])
+@pytest.mark.parametrize("name", ["pow2_z32", "ragged3d"])
+def test_xy_shapes(name, prec):
+    """Rows per x block and lines per y block, forward and inverse."""
+    p, _, _, _ = reference(name)
+    g = mmp.Grid(p, prec)
+    errs = {}
+    for rf, ri in ((2, 16), (4, 8), (8, 2), (16, 4)):
+        for lf, li in ((1, 64), (4, 2), (64, 1), (16, 16)):
+            if try_plan(g, x_rows=[rf, ri], y_lines=[lf, li]):
+                errs[(rf, ri, lf, li)] = demag_err(g, name, prec)
+    if name == "ragged3d":
+        for zc in (1, 4, 16, 64):
+            if try_plan(g, x_rows=[2, 2], y_lines=[1, 1], z_cols=zc):
+                errs[("z_cols", zc)] = demag_err(g, name, prec)
+    g.close()
+    assert len(errs) >= 6, errs
+    bad = {k: v for k, v in errs.items() if not v <= TOL[prec]}
+    assert not bad, (name, prec, bad)
+
+
+@pytest.mark.parametrize("prec", [mmp.FP32, mmp.FP64])
+def test_2d_column_shapes(prec):
+    p, _, _, _ = reference("plane2d")
+    g = mmp.Grid(p, prec)
+    errs = {}
+    for k in (1, 2, 8, 64):
+        if try_plan(g, xy_cols=k):
+            errs[k] = demag_err(g, "plane2d", prec)
+    g.close()
+    assert len(errs) >= 3
+    assert max(errs.values()) <= TOL[prec], errs
+
+
+@pytest.mark.parametrize("prec", [mmp.FP32, mmp.FP64])
+@pytest.mark.parametrize("pads", [(80, 48, 10), (128, 64, 16), (84, 50, 12), (128, 48, 16),
+                                  (80, 64, 10)])
+def test_pads(pads, prec):
+    """Smallest 7-smooth, power-of-two, larger 7-smooth and mixed pads."""
+    p, _, _, _ = reference("ragged3d")
+    g = mmp.Grid(p, prec)
+    pl = g.set_plan(pad=list(pads))
+    assert tuple(pl["pad"]) == pads
+    err = demag_err(g, "ragged3d", prec)
+    g.close()
+    assert err <= TOL[prec], (pads, err)
+
+
+def test_plan_rejections():
+    p, _, _, _ = reference("ragged3d")
+    g = mmp.Grid(p, mmp.FP32)
+    before = g.plan()
+    assert before["pad"] == [80, 48, 10]
+    for bad in ({"pad": [74, 48, 10]},      # 74 = 2 * 37 is not 7-smooth
+                {"pad": [72, 48, 10]},      # < 2n - 1
+                {"pad": [81, 48, 10]},      # odd
+                {"pad": [8192, 48, 10]},    # above 4096
+                {"x_rows": [32, 2]}, {"x_rows": [3, 2]}, {"y_lines": [0, 1]},
+                {"y_lines": [128, 1]}, {"z_cols": 128}, {"field_zplanes": 0},
+                {"field_zplanes": 6}):
+        assert not try_plan(g, **bad), bad
+        assert g.plan() == before
+    g.close()
+    q, _, _, _ = reference("pow2_z32")
+    g = mmp.Grid(q, mmp.FP64)
+    assert not try_plan(g, z_lanes=1)        # 32 FP64 points x 3 per lane: not built
+    assert not try_plan(g, z_lanes=8)
+    assert not try_plan(g, z_threads=512)
+    g.close()
+
+
+@pytest.mark.parametrize("prec", [mmp.FP32, mmp.FP64])
+def test_field_zplanes(prec):
+    """The field kernel's z march length does not change a bit of the result."""
+    p, m = inputs.config_c2_crop()
+    g = mmp.Grid(p, prec)
+    g.set_state(m)
+    outs = []
+    for zc in (1, 2, 3, 4):
+        g.set_plan(field_zplanes=zc)
+        b, e = g.eval_heff(mmp.T_ALL | mmp.T_ZL | mmp.OUT_TORQUE)
+        g.set_state(m)
+        g.run_fixed(inputs.c2_fixed_dt(), 3)
+        outs.append((b, g.get_state()[0]))
+        g.set_state(m)
+    g.close()
+    for b, s in outs[1:]:
+        assert np.array_equal(b, outs[0][0]) and np.array_equal(s, outs[0][1])
+
+
+@pytest.mark.parametrize("prec", [mmp.FP32, mmp.FP64])
+def test_autotune(prec):
+    p, m = inputs.config_c2_crop()
+    P = Problem(p)
+    if prec == mmp.FP32:
+        m = np.asarray(m, np.float32).astype(np.float64)
+    g = mmp.Grid(p, prec)
+    g.set_state(m)
+    pl = g.autotune()
+    assert pl["demag_ms"] > 0 and pl["field_ms"] > 0
+    b, _ = g.eval_heff(mmp.T_ALL)
+    assert relerr(b, P.eval_heff(m)) <= TOL[prec], pl
+    # the state is untouched by the timed launches
+    m2 = g.get_state()[0]
+    assert np.array_equal(m2.reshape(np.shape(m)), m)
+    g.close()
+    # a new grid of the same shape and precision starts from the tuned plan
+    g2 = mmp.Grid(p, prec)
+    assert g2.plan() == pl
+    g2.close()

@@ -9,7 +9,9 @@
 * With no damping, no coupling and no drive the elastic energy
   1/2 sigma:eps + 1/2 rho v^2 of an interior pulse is conserved.
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -36,11 +38,17 @@ def test_derivative_polynomial_exactness():
     assert el.deriv(np.ones((1, 3)), 0, 1.0).max() == 0.0
 
 
+with open(os.path.join(os.path.dirname(__file__), "golden", "paper_printed.json")) as _fh:
+    NIO = json.load(_fh)["nio_racetrack"]
+
+
 def _nio_bar(nx, dx):
     p = inputs.base_params((nx, 1, 1), (dx, dx, dx))
-    # Table 1: rho, C11, C12, C44 of NiO; magnetisation switched off
-    p.update(Ms=[0.0], elastic=dict(rho=6853.0, C11=330e9, C12=60e9, C44=110e9,
-                                    eta=0.0, trac_amp=0.3e9, trac_freq=8e9))
+    # the paper's NiO table: rho, C11, C12, C44; magnetisation switched off
+    p.update(Ms=[0.0], elastic=dict(rho=NIO["rho_kg_m3"], C11=NIO["C11_Pa"], C12=NIO["C12_Pa"],
+                                    C44=NIO["C44_Pa"], eta=0.0,
+                                    trac_amp=NIO["traction_amplitude_Pa"],
+                                    trac_freq=NIO["traction_frequency_Hz"]))
     return p
 
 
@@ -53,7 +61,7 @@ def test_printed_racetrack_numbers():
     y = P.initial_state(m)
     # one period of the 8 GHz drive, then switch it off and let it travel
     dt = 1e-13
-    nper = int(round(1 / 8e9 / dt))
+    nper = int(round(NIO["traction_periods"] / NIO["traction_frequency_Hz"] / dt))
     y, t = P.run_fixed(y, 0.0, dt, nper)
     P.p = dict(p)
     P.p["elastic"] = dict(p["elastic"], trac_amp=0.0)
@@ -66,12 +74,16 @@ def test_printed_racetrack_numbers():
     x = (np.arange(nx) + 0.5) * dx
     front = x[np.nonzero(np.abs(uz) > 0.01 * np.abs(uz).max())[0].max()]
     speed = front / t
-    c_shear = math.sqrt(110e9 / 6853.0)
-    assert c_shear == pytest.approx(4006, rel=1e-3)        # "about 4 km/s"
+    c_shear = math.sqrt(NIO["C44_Pa"] / NIO["rho_kg_m3"])
+    # "about 4 km/s": the printed speed to its one significant digit
+    assert c_shear == pytest.approx(NIO["pulse_speed_m_s_about"], rel=0.05)
     assert speed == pytest.approx(c_shear, rel=0.06)
+    assert speed == pytest.approx(NIO["pulse_speed_m_s_about"], rel=0.1)
     # strain amplitude in the travelling pulse: sigma/(2 C44) ~ 0.136 %
-    assert np.abs(eps_xz).max() == pytest.approx(0.3e9 / (2 * 110e9), rel=0.06)
-    assert abs(np.abs(eps_xz).max() * 100 - 0.14) < 0.01   # "approximately 0.14 %"
+    amp = NIO["traction_amplitude_Pa"] / (2 * NIO["C44_Pa"])
+    assert np.abs(eps_xz).max() == pytest.approx(amp, rel=0.06)
+    # "approximately 0.14 %"
+    assert abs(np.abs(eps_xz).max() * 100 - NIO["strain_amplitude_percent_about"]) < 0.01
 
 
 def test_energy_conservation_free_pulse():

@@ -15,7 +15,9 @@
   current and no time dependence.
 * Zhang-Li: a uniform state feels no spin-transfer torque.
 """
+import json
 import math
+import os
 from fractions import Fraction as F
 
 import numpy as np
@@ -28,10 +30,13 @@ from paper_2411_18194_amd import inputs
 
 
 def test_order_conditions():
+    with open(os.path.join(os.path.dirname(__file__), "golden", "paper_printed.json")) as fh:
+        printed = json.load(fh)["rk_solvers"]["Dormand-Prince"]
     c, A, b, bs = rk.C, rk.A, rk.B5, rk.B4
     for i in range(1, 7):
         assert sum(A[i]) == c[i]
-    for w, order in ((b, 5), (bs, 4)):
+    # the solver table prints convergence order 5 and error-estimate order 4
+    for w, order in ((b, printed[0]), (bs, printed[1])):
         s = len(w)
         cc = c[:s]
 
@@ -146,3 +151,22 @@ def test_zhang_li_uniform_zero():
     u = tq.drift_velocity(0.5, (1e12, 0, 0), 4e5)
     assert np.abs(tq.zhang_li_torque(m, u, 0.01, 0.1, (1e-9,) * 3)).max() == 0.0
     assert u[0] == pytest.approx(0.5 * 9.2740100783e-24 * 1e12 / (1.602176634e-19 * 4e5))
+
+
+def test_output_times_merge_with_the_end():
+    """Sampling every 1e-11 s up to 5e-11 s: 5 * 1e-11 is not 5e-11 in
+    floating point, yet the run ends at t_end with one sample per output time
+    (the last one at t_end) instead of a spurious ~1e-26 s landing step."""
+    p = inputs.base_params((1, 1, 1), (2e-9,) * 3)
+    p.update(Ms=[8e5], A11=[0.0], alpha=[0.1], B_ext=(0.0, 0.0, 0.1), demag=False)
+    P = Problem(p)
+    m = np.zeros((1, 3, 1, 1, 1))
+    m[0, 0] = 1.0
+    every, t_end = 1e-11, 0.05e-9
+    assert 5 * every != t_end
+    y, t, info, samples = P.run(P.initial_state(m), 0.0, t_end, sample_every=every,
+                                sample=lambda y: y[0].copy())
+    assert t == t_end
+    ts = [s[0] for s in samples]
+    assert len(ts) == 6 and ts[-1] == t_end
+    assert np.allclose(ts, np.arange(6) * every, rtol=1e-12, atol=0)
