@@ -236,6 +236,79 @@ def run_serve(count, max_active=8):
             "arrival_rate_0.8_capacity_per_s": round(200.0 / scale, 3)}
 
 
+# rocprofv3 kernel names -> kernel classes of the library's event profiler
+KERNEL_CLASSES = (("k4_fftx_fwd", "fftx_fwd"), ("k_fftx_fwd", "fftx_fwd"),
+                  ("k4_fftx_inv", "fftx_inv"), ("k_fftx_inv", "fftx_inv"),
+                  ("k4_fftz_mul", "fftz_mul"), ("k_fftz_mul", "fftz_mul"),
+                  ("k4_ffty_mul2d", "ffty_mul2d"), ("k_ffty_mul2d", "ffty_mul2d"),
+                  ("k_field", "field"))
+
+
+def _kernel_class(name):
+    base = name.split("(")[0].replace("void ", "").replace("mmp::", "")
+    for pre, cls in KERNEL_CLASSES:
+        if base.startswith(pre + "<") or base == pre:
+            return cls
+    if base.startswith(("k4_ffty<", "k_ffty<")):
+        targs = [a.strip() for a in base.split("<", 1)[1].rstrip(">").split(",")]
+        inv = targs[-1] if base.startswith("k4_ffty<") else targs[1]   # <T, L1, L2, INV> / <T, INV, P2>
+        return "ffty_inv" if inv == "true" else "ffty_fwd"
+    return None
+
+
+def counters_from(root, last):
+    """profiles/counters_c2_fp32.json from rocprofv3 --pmc CSVs.
+
+    root holds four runs: fetch/ and write/ (FETCH_SIZE, WRITE_SIZE of a
+    short bench.py run) and cfetch/ and cwrite/ (the same counters for
+    bench.py --copy-calib, a 1 GiB device copy).  Per kernel class the last
+    `last` dispatches (the timed steps, after the autotuner's candidate
+    launches) are averaged; KiB per dispatch are scaled by what the counter
+    reads per byte of the copy."""
+    import csv
+    import glob
+
+    def read(sub, ctr):
+        out = {}
+        for f in glob.glob(os.path.join(root, sub, "**", "*counter_collection.csv"),
+                           recursive=True):
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    if r["Counter_Name"] == ctr:
+                        out.setdefault(r["Kernel_Name"], []).append(
+                            (int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+        return out
+
+    copy_bytes = 1 << 30
+    cf = max(v for vals in read("cfetch", "FETCH_SIZE").values() for _, v in vals)
+    cw = max(v for vals in read("cwrite", "WRITE_SIZE").values() for _, v in vals)
+    f_scale, w_scale = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
+    res = {}
+    for ctr, sub, scale, key in (("FETCH_SIZE", "fetch", f_scale, "read"),
+                                 ("WRITE_SIZE", "write", w_scale, "write")):
+        per = {}
+        for name, vals in read(sub, ctr).items():
+            cls = _kernel_class(name)
+            if cls:
+                per.setdefault(cls, []).extend(vals)
+        for cls, vals in per.items():
+            vals.sort()
+            tail = [v for _, v in vals[-last:]]
+            res.setdefault(cls, {})[key + "_bytes_per_launch"] = \
+                sum(tail) / len(tail) * 1024.0 * scale
+    for cls, d in res.items():
+        d["bytes_per_launch"] = d.get("read_bytes_per_launch", 0.0) + \
+            d.get("write_bytes_per_launch", 0.0)
+    out = {"source_hash": src_hash(), "fetch_scale": f_scale, "write_scale": w_scale,
+           "note": "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE per dispatch (KiB), scaled by the "
+                   "counter's reading for a 1 GiB device-to-device copy; mean of the last "
+                   f"{last} dispatches of each kernel class (the timed steps)",
+           "kernels": res}
+    with open(COUNTERS, "w") as fh:
+        json.dump(out, fh, indent=1)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -250,7 +323,14 @@ def main():
                     help="keep the default demag plan instead of timing candidates first")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a 1 GiB device-to-device copy (counter calibration)")
+    ap.add_argument("--counters-from", metavar="DIR",
+                    help="write the HBM-traffic summary from rocprofv3 --pmc runs in DIR "
+                         "(fetch/, write/, cfetch/, cwrite/) and exit")
+    ap.add_argument("--counters-last", type=int, default=12)
     args = ap.parse_args()
+    if args.counters_from:
+        print(json.dumps(counters_from(args.counters_from, args.counters_last), indent=1))
+        return
     if args.copy_calib:
         import torch
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")

@@ -451,7 +451,6 @@ void demag_pass(int pass, const DemagPlan& p, const DemagBufs<T>& b, const Table
         a.nx = p.nx; a.ny = p.ny; a.nz = p.nz; a.Hx = p.Hx; a.ldy = p.ldy; a.ty = ty;
         a.lnl = 0;
         while ((2 << a.lnl) < ty) ++a.lnl;
-        a.swm = 32 / ty;
         launch_x4<T>(p.Px, inv, g, x_threads(p, ty), lds, st, a);
       } else {
         XArgs<T> a;

@@ -17,7 +17,7 @@ struct X4Args {
   T* Bd;
   const cpx<T>* tw4;
   int nx, ny, nz, Hx, ldy, ty;
-  int lnl, swm;  // log2(ty / 2), 32 / ty
+  int lnl;  // log2(ty / 2)
 };
 
 template <typename T>

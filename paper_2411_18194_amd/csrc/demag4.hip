@@ -69,14 +69,6 @@ __device__ __forceinline__ void fs_step3(cpx<T> (*u)[L2], const cpx<T>* line, in
   }
 }
 
-// Bank swizzle of line q's natural-order spectrum in LDS for the x passes:
-// element k sits at k ^ xsw(q).  The lines of one block start on the same
-// bank (L is a multiple of the bank count), and the (un)pack loops read one
-// frequency of every line at once; the XOR spreads those lines over the
-// banks.  ty = rows per block, nl = ty/2 lines.
-// swm = 32 / ty, passed in so the loops need no division
-__device__ __forceinline__ int xsw(int q, int swm, int L) { return (q * swm) & (L - 1); }
-
 // two consecutive complex values as one 16-byte access where they fit
 template <typename T>
 __device__ __forceinline__ void store2(cpx<T>* o, cpx<T> a, cpx<T> b) {
@@ -178,21 +170,18 @@ __global__ __launch_bounds__(256) void k4_fftx_fwd(X4Args<T> a) {
   V u[L1 / L2][L2];
   fs_step3<T, L1, L2, false>(u, line, t);
   __syncthreads();
-  const int swq = xsw(q, a.swm, L);
 #pragma unroll
   for (int i = 0; i < L1 / L2; ++i)
 #pragma unroll
-    for (int k2 = 0; k2 < L2; ++k2)
-      line[(t + L2 * i + L1 * k2) ^ swq] = u[i][bitrev<L2>(k2)];
+    for (int k2 = 0; k2 < L2; ++k2) line[t + L2 * i + L1 * k2] = u[i][bitrev<L2>(k2)];
   __syncthreads();
   // unpack the two real spectra and store them transposed (y contiguous,
   // rows 2qq and 2qq+1 as one 16-byte store for FP32)
   V* out = a.S1 + ((long)(c * a.nz + z) * a.Hx) * a.ldy + y0;
   for (int idx = tid; idx < nl * a.Hx; idx += nthr) {
     const int qq = idx & (nl - 1), kx = idx >> a.lnl;
-    const int sw = xsw(qq, a.swm, L);
-    const V zk = lds[qq * L + (kx ^ sw)];
-    const V zm = lds[qq * L + (((L - kx) & (L - 1)) ^ sw)];
+    const V zk = lds[qq * L + kx];
+    const V zm = lds[qq * L + ((L - kx) & (L - 1))];
     const T h = T(0.5);
     store2<T>(out + (long)kx * a.ldy + 2 * qq, cmk<T>(h * (zk.x + zm.x), h * (zk.y - zm.y)),
               cmk<T>(h * (zk.y + zm.y), h * (zm.x - zk.x)));
@@ -213,18 +202,16 @@ __global__ __launch_bounds__(256) void k4_fftx_inv(X4Args<T> a) {
   const V* in = a.S1 + ((long)(c * a.nz + z) * a.Hx) * a.ldy + y0;
   for (int idx = tid; idx < nl * a.Hx; idx += nthr) {
     const int qq = idx & (nl - 1), kx = idx >> a.lnl;
-    const int sw = xsw(qq, a.swm, L);
     V xa, xb;
     load2<T>(in + (long)kx * a.ldy + 2 * qq, xa, xb);
-    lds[qq * L + (kx ^ sw)] = cmk<T>(xa.x - xb.y, xa.y + xb.x);
-    if (kx > 0 && 2 * kx < L) lds[qq * L + ((L - kx) ^ sw)] = cmk<T>(xa.x + xb.y, xb.x - xa.y);
+    lds[qq * L + kx] = cmk<T>(xa.x - xb.y, xa.y + xb.x);
+    if (kx > 0 && 2 * kx < L) lds[qq * L + L - kx] = cmk<T>(xa.x + xb.y, xb.x - xa.y);
   }
   __syncthreads();
   V* line = lds + q * L;
-  const int swq = xsw(q, a.swm, L);
   V v[L1];
 #pragma unroll
-  for (int n1 = 0; n1 < L1; ++n1) v[n1] = line[(L2 * n1 + t) ^ swq];
+  for (int n1 = 0; n1 < L1; ++n1) v[n1] = line[L2 * n1 + t];
   __syncthreads();
   fs_step1<T, L1, L2, true>(v, line, a.tw4, t);
   __syncthreads();

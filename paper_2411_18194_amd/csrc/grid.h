@@ -42,11 +42,12 @@ struct GridBase {
   virtual int autotune(mmp_plan* out) = 0;
   virtual int set_graphs(bool on) = 0;
   // non-blocking adaptive run used by the server: begin, enqueue chunks of
-  // attempts (each followed by an async controller read-back and an event),
-  // poll for completion
+  // attempts (each followed by an async controller read-back and an event;
+  // at most two in flight), poll the oldest for completion
   virtual int run_begin(double t_end) = 0;
   virtual int run_chunk(int attempts) = 0;
   virtual int run_poll(bool* finished, int* status, long long* steps, long long* rejects) = 0;
+  virtual int chunks_in_flight() const = 0;
 };
 
 GridBase* make_grid(int precision);

@@ -75,7 +75,10 @@ struct Grid final : GridBase {
     if (stream) (void)hipStreamSynchronize(stream);
     free_all();
     if (hctrl) (void)hipHostFree(hctrl);
-    if (chunk_ev) (void)hipEventDestroy(chunk_ev);
+    for (int i = 0; i < 2; ++i) {
+      if (chunk_ev[i]) (void)hipEventDestroy(chunk_ev[i]);
+      if (chunk_ctrl[i]) (void)hipHostFree(chunk_ctrl[i]);
+    }
   }
 
   void free_all() {
@@ -941,7 +944,13 @@ struct Grid final : GridBase {
     return 0;
   }
 
-  hipEvent_t chunk_ev = nullptr;
+  // Chunks of the non-blocking run: each ends with an asynchronous copy of
+  // the controller into a pinned slot of its own and an event, so two
+  // chunks can be in flight while the host reads the older one.
+  hipEvent_t chunk_ev[2] = {nullptr, nullptr};
+  Ctrl* chunk_ctrl[2] = {nullptr, nullptr};
+  int chunk_head = 0, chunk_count = 0;
+  Ctrl chunk_last{};
 
   int run_begin(double t_end) override {
     int rc = ensure_ready();
@@ -955,28 +964,47 @@ struct Grid final : GridBase {
     init.tol = p.tol > 0 ? p.tol : 1e-5;
     init.dt_min = p.dt_min > 0 ? p.dt_min : 1e-20;
     if ((rc = begin_segment(init))) return rc;
-    if (!chunk_ev) MMP_HIP_TRY(hipEventCreateWithFlags(&chunk_ev, hipEventDisableTiming));
+    for (int i = 0; i < 2; ++i) {
+      if (!chunk_ev[i]) MMP_HIP_TRY(hipEventCreateWithFlags(&chunk_ev[i], hipEventDisableTiming));
+      if (!chunk_ctrl[i]) MMP_HIP_TRY(hipHostMalloc((void**)&chunk_ctrl[i], sizeof(Ctrl), 0));
+    }
+    chunk_head = 0;
+    chunk_count = 0;
+    chunk_last = *hctrl;
     return 0;
   }
 
   int run_chunk(int attempts) override {
+    if (chunk_count >= 2) { set_error("two chunks already in flight"); return MMP_E_STATE; }
     if (int rc = enqueue_attempts(false, false, attempts)) return rc;
-    MMP_HIP_TRY(hipMemcpyAsync(hctrl, dctrl.p, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
-    MMP_HIP_TRY(hipEventRecord(chunk_ev, stream));
+    const int slot = (chunk_head + chunk_count) & 1;
+    MMP_HIP_TRY(hipMemcpyAsync(chunk_ctrl[slot], dctrl.p, sizeof(Ctrl), hipMemcpyDeviceToHost,
+                               stream));
+    MMP_HIP_TRY(hipEventRecord(chunk_ev[slot], stream));
+    ++chunk_count;
     return 0;
   }
 
+  // state after the oldest chunk in flight (MMP_PENDING while it runs; the
+  // last state read when none is in flight)
   int run_poll(bool* finished, int* status, long long* steps, long long* rejects) override {
-    const hipError_t q = hipEventQuery(chunk_ev);
-    if (q == hipErrorNotReady) { *finished = false; return MMP_PENDING; }
-    if (q != hipSuccess) { set_error(hipGetErrorString(q)); return MMP_E_HIP; }
-    const Ctrl c = *hctrl;
+    if (chunk_count > 0) {
+      const hipError_t q = hipEventQuery(chunk_ev[chunk_head]);
+      if (q == hipErrorNotReady) { *finished = false; return MMP_PENDING; }
+      if (q != hipSuccess) { set_error(hipGetErrorString(q)); return MMP_E_HIP; }
+      chunk_last = *chunk_ctrl[chunk_head];
+      chunk_head ^= 1;
+      --chunk_count;
+    }
+    const Ctrl& c = chunk_last;
     *finished = (c.done || c.status) != 0;
     *status = c.status;
     *steps = c.steps;
     *rejects = c.rejects;
     return 0;
   }
+
+  int chunks_in_flight() const override { return chunk_count; }
 
   int tensor(double* n6) override {
     double* d6 = nullptr;

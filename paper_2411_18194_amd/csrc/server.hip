@@ -11,6 +11,7 @@
 // the next queued request is admitted at once.  Results are read with
 // mmp_poll.  Each request runs exactly the kernels it would run alone, so
 // its result does not depend on what else is in flight.
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -103,10 +104,14 @@ struct mmp_server_s {
       } else {
         res.status = rc;
       }
+      // the stream is idle after mmp_get_state: drain the chunks in flight
       long long steps = 0, rejects = 0;
       bool fin = false;
       int st = 0;
-      if (q->g->impl) q->g->impl->run_poll(&fin, &st, &steps, &rejects);
+      if (q->g->impl)
+        do {
+          if (q->g->impl->run_poll(&fin, &st, &steps, &rejects) != 0) break;
+        } while (q->g->impl->chunks_in_flight() > 0);
       res.steps = steps;
       res.rejects = rejects;
     }
@@ -132,8 +137,11 @@ struct mmp_server_s {
     if ((rc = mmp_set_params(g, &p))) return rc;
     if ((rc = mmp_set_state(g, q->m0.data(), nullptr, nullptr, 0.0))) return rc;
     if ((rc = g->impl->run_begin(q->r.t_relax))) return rc;
-    const int64_t N = (int64_t)q->r.nx * q->r.ny * q->r.nz;
-    q->chunk = N >= 65536 ? 4 : (N >= 4096 ? 16 : 32);
+    // attempts per chunk: a few ms of device work for any grid size; two
+    // chunks stay in flight so the device never waits for the host
+    const int64_t N = (int64_t)q->r.nx * q->r.ny * q->r.nz * q->r.params.nsub;
+    q->chunk = (int)std::max<int64_t>(8, std::min<int64_t>(64, (int64_t(1) << 21) / N));
+    if ((rc = g->impl->run_chunk(q->chunk))) return rc;
     return g->impl->run_chunk(q->chunk);
   }
 
@@ -171,7 +179,12 @@ struct mmp_server_s {
           finish(q, rc != 0 ? rc : st);
           continue;
         }
-        (void)q->g->impl->run_chunk(q->chunk);
+        const int rc2 = q->g->impl->run_chunk(q->chunk);
+        if (rc2 != 0) {
+          active.erase(active.begin() + i);
+          finish(q, rc2);
+          continue;
+        }
         ++i;
       }
       if (!any) {
