@@ -167,7 +167,7 @@ def cpu_baseline():
     y = P.initial_state(m)
     y, _ = P.run_fixed(y, 0.0, dt, 1)          # warm-up (also fills the FSAL stage)
     t0 = time.perf_counter()
-    nsteps = 2
+    nsteps = 6   # ~10 s of host work
     y, _ = P.run_fixed(y, 0.0, dt, nsteps)
     sec = time.perf_counter() - t0
     N = n[0] * n[1] * n[2]
@@ -213,7 +213,34 @@ def _serve_pass(reqs, states, precision, rate_scale, max_active):
             "requests": len(res), "attempts": int(steps), "cells": int(cells)}
 
 
-def run_serve(count, max_active=8):
+def _sequential_fp64(reqs, states):
+    """Each request alone, one after another, FP64, direct launches (no
+    graphs, no server); latencies by FIFO replay of the measured service
+    times against the stream's arrival times."""
+    from paper_2411_18194_amd import mmp
+
+    service = []
+    for r, m in zip(reqs, states):
+        t0 = time.perf_counter()
+        g = mmp.Grid(r["params"], mmp.FP64, tol=r["tol"])
+        g.set_graphs(False)
+        g.set_state(m)
+        g.run(r["t_relax"])
+        g.get_state()
+        g.eval_heff(0, want_b=False)
+        g.close()
+        service.append(time.perf_counter() - t0)
+    t_free, lat = 0.0, []
+    for r, sv in zip(reqs, service):
+        start = max(t_free, r["t_arrive"])
+        t_free = start + sv
+        lat.append(t_free - r["t_arrive"])
+    p50, p99 = _percentiles(lat)
+    return {"solves_per_s": len(reqs) / sum(service), "p50_s": p50, "p99_s": p99,
+            "requests": len(reqs), "service_s": [round(x, 3) for x in service]}
+
+
+def run_serve(count, max_active=8, baseline=0):
     """Relaxation requests (a seeded prefix of the 4000-request stream at
     200/s: 70 % FM with demag, 30 % two-sublattice AFM, 0.5 ns each) served
     by the library's server in FP32; then the same requests re-timed with
@@ -226,6 +253,15 @@ def run_serve(count, max_active=8):
     # arrivals at 0.8 x capacity: scale the stream's mean rate (200/s) down
     scale = 200.0 / (0.8 * full["solves_per_s"])
     sus = _serve_pass(reqs, states, mmp.FP32, scale, max_active)
+    base = None
+    if baseline > 0:
+        base = _sequential_fp64(reqs[:baseline], states[:baseline])
+        # the same subsample through the server, for a like-for-like ratio
+        sub = _serve_pass(reqs[:baseline], states[:baseline], mmp.FP32, 1.0, max_active)
+        base["served_fp32_same_requests"] = {k: round(v, 4) if isinstance(v, float) else v
+                                             for k, v in sub.items()}
+        base["note"] = (f"sequential plain FP64 timed on the first {baseline} requests only "
+                        "(a seeded subsample; the full list would take minutes)")
     return {"workload": f"first {count} requests of the seeded c5 stream (Poisson 200/s, "
                         "nx, ny log-uniform 32..512, nz log-uniform 1..8, 70 % FM with "
                         "demag / 30 % AFM, 0.5 ns DP45 relaxation each, tol 1e-5)",
@@ -233,7 +269,8 @@ def run_serve(count, max_active=8):
             "offered": {k: round(v, 4) if isinstance(v, float) else v for k, v in full.items()},
             "at_0.8_capacity": {k: round(v, 4) if isinstance(v, float) else v
                                 for k, v in sus.items()},
-            "arrival_rate_0.8_capacity_per_s": round(200.0 / scale, 3)}
+            "arrival_rate_0.8_capacity_per_s": round(200.0 / scale, 3),
+            "sequential_fp64": base}
 
 
 # rocprofv3 kernel names -> kernel classes of the library's event profiler
@@ -317,8 +354,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-prof", action="store_true")
-    ap.add_argument("--serve", type=int, default=24,
+    ap.add_argument("--serve", type=int, default=8,
                     help="requests in the serving measurement (0 = skip)")
+    ap.add_argument("--serve-baseline", type=int, default=3,
+                    help="requests of that list also run one at a time in FP64")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default demag plan instead of timing candidates first")
     ap.add_argument("--copy-calib", action="store_true",
@@ -372,7 +411,7 @@ def main():
                        "fp32_speedup": round(r32["value"] / r64["value"], 3),
                        "plan": {k: v for k, v in r64["plan"].items() if k != "demag_ms"}}
     if args.serve > 0:
-        out["serving"] = run_serve(args.serve)
+        out["serving"] = run_serve(args.serve, baseline=min(args.serve_baseline, args.serve))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
