@@ -184,7 +184,7 @@ def _percentiles(lat):
     return (float(np.percentile(lat, 50)), float(np.percentile(lat, 99)))
 
 
-def _serve_pass(reqs, states, precision, rate_scale, max_active):
+def _serve_pass(reqs, states, precision, rate_scale, max_active, batch=True):
     """Open-loop replay of the request stream through the server.
 
     Request i is submitted at t_arrive[i] * rate_scale after the start (a
@@ -192,7 +192,8 @@ def _serve_pass(reqs, states, precision, rate_scale, max_active):
     the server's clock."""
     from paper_2411_18194_amd import mmp
 
-    srv = mmp.Server(hbm_budget=64 << 30, max_active=max_active, precision=precision)
+    srv = mmp.Server(hbm_budget=64 << 30, max_active=max_active, precision=precision,
+                     batch=batch)
     t0 = srv.clock()
     tickets = []
     for r, m in zip(reqs, states):

@@ -288,6 +288,10 @@ typedef struct {
   int64_t hbm_budget;     /* bytes of device memory for requests           */
   int32_t max_active;     /* concurrent requests on the device             */
   int32_t precision;      /* MMP_FP32 or MMP_FP64 for every request        */
+  int32_t batch;          /* 1: requests without demag and elasticity step
+                             together, one launch per stage for all of
+                             them (same results as alone); 0: each request
+                             on its own stream                             */
 } mmp_server_opts;
 
 typedef struct {

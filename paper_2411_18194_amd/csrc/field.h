@@ -55,6 +55,28 @@ struct FieldArgs {
 template <typename T>
 void launch_field(const FieldArgs<T>& a, bool eval, hipStream_t st, Prof* prof);
 
+// Per-grid pointers of a batch for the step controller and the stage-2
+// combination (one entry per grid).
+template <typename T>
+struct StepWork {
+  Ctrl* ctrl;
+  Table<T>* tbl;
+  const double* errpart;
+  int nerr;
+  int nsub;
+  long N;
+};
+
+// Stage `stage` of many grids (no demag, no elasticity) in one launch:
+// args[g] are the grids' field arguments in device memory, work[b] =
+// (grid, block) for every field block of every grid.
+template <typename T>
+void launch_field_multi(const FieldArgs<T>* args, const int2* work, int nwork, int nsub, int stage,
+                        int fuse2, hipStream_t st);
+// step control of every grid, then its next stage-2 input
+template <typename T>
+void launch_step_multi(const StepWork<T>* w, int ngrids, long max_cells, hipStream_t st);
+
 template <typename T>
 void launch_combine2(const Table<T>* tbl, const Ctrl* ctrl, long Ncell, int nsub, hipStream_t st,
                      Prof* prof);

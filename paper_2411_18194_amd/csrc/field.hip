@@ -50,10 +50,11 @@ __device__ __forceinline__ double dot3d(const T* a, const T* b) {
   return (double)a[0] * b[0] + (double)a[1] * b[1] + (double)a[2] * b[2];
 }
 
+// Block w (tile-major over z chunks) of one grid; stage and fuse2 come from
+// the launch so that one argument block serves every stage.
 template <typename T, int NSUB, bool EVAL>
-__global__ __launch_bounds__(256) void k_field(const FieldArgs<T> a) {
-  if (ctrl_stopped(a.ctrl)) return;
-  const int w = xcd_remap(blockIdx.x, a.nb_pad);
+__device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, const int stage,
+                                            const int fuse2) {
   const int ntile = a.nbx * a.nby;
   if (w >= ntile * a.nzc) return;
   const int tile = w % ntile;
@@ -64,7 +65,6 @@ __global__ __launch_bounds__(256) void k_field(const FieldArgs<T> a) {
   const bool in = x < a.nx && y < a.ny;
   const long N = a.N;
   const long N3 = 3 * N;
-  const int stage = a.stage;
   const T* __restrict__ m = EVAL ? a.tbl->yn : stage_in(a.tbl, stage);
 
   double h = 0.0;
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void k_field(const FieldArgs<T> a) {
       ynext = stage_out(a.tbl, stage);
       for (int j = 0; j < stage; ++j) ca[j] = (T)(DP::a[stage][j] * h);
     } else {
-      if (a.fuse2) ynext = a.tbl->sa;
+      if (fuse2) ynext = a.tbl->sa;
       ca[0] = (T)(DP::a[1][0] * h);
       for (int j = 0; j < 6; ++j) kin[j] = a.tbl->k[j];
     }
@@ -329,7 +329,7 @@ __global__ __launch_bounds__(256) void k_field(const FieldArgs<T> a) {
             ynext[base] = v[0] * inv;
             ynext[base + N] = v[1] * inv;
             ynext[base + 2 * N] = v[2] * inv;
-          } else if (!a.fuse2) {
+          } else if (!fuse2) {
             double ev[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -375,7 +375,7 @@ __global__ __launch_bounds__(256) void k_field(const FieldArgs<T> a) {
       }
       if (threadIdx.x < kNE) a.epart[(long)w * kNE + threadIdx.x] = red[threadIdx.x][0];
     }
-  } else if (stage == 7 && !a.fuse2) {
+  } else if (stage == 7 && !fuse2) {
     __shared__ double red[256];
     red[threadIdx.x] = emax;
     __syncthreads();
@@ -385,6 +385,39 @@ __global__ __launch_bounds__(256) void k_field(const FieldArgs<T> a) {
     }
     if (threadIdx.x == 0) a.errpart[w] = red[0];
   }
+}
+
+template <typename T, int NSUB, bool EVAL>
+__global__ __launch_bounds__(256) void k_field(const FieldArgs<T> a) {
+  if (ctrl_stopped(a.ctrl)) return;
+  field_block<T, NSUB, EVAL>(a, xcd_remap(blockIdx.x, a.nb_pad), a.stage, a.fuse2);
+}
+
+// Many grids in one launch: block b runs block work[b].y of grid work[b].x
+// (the argument blocks live in device memory); a grid whose run is over
+// skips its blocks.
+template <typename T, int NSUB>
+__global__ __launch_bounds__(256) void k_field_multi(const FieldArgs<T>* __restrict__ args,
+                                                     const int2* __restrict__ work, int nwork,
+                                                     int nb_pad, int stage, int fuse2) {
+  const int b = xcd_remap(blockIdx.x, nb_pad);
+  if (b >= nwork) return;
+  const int2 wk = work[b];
+  const FieldArgs<T>& a = args[wk.x];
+  if (ctrl_stopped(a.ctrl)) return;
+  field_block<T, NSUB, false>(a, wk.y, stage, fuse2);
+}
+
+template <typename T>
+void launch_field_multi(const FieldArgs<T>* args, const int2* work, int nwork, int nsub, int stage,
+                        int fuse2, hipStream_t st) {
+  const int nb_pad = round_up(nwork, 8);
+  if (nsub == 1)
+    hipLaunchKernelGGL((k_field_multi<T, 1>), dim3(nb_pad), dim3(256), 0, st, args, work, nwork,
+                       nb_pad, stage, fuse2);
+  else
+    hipLaunchKernelGGL((k_field_multi<T, 2>), dim3(nb_pad), dim3(256), 0, st, args, work, nwork,
+                       nb_pad, stage, fuse2);
 }
 
 template <typename T>
@@ -403,10 +436,8 @@ void launch_field(const FieldArgs<T>& a, bool eval, hipStream_t st, Prof* prof) 
 // --------------------------------------------------------- combine2 ----
 // Stage-2 input for a new attempt: normalise(y_n + h a21 k1).
 template <typename T>
-__global__ void k_combine2_cells(const Table<T>* tbl, const Ctrl* ctrl, long Ncell, int nsub) {
-  if (ctrl_stopped(ctrl)) return;
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= Ncell * nsub) return;
+__device__ __forceinline__ void combine2_cell(const Table<T>* tbl, const Ctrl* ctrl, long Ncell,
+                                              long i) {
   const long s = i / Ncell, cell = i - s * Ncell;
   const long base = s * 3 * Ncell + cell;
   const T c = (T)(DP::a[1][0] * ctrl->h);
@@ -420,6 +451,14 @@ __global__ void k_combine2_cells(const Table<T>* tbl, const Ctrl* ctrl, long Nce
 }
 
 template <typename T>
+__global__ void k_combine2_cells(const Table<T>* tbl, const Ctrl* ctrl, long Ncell, int nsub) {
+  if (ctrl_stopped(ctrl)) return;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Ncell * nsub) return;
+  combine2_cell<T>(tbl, ctrl, Ncell, i);
+}
+
+template <typename T>
 void launch_combine2(const Table<T>* tbl, const Ctrl* ctrl, long Ncell, int nsub, hipStream_t st,
                      Prof* prof) {
   ProfScope ps(prof, P_COMBINE, st);
@@ -430,7 +469,8 @@ void launch_combine2(const Table<T>* tbl, const Ctrl* ctrl, long Ncell, int nsub
 
 // ---------------------------------------------------------- control ----
 template <typename T>
-__global__ void k_control(Ctrl* c, Table<T>* tbl, const double* errpart, int nerr, int elastic) {
+__device__ __forceinline__ void control_block(Ctrl* c, Table<T>* tbl, const double* errpart,
+                                              int nerr, int elastic) {
   if (c->done || c->status) return;
   __shared__ double red[256];
   double e = 0.0;
@@ -497,6 +537,34 @@ __global__ void k_control(Ctrl* c, Table<T>* tbl, const double* errpart, int ner
     c->land = c->dt >= rem ? 1 : 0;
     c->h = c->land ? rem : c->dt;
   }
+}
+
+template <typename T>
+__global__ void k_control(Ctrl* c, Table<T>* tbl, const double* errpart, int nerr, int elastic) {
+  control_block<T>(c, tbl, errpart, nerr, elastic);
+}
+
+// one block per grid of a batch
+template <typename T>
+__global__ void k_control_multi(const StepWork<T>* __restrict__ w) {
+  const StepWork<T> g = w[blockIdx.x];
+  control_block<T>(g.ctrl, g.tbl, g.errpart, g.nerr, 0);
+}
+
+template <typename T>
+__global__ void k_combine2_multi(const StepWork<T>* __restrict__ w) {
+  const StepWork<T> g = w[blockIdx.y];
+  if (ctrl_stopped(g.ctrl)) return;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.N * g.nsub) return;
+  combine2_cell<T>(g.tbl, g.ctrl, g.N, i);
+}
+
+template <typename T>
+void launch_step_multi(const StepWork<T>* w, int ngrids, long max_cells, hipStream_t st) {
+  hipLaunchKernelGGL((k_control_multi<T>), dim3(ngrids), dim3(256), 0, st, w);
+  hipLaunchKernelGGL((k_combine2_multi<T>), dim3((unsigned)((max_cells + 255) / 256), ngrids),
+                     dim3(256), 0, st, w);
 }
 
 template <typename T>
@@ -571,7 +639,10 @@ void launch_energy_final(const double* epart, int nblk, double* out, hipStream_t
   template void launch_control<T>(Ctrl*, Table<T>*, const double*, int, int, hipStream_t,   \
                                   Prof*);                                                    \
   template void launch_sample<T>(Ctrl*, const Table<T>*, int, long, double*, int, double*,  \
-                                 double*, int, hipStream_t, Prof*);
+                                 double*, int, hipStream_t, Prof*);                          \
+  template void launch_field_multi<T>(const FieldArgs<T>*, const int2*, int, int, int, int,   \
+                                      hipStream_t);                                          \
+  template void launch_step_multi<T>(const StepWork<T>*, int, long, hipStream_t);
 INST(float)
 INST(double)
 

@@ -48,9 +48,39 @@ struct GridBase {
   virtual int run_chunk(int attempts) = 0;
   virtual int run_poll(bool* finished, int* status, long long* steps, long long* rejects) = 0;
   virtual int chunks_in_flight() const = 0;
+  // for a batch: the member's stream is idle and its last controller state
+  // is `c` (host copy)
+  virtual void set_chunk_state(const void* c) = 0;
 };
 
 GridBase* make_grid(int precision);
+
+// Many grids stepped together: each stage of every member is one launch
+// (a device work table of (grid, block)), the step controllers and stage-2
+// combinations one launch each, 8 attempts per captured HIP graph, on the
+// batch's own stream.  Members keep their own buffers and device-side step
+// control, so each one takes exactly the steps it would take alone.  Only
+// grids without demag and elasticity join, all with the batch's precision
+// and sublattice count, and membership changes only while no chunk is in
+// flight (kernels of a chunk read every member's controller).
+struct BatchBase {
+  virtual ~BatchBase() {}
+  virtual bool accepts(const GridBase* g) const = 0;
+  // g must have begun its run (run_begin) on its own stream
+  virtual int add(GridBase* g) = 0;
+  virtual int remove(GridBase* g) = 0;
+  virtual int size() const = 0;
+  virtual int in_flight() const = 0;
+  // enqueue `attempts` attempts of every member, then a read-back of their
+  // controllers (at most two chunks in flight)
+  virtual int run_chunk(int attempts) = 0;
+  // MMP_PENDING while the oldest chunk runs; else its controller states are
+  // handed to the members (their run_poll reports them)
+  virtual int poll() = 0;
+  virtual long long cells() const = 0;
+};
+
+BatchBase* make_batch(int precision, int nsub);
 
 }  // namespace mmp
 

@@ -1006,6 +1006,11 @@ struct Grid final : GridBase {
 
   int chunks_in_flight() const override { return chunk_count; }
 
+  void set_chunk_state(const void* c) override {
+    chunk_last = *static_cast<const Ctrl*>(c);
+    chunk_count = 0;
+  }
+
   int tensor(double* n6) override {
     double* d6 = nullptr;
     MMP_HIP_TRY(hipMalloc(&d6, 6 * (size_t)N * sizeof(double)));
@@ -1022,6 +1027,208 @@ struct Grid final : GridBase {
 GridBase* make_grid(int precision) {
   if (precision == MMP_FP64) return new Grid<double>();
   return new Grid<float>();
+}
+
+// gathers the members' controllers for one read-back
+__global__ void k_gather_ctrl(Ctrl* const* __restrict__ src, Ctrl* __restrict__ dst, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = *src[i];
+}
+
+template <typename T>
+struct Batch final : BatchBase {
+  int nsub;
+  std::vector<Grid<T>*> mem;
+  hipStream_t st = nullptr;
+  // device tables (rebuilt when membership changes)
+  Buf<FieldArgs<T>> d_args;
+  Buf<int2> d_work;
+  Buf<StepWork<T>> d_step;
+  Buf<Ctrl*> d_cptr;
+  Buf<Ctrl> d_cgather;
+  int nwork = 0;
+  long max_cells = 0;
+  bool dirty = true;
+  hipGraphExec_t gexec = nullptr;
+  static constexpr int kGA = 8;
+  // two read-back slots
+  Ctrl* h_c[2] = {nullptr, nullptr};
+  int h_cap = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int head = 0, count = 0;
+  std::vector<Grid<T>*> slot_mem[2];
+
+  explicit Batch(int ns) : nsub(ns) {}
+  ~Batch() override {
+    if (st) (void)hipStreamSynchronize(st);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    for (int i = 0; i < 2; ++i) {
+      if (h_c[i]) (void)hipHostFree(h_c[i]);
+      if (ev[i]) (void)hipEventDestroy(ev[i]);
+    }
+    if (st) (void)hipStreamDestroy(st);
+  }
+
+  bool accepts(const GridBase* g) const override {
+    const auto* t = dynamic_cast<const Grid<T>*>(g);
+    return t && t->params_set && !t->p.demag && !t->p.elastic && t->p.nsub == nsub;
+  }
+  int size() const override { return (int)mem.size(); }
+  int in_flight() const override { return count; }
+  long long cells() const override {
+    long long c = 0;
+    for (auto* g : mem) c += g->N * g->p.nsub;
+    return c;
+  }
+
+  int ensure_stream() {
+    if (!st) MMP_HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    for (int i = 0; i < 2; ++i)
+      if (!ev[i]) MMP_HIP_TRY(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+    return 0;
+  }
+
+  int add(GridBase* gb) override {
+    if (count) { set_error("batch membership changes need an idle batch"); return MMP_E_STATE; }
+    auto* g = dynamic_cast<Grid<T>*>(gb);
+    if (!g || !accepts(g)) { set_error("grid cannot join this batch"); return MMP_E_ARG; }
+    if (int rc = ensure_stream()) return rc;
+    // the batch stream waits for the member's set-up (run_begin)
+    hipEvent_t e;
+    MMP_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    MMP_HIP_TRY(hipEventRecord(e, g->stream));
+    MMP_HIP_TRY(hipStreamWaitEvent(st, e, 0));
+    (void)hipEventDestroy(e);
+    mem.push_back(g);
+    dirty = true;
+    return 0;
+  }
+
+  int remove(GridBase* gb) override {
+    if (count) { set_error("batch membership changes need an idle batch"); return MMP_E_STATE; }
+    for (size_t i = 0; i < mem.size(); ++i)
+      if (mem[i] == gb) {
+        mem.erase(mem.begin() + i);
+        dirty = true;
+        return 0;
+      }
+    return MMP_E_ARG;
+  }
+
+  int rebuild() {
+    if (gexec) {
+      (void)hipGraphExecDestroy(gexec);
+      gexec = nullptr;
+    }
+    const int n = (int)mem.size();
+    std::vector<FieldArgs<T>> args(n);
+    std::vector<int2> work;
+    std::vector<StepWork<T>> step(n);
+    std::vector<Ctrl*> cptr(n);
+    max_cells = 0;
+    for (int i = 0; i < n; ++i) {
+      Grid<T>* g = mem[i];
+      args[i] = g->fa;
+      for (int b = 0; b < g->nblk; ++b) work.push_back(make_int2(i, b));
+      step[i].ctrl = g->dctrl.p;
+      step[i].tbl = g->dtbl.p;
+      step[i].errpart = g->errpart.p;
+      step[i].nerr = g->nblk;
+      step[i].nsub = g->p.nsub;
+      step[i].N = g->N;
+      cptr[i] = g->dctrl.p;
+      max_cells = std::max(max_cells, (long)g->N * g->p.nsub);
+    }
+    nwork = (int)work.size();
+    d_args.release(); d_work.release(); d_step.release(); d_cptr.release(); d_cgather.release();
+    if (d_args.alloc(n) || d_work.alloc(work.size()) || d_step.alloc(n) || d_cptr.alloc(n) ||
+        d_cgather.alloc(n)) {
+      set_error("device allocation failed");
+      return MMP_E_NOMEM;
+    }
+    MMP_HIP_TRY(hipMemcpyAsync(d_args.p, args.data(), n * sizeof(FieldArgs<T>),
+                               hipMemcpyHostToDevice, st));
+    MMP_HIP_TRY(hipMemcpyAsync(d_work.p, work.data(), work.size() * sizeof(int2),
+                               hipMemcpyHostToDevice, st));
+    MMP_HIP_TRY(hipMemcpyAsync(d_step.p, step.data(), n * sizeof(StepWork<T>),
+                               hipMemcpyHostToDevice, st));
+    MMP_HIP_TRY(hipMemcpyAsync(d_cptr.p, cptr.data(), n * sizeof(Ctrl*), hipMemcpyHostToDevice,
+                               st));
+    MMP_HIP_TRY(hipStreamSynchronize(st));  // host vectors go out of scope
+    if (n > h_cap) {
+      for (int i = 0; i < 2; ++i) {
+        if (h_c[i]) (void)hipHostFree(h_c[i]);
+        h_c[i] = nullptr;
+        MMP_HIP_TRY(hipHostMalloc((void**)&h_c[i], n * sizeof(Ctrl), 0));
+      }
+      h_cap = n;
+    }
+    dirty = false;
+    return 0;
+  }
+
+  void attempt() {
+    for (int s = 2; s <= 7; ++s) launch_field_multi<T>(d_args.p, d_work.p, nwork, nsub, s, 0, st);
+    launch_step_multi<T>(d_step.p, (int)mem.size(), max_cells, st);
+  }
+
+  int run_chunk(int attempts) override {
+    if (mem.empty()) return 0;
+    if (count >= 2) { set_error("two chunks already in flight"); return MMP_E_STATE; }
+    if (dirty) {
+      if (int rc = rebuild()) return rc;
+    }
+    int left = attempts;
+    if (left >= kGA) {
+      if (!gexec) {
+        hipGraph_t g = nullptr;
+        MMP_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        for (int i = 0; i < kGA; ++i) attempt();
+        const hipError_t e = hipStreamEndCapture(st, &g);
+        if (e != hipSuccess) {
+          if (g) (void)hipGraphDestroy(g);
+          set_error(std::string("batch graph capture: ") + hipGetErrorString(e));
+          return MMP_E_HIP;
+        }
+        const hipError_t e2 = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e2 != hipSuccess) {
+          gexec = nullptr;
+          set_error(std::string("batch graph instantiate: ") + hipGetErrorString(e2));
+          return MMP_E_HIP;
+        }
+      }
+      for (; left >= kGA; left -= kGA) MMP_HIP_TRY(hipGraphLaunch(gexec, st));
+    }
+    for (; left > 0; --left) attempt();
+    const int n = (int)mem.size();
+    const int slot = (head + count) & 1;
+    hipLaunchKernelGGL(k_gather_ctrl, dim3((n + 63) / 64), dim3(64), 0, st, d_cptr.p, d_cgather.p,
+                       n);
+    MMP_HIP_TRY(hipGetLastError());
+    MMP_HIP_TRY(hipMemcpyAsync(h_c[slot], d_cgather.p, n * sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    MMP_HIP_TRY(hipEventRecord(ev[slot], st));
+    slot_mem[slot] = mem;
+    ++count;
+    return 0;
+  }
+
+  int poll() override {
+    if (count == 0) return 0;
+    const hipError_t q = hipEventQuery(ev[head]);
+    if (q == hipErrorNotReady) return MMP_PENDING;
+    if (q != hipSuccess) { set_error(hipGetErrorString(q)); return MMP_E_HIP; }
+    const std::vector<Grid<T>*>& m = slot_mem[head];
+    for (size_t i = 0; i < m.size(); ++i) m[i]->set_chunk_state(&h_c[head][i]);
+    head ^= 1;
+    --count;
+    return 0;
+  }
+};
+
+BatchBase* make_batch(int precision, int nsub) {
+  if (precision == MMP_FP64) return new Batch<double>(nsub);
+  return new Batch<float>(nsub);
 }
 
 }  // namespace mmp

@@ -38,6 +38,7 @@ struct Req {
   int64_t footprint = 0;
   mmp_grid g = nullptr;
   int chunk = 8;
+  bool batched = false;
 };
 
 int64_t estimate_bytes(const mmp_request& r, int precision) {
@@ -70,6 +71,17 @@ struct mmp_server_s {
   int64_t used = 0;
   std::thread worker;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  // grids without demag step together in one batch per sublattice count
+  struct BatchState {
+    BatchBase* b = nullptr;
+    std::vector<Req*> members, joining;
+    bool draining = false;
+  };
+  BatchState batches[2];
+
+  ~mmp_server_s() {
+    for (auto& B : batches) delete B.b;
+  }
 
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -137,12 +149,94 @@ struct mmp_server_s {
     if ((rc = mmp_set_params(g, &p))) return rc;
     if ((rc = mmp_set_state(g, q->m0.data(), nullptr, nullptr, 0.0))) return rc;
     if ((rc = g->impl->run_begin(q->r.t_relax))) return rc;
+    if (o.batch && !p.demag && !p.elastic && (p.nsub == 1 || p.nsub == 2)) {
+      BatchState& B = batches[p.nsub - 1];
+      if (!B.b) B.b = make_batch(o.precision, p.nsub);
+      if (B.b->accepts(g->impl.get())) {
+        q->batched = true;
+        B.joining.push_back(q);
+        B.draining = true;
+        return 0;
+      }
+    }
     // attempts per chunk: a few ms of device work for any grid size; two
     // chunks stay in flight so the device never waits for the host
     const int64_t N = (int64_t)q->r.nx * q->r.ny * q->r.nz * q->r.params.nsub;
     q->chunk = (int)std::max<int64_t>(8, std::min<int64_t>(64, (int64_t(1) << 21) / N));
     if ((rc = g->impl->run_chunk(q->chunk))) return rc;
     return g->impl->run_chunk(q->chunk);
+  }
+
+  static bool member_done(Req* q, int* status) {
+    bool fin = false;
+    int st = 0;
+    long long steps = 0, rejects = 0;
+    const int rc = q->g->impl->run_poll(&fin, &st, &steps, &rejects);
+    *status = rc != 0 ? rc : st;
+    return rc != 0 || fin;
+  }
+
+  // one round of a batch: collect finished chunks; when it is idle and a
+  // member has finished or requests wait to join, change the membership;
+  // keep two chunks in flight otherwise.  Returns whether anything moved.
+  bool step_batch(BatchState& B) {
+    if (!B.b) return false;
+    bool any = false;
+    while (B.b->in_flight() > 0) {
+      const int rc = B.b->poll();
+      if (rc == MMP_PENDING) break;
+      any = true;
+      if (rc != 0) {
+        for (Req* q : B.members) finish(q, rc);
+        B.members.clear();
+        return true;
+      }
+      int st = 0;
+      for (Req* q : B.members)
+        if (member_done(q, &st)) B.draining = true;
+    }
+    if (B.b->in_flight() > 0) return any;
+    if (B.draining) {
+      for (size_t i = 0; i < B.members.size();) {
+        Req* q = B.members[i];
+        int st = 0;
+        if (member_done(q, &st)) {
+          (void)B.b->remove(q->g->impl.get());
+          B.members.erase(B.members.begin() + i);
+          finish(q, st);
+        } else {
+          ++i;
+        }
+      }
+      for (Req* q : B.joining) {
+        const int rc = B.b->add(q->g->impl.get());
+        if (rc) finish(q, rc);
+        else B.members.push_back(q);
+      }
+      B.joining.clear();
+      B.draining = false;
+      any = true;
+    }
+    if (!B.members.empty()) {
+      // a few ms of device work per chunk
+      const long long cells = std::max<long long>(1, B.b->cells());
+      const int chunk = (int)std::max<long long>(8, std::min<long long>(64, (1LL << 21) / cells));
+      while (B.b->in_flight() < 2) {
+        const int rc = B.b->run_chunk(chunk);
+        if (rc) {
+          for (Req* q : B.members) finish(q, rc);
+          B.members.clear();
+          break;
+        }
+        any = true;
+      }
+    }
+    return any;
+  }
+
+  int batched_count() const {
+    return (int)(batches[0].members.size() + batches[0].joining.size() +
+                 batches[1].members.size() + batches[1].joining.size());
   }
 
   void loop() {
@@ -152,9 +246,10 @@ struct mmp_server_s {
         Req* q = nullptr;
         {
           std::lock_guard<std::mutex> lk(mu);
-          if (queue.empty() || (int)active.size() >= o.max_active) break;
+          const int busy = (int)active.size() + batched_count();
+          if (queue.empty() || busy >= o.max_active) break;
           Req* h = queue.front();
-          if (used + h->footprint > o.hbm_budget && !active.empty()) break;
+          if (used + h->footprint > o.hbm_budget && busy > 0) break;
           queue.pop_front();
           used += h->footprint;
           q = h;
@@ -162,10 +257,11 @@ struct mmp_server_s {
         q->t_admit = now();
         const int rc = start_request(q);
         if (rc) finish(q, rc);
-        else active.push_back(q);
+        else if (!q->batched) active.push_back(q);
       }
       // progress
       bool any = false;
+      for (auto& B : batches) any |= step_batch(B);
       for (size_t i = 0; i < active.size();) {
         Req* q = active[i];
         bool fin = false;
@@ -194,6 +290,16 @@ struct mmp_server_s {
     }
     for (Req* q : active) finish(q, MMP_E_STATE);
     active.clear();
+    for (auto& B : batches) {
+      if (B.b) {
+        while (B.b->in_flight() > 0 && B.b->poll() == MMP_PENDING) {
+        }
+      }
+      for (Req* q : B.members) finish(q, MMP_E_STATE);
+      for (Req* q : B.joining) finish(q, MMP_E_STATE);
+      B.members.clear();
+      B.joining.clear();
+    }
   }
 };
 

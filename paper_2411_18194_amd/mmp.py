@@ -75,7 +75,7 @@ class RunInfo(C.Structure):
 
 class ServerOpts(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("hbm_budget", C.c_int64),
-                ("max_active", C.c_int32), ("precision", C.c_int32)]
+                ("max_active", C.c_int32), ("precision", C.c_int32), ("batch", C.c_int32)]
 
 
 class Request(C.Structure):
@@ -374,13 +374,14 @@ class Grid:
 class Server:
     """Continuous-batching request server in the HIP library."""
 
-    def __init__(self, hbm_budget, max_active=8, precision=FP32):
+    def __init__(self, hbm_budget, max_active=8, precision=FP32, batch=True):
         self.lib = load()
         o = ServerOpts()
         o.struct_size = C.sizeof(ServerOpts)
         o.hbm_budget = int(hbm_budget)
         o.max_active = max_active
         o.precision = precision
+        o.batch = 1 if batch else 0
         h = C.c_void_p()
         _check(self.lib.mmp_server_create(C.byref(o), C.byref(h)))
         self.h = h

@@ -87,3 +87,38 @@ def test_server_matches_direct_run():
         assert out.steps == info.steps and out.rejects == info.rejects
         got = np.array([[out.m_avg[s][c] for c in range(3)] for s in range(ns)])
         assert np.allclose(got, m, rtol=0, atol=1e-12)
+
+
+def _small_afm(n, seed):
+    p = inputs.base_params(n, (1.5e-9,) * 3, nsub=2)
+    p.update(Ms=[4e5, 4e5], A11=[1e-11, 1e-11], alpha=[0.05, 0.05], A0=-2.5e-11,
+             A12=-5e-12, latcon=0.35e-9, Ku1=[6e4, 6e4], demag=False)
+    m = inputs.smoothed_random_unit(inputs.rng(seed), 1, n, sigma=1.5)
+    return p, np.concatenate([m, -m])
+
+
+@pytest.mark.parametrize("batch", [True, False])
+def test_batched_afm_requests_match_alone(batch):
+    """Requests without demag of different sizes step together in one batch
+    (one launch per stage for all of them), join at different times and
+    leave when done; each result equals the same relaxation run alone."""
+    cases = [_small_afm(n, 40 + i) for i, n in
+             enumerate(((48, 20, 1), (17, 33, 3), (64, 64, 1), (5, 7, 2), (40, 24, 2)))]
+    t_relax = [4e-12, 7e-12, 3e-12, 9e-12, 5e-12]
+    srv = mmp.Server(hbm_budget=8 << 30, max_active=3, precision=mmp.FP32, batch=batch)
+    tickets = [srv.submit(p, m, t) for (p, m), t in zip(cases, t_relax)]
+    res = [srv.wait(t) for t in tickets]
+    srv.close()
+    for (p, m), t, out in zip(cases, t_relax, res):
+        assert out.status == 0
+        g = mmp.Grid(p, mmp.FP32)
+        g.set_state(m)
+        info, _, _ = g.run(t)
+        ref = g.get_state()[0].reshape(2, 3, -1).mean(axis=2)
+        _, e = g.eval_heff(mmp.T_ALL, want_b=False)
+        g.close()
+        assert (out.steps, out.rejects) == (info.steps, info.rejects)
+        got = np.array([[out.m_avg[s][c] for c in range(3)] for s in range(2)])
+        assert np.allclose(got, ref, rtol=0, atol=1e-12)
+        etot = sum(e.values())
+        assert abs(out.energy - etot) <= 1e-9 * abs(etot)
