@@ -105,14 +105,19 @@ __global__ __launch_bounds__(256) void k4_ffty(Y4Args<T> a) {
   const int gl = blockIdx.x * a.nl + q;
   const bool valid = gl < a.nlines;
   V* line = lds + q * L;
-  const V* in = a.in + (long)gl * a.ld_in;
+  // loads are unconditional (clamped to element 0 of line 0) and zeroed
+  // afterwards, so they all go out before the first wait
+  const V* in = a.in + (long)(valid ? gl : 0) * a.ld_in;
   V v[L1];
   constexpr int NLOAD = (!INV && L1 >= 2) ? L1 / 2 : L1;
 #pragma unroll
   for (int n1 = 0; n1 < NLOAD; ++n1) {
     const int idx = L2 * n1 + t;
-    v[n1] = (valid && idx < a.nvalid_in) ? in[idx] : cmk<T>(0, 0);
+    v[n1] = in[idx < a.nvalid_in ? idx : 0];
   }
+#pragma unroll
+  for (int n1 = 0; n1 < NLOAD; ++n1)
+    if (!valid || L2 * n1 + t >= a.nvalid_in) v[n1] = cmk<T>(0, 0);
   fs_step1<T, L1, L2, INV, !INV>(v, line, a.tw4, t);
   __syncthreads();
   V u[L1 / L2][L2];
@@ -149,21 +154,30 @@ __global__ __launch_bounds__(256) void k4_fftx_fwd(X4Args<T> a) {
   V* line = lds + q * L;
   V v[L1];
   constexpr int NLOAD = L1 >= 2 ? L1 / 2 : L1;
+  // rows ya, yb (clamped to row 0 past ny, column 0 past nx): every load is
+  // unconditional so they all go out before the first wait
+  const long ra = (long)(ya < a.ny ? ya : 0) * a.nx, rb = (long)(yb < a.ny ? yb : 0) * a.nx;
+  T xa[NLOAD], xb[NLOAD];
 #pragma unroll
   for (int n1 = 0; n1 < NLOAD; ++n1) {
     const int x = L2 * n1 + t;
-    T re = 0, im = 0;
-    if (x < a.nx) {
-      if (ya < a.ny) {
-        re = a.ms0 * m0[(long)ya * a.nx + x];
-        if (a.nsub == 2) re += a.ms1 * m1[(long)ya * a.nx + x];
-      }
-      if (yb < a.ny) {
-        im = a.ms0 * m0[(long)yb * a.nx + x];
-        if (a.nsub == 2) im += a.ms1 * m1[(long)yb * a.nx + x];
-      }
+    const int xc = x < a.nx ? x : 0;
+    xa[n1] = a.ms0 * m0[ra + xc];
+    xb[n1] = a.ms0 * m0[rb + xc];
+  }
+  if (a.nsub == 2) {
+#pragma unroll
+    for (int n1 = 0; n1 < NLOAD; ++n1) {
+      const int x = L2 * n1 + t;
+      const int xc = x < a.nx ? x : 0;
+      xa[n1] += a.ms1 * m1[ra + xc];
+      xb[n1] += a.ms1 * m1[rb + xc];
     }
-    v[n1] = cmk<T>(re, im);
+  }
+#pragma unroll
+  for (int n1 = 0; n1 < NLOAD; ++n1) {
+    const bool inx = L2 * n1 + t < a.nx;
+    v[n1] = cmk<T>(inx && ya < a.ny ? xa[n1] : T(0), inx && yb < a.ny ? xb[n1] : T(0));
   }
   fs_step1<T, L1, L2, false, true>(v, line, a.tw4, t);
   __syncthreads();
@@ -200,12 +214,27 @@ __global__ __launch_bounds__(256) void k4_fftx_inv(X4Args<T> a) {
   const int c = blockIdx.z, z = blockIdx.y, y0 = blockIdx.x * a.ty;
   const int nl = a.ty >> 1;
   const V* in = a.S1 + ((long)(c * a.nz + z) * a.Hx) * a.ldy + y0;
-  for (int idx = tid; idx < nl * a.Hx; idx += nthr) {
-    const int qq = idx & (nl - 1), kx = idx >> a.lnl;
-    V xa, xb;
-    load2<T>(in + (long)kx * a.ldy + 2 * qq, xa, xb);
-    lds[qq * L + kx] = cmk<T>(xa.x - xb.y, xa.y + xb.x);
-    if (kx > 0 && 2 * kx < L) lds[qq * L + L - kx] = cmk<T>(xa.x + xb.y, xb.x - xa.y);
+  // (spectrum pairs of the block) / threads = Hx / L2 <= L1/2 + 1: all
+  // loads unconditional (clamped to pair 0), issued before the first wait
+  constexpr int NI = L1 / 2 + 1;
+  const int npair = nl * a.Hx;
+  V pa[NI], pb[NI];
+#pragma unroll
+  for (int j = 0; j < NI; ++j) {
+    const int idx = tid + j * nthr;
+    const int ic = idx < npair ? idx : 0;
+    const int qq = ic & (nl - 1), kx = ic >> a.lnl;
+    load2<T>(in + (long)kx * a.ldy + 2 * qq, pa[j], pb[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < NI; ++j) {
+    const int idx = tid + j * nthr;
+    if (idx < npair) {
+      const int qq = idx & (nl - 1), kx = idx >> a.lnl;
+      const V xa = pa[j], xb = pb[j];
+      lds[qq * L + kx] = cmk<T>(xa.x - xb.y, xa.y + xb.x);
+      if (kx > 0 && 2 * kx < L) lds[qq * L + L - kx] = cmk<T>(xa.x + xb.y, xb.x - xa.y);
+    }
   }
   __syncthreads();
   V* line = lds + q * L;

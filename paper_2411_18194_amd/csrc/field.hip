@@ -97,31 +97,36 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
     const long col = (long)y * a.nx + x;
     const long plane = (long)a.nx * a.ny;
     const long i0 = (long)z0 * plane + col;
+    // A missing neighbour is the cell itself, so every neighbour load is an
+    // unconditional load from a clamped offset: no branches between the
+    // loads, which then all go out before the first wait.
+    const long dxm = x > 0 ? -1 : 0, dxp = x + 1 < a.nx ? 1 : 0;
+    const long dym = y > 0 ? -(long)a.nx : 0, dyp = y + 1 < a.ny ? (long)a.nx : 0;
+    const long dz0 = z0 > 0 ? -plane : 0;
 #pragma unroll
     for (int s = 0; s < NSUB; ++s)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         cur[s][c] = m[s * N3 + c * N + i0];
-        zm[s][c] = z0 > 0 ? m[s * N3 + c * N + i0 - plane] : cur[s][c];
+        zm[s][c] = m[s * N3 + c * N + i0 + dz0];
       }
     for (int z = z0; z < z1; ++z) {
       const long i = (long)z * plane + col;
+      const long dzp = z + 1 < a.nz ? plane : 0;
 #pragma unroll
       for (int s = 0; s < NSUB; ++s)
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-          zp[s][c] = (z + 1 < a.nz) ? m[s * N3 + c * N + i + plane] : cur[s][c];
-      // clamped in-plane neighbours
+        for (int c = 0; c < 3; ++c) zp[s][c] = m[s * N3 + c * N + i + dzp];
       T xm[NSUB][3], xp[NSUB][3], ym[NSUB][3], yp[NSUB][3];
 #pragma unroll
       for (int s = 0; s < NSUB; ++s)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const T* mc = m + s * N3 + c * N + i;
-          xm[s][c] = x > 0 ? mc[-1] : cur[s][c];
-          xp[s][c] = x + 1 < a.nx ? mc[1] : cur[s][c];
-          ym[s][c] = y > 0 ? mc[-a.nx] : cur[s][c];
-          yp[s][c] = y + 1 < a.ny ? mc[a.nx] : cur[s][c];
+          xm[s][c] = mc[dxm];
+          xp[s][c] = mc[dxp];
+          ym[s][c] = mc[dym];
+          yp[s][c] = mc[dyp];
         }
       T Bd[3] = {0, 0, 0};
       if (a.has_demag) {
@@ -318,12 +323,34 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
           kout[base + 2 * N] = tau[2];
           if (stage < 7) {
             T v[3];
+            if constexpr (NSUB == 1) {
+              // the slopes this stage needs are loaded first (uniform
+              // branches on the stage, no use in between), then summed in
+              // order.  (Two sublattices would need twice the registers and
+              // lose more waves than the batching gains.)
+              T kv[5][3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              T acc = yn[base + c * N];
-              for (int j = 0; j < stage - 1; ++j) acc += ca[j] * kin[j][base + c * N];
-              acc += ca[stage - 1] * tau[c];
-              v[c] = acc;
+              for (int j = 0; j < 5; ++j)
+                if (j < stage - 1)
+#pragma unroll
+                  for (int c = 0; c < 3; ++c) kv[j][c] = kin[j][base + c * N];
+#pragma unroll
+              for (int c = 0; c < 3; ++c) {
+                T acc = yn[base + c * N];
+#pragma unroll
+                for (int j = 0; j < 5; ++j)
+                  if (j < stage - 1) acc += ca[j] * kv[j][c];
+                acc += ca[stage - 1] * tau[c];
+                v[c] = acc;
+              }
+            } else {
+#pragma unroll
+              for (int c = 0; c < 3; ++c) {
+                T acc = yn[base + c * N];
+                for (int j = 0; j < stage - 1; ++j) acc += ca[j] * kin[j][base + c * N];
+                acc += ca[stage - 1] * tau[c];
+                v[c] = acc;
+              }
             }
             const T inv = T(1) / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
             ynext[base] = v[0] * inv;
@@ -331,12 +358,29 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
             ynext[base + 2 * N] = v[2] * inv;
           } else if (!fuse2) {
             double ev[3];
+            if constexpr (NSUB == 1) {
+              T kv[6][3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              double acc = DP::e[6] * (double)tau[c];
               for (int j = 0; j < 6; ++j)
-                if (DP::e[j] != 0.0) acc += DP::e[j] * (double)kin[j][base + c * N];
-              ev[c] = acc;
+                if (DP::e[j] != 0.0)
+#pragma unroll
+                  for (int c = 0; c < 3; ++c) kv[j][c] = kin[j][base + c * N];
+#pragma unroll
+              for (int c = 0; c < 3; ++c) {
+                double acc = DP::e[6] * (double)tau[c];
+#pragma unroll
+                for (int j = 0; j < 6; ++j)
+                  if (DP::e[j] != 0.0) acc += DP::e[j] * (double)kv[j][c];
+                ev[c] = acc;
+              }
+            } else {
+#pragma unroll
+              for (int c = 0; c < 3; ++c) {
+                double acc = DP::e[6] * (double)tau[c];
+                for (int j = 0; j < 6; ++j)
+                  if (DP::e[j] != 0.0) acc += DP::e[j] * (double)kin[j][base + c * N];
+                ev[c] = acc;
+              }
             }
             const double nrm = sqrt(ev[0] * ev[0] + ev[1] * ev[1] + ev[2] * ev[2]);
             emax = nrm > emax ? nrm : emax;
