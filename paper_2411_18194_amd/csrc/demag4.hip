@@ -262,28 +262,6 @@ __global__ __launch_bounds__(256) void k4_fftx_inv(X4Args<T> a) {
     }
 }
 
-// row c of the symmetric kernel applied to (Mx, My, Mz)
-template <typename T>
-__device__ __forceinline__ cpx<T> krow(int c, cpx<T> mx, cpx<T> my, cpx<T> mz,
-                                       const T* __restrict__ K, long kidx, long ks, T sy, T sz,
-                                       bool three_d) {
-  T k0, k1, k2;
-  if (c == 0) {
-    k0 = K[kidx];
-    k1 = sy * K[kidx + 3 * ks];
-    k2 = three_d ? sz * K[kidx + 4 * ks] : T(0);
-  } else if (c == 1) {
-    k0 = sy * K[kidx + 3 * ks];
-    k1 = K[kidx + ks];
-    k2 = three_d ? sy * sz * K[kidx + 5 * ks] : T(0);
-  } else {
-    k0 = three_d ? sz * K[kidx + 4 * ks] : T(0);
-    k1 = three_d ? sy * sz * K[kidx + 5 * ks] : T(0);
-    k2 = K[kidx + 2 * ks];
-  }
-  return cmk<T>(k0 * mx.x + k1 * my.x + k2 * mz.x, k0 * mx.y + k1 * my.y + k2 * mz.y);
-}
-
 // ---------------------------------------------- 2-D fused y + multiply --
 template <typename T, int L1, int L2>
 __global__ __launch_bounds__(256) void k4_ffty_mul2d(M4Args<T> a) {
@@ -320,14 +298,29 @@ __global__ __launch_bounds__(256) void k4_ffty_mul2d(M4Args<T> a) {
   const V* ly = lds + (1 * a.nk + j) * L;
   const V* lz = lds + (2 * a.nk + j) * L;
   const long ks = (long)a.Hx * a.Hy;
+  // row c of the 2-D kernel (K_xz = K_yz = 0):  c = 0: (xx, sy xy, 0),
+  // c = 1: (sy xy, yy, 0),  c = 2: (0, 0, zz).  Both kernel values of every
+  // ky are loaded first (kx clamped for the idle columns past Hx), so the
+  // loads go out back to back.
+  const T* kc = a.K + (long)(valid ? kx : 0) * a.Hy;
+  const long oa = (c == 0 ? 0 : c == 1 ? 3 : 2) * ks, ob = (c == 0 ? 3 : c == 1 ? 1 : 2) * ks;
+  T ka[L1], kb[L1];
 #pragma unroll
   for (int n1 = 0; n1 < L1; ++n1) {
     const int ky = L2 * n1 + t;
     const int kyo = ky <= L / 2 ? ky : L - ky;
+    ka[n1] = kc[oa + kyo];
+    kb[n1] = kc[ob + kyo];
+  }
+#pragma unroll
+  for (int n1 = 0; n1 < L1; ++n1) {
+    const int ky = L2 * n1 + t;
     const T sy = ky <= L / 2 ? T(1) : T(-1);
-    v[n1] = valid ? krow<T>(c, lx[ky], ly[ky], lz[ky], a.K, (long)kx * a.Hy + kyo, ks, sy, T(1),
-                            false)
-                  : cmk<T>(0, 0);
+    const V m1 = c == 2 ? lz[ky] : lx[ky];
+    const V m2 = ly[ky];
+    const T f1 = c == 1 ? sy * ka[n1] : ka[n1];
+    const T f2 = c == 2 ? T(0) : (c == 0 ? sy * kb[n1] : kb[n1]);
+    v[n1] = valid ? cmk<T>(f1 * m1.x + f2 * m2.x, f1 * m1.y + f2 * m2.y) : cmk<T>(0, 0);
   }
   __syncthreads();
   fs_step1<T, L1, L2, true>(v, line, a.tw4, t);
