@@ -15,13 +15,22 @@
 
 namespace mmp {
 
+// The five points are loaded unconditionally from offsets clamped to the
+// axis (so all loads of a cell go out together), then the scheme of this
+// position is applied.
 template <typename T>
 __device__ __forceinline__ T d1(const T* __restrict__ f, long idx, int i, int n, long s, T h) {
-  if (n == 1) return T(0);
-  if (i == 0) return (f[idx + s] - f[idx]) / h;
-  if (i == n - 1) return (f[idx] - f[idx - s]) / h;
-  if (i == 1 || i == n - 2) return (f[idx + s] - f[idx - s]) / (T(2) * h);
-  return (-f[idx + 2 * s] + T(8) * f[idx + s] - T(8) * f[idx - s] + f[idx - 2 * s]) / (T(12) * h);
+  const long om2 = (long)(max(i - 2, 0) - i) * s, om1 = (long)(max(i - 1, 0) - i) * s;
+  const long op1 = (long)(min(i + 1, n - 1) - i) * s, op2 = (long)(min(i + 2, n - 1) - i) * s;
+  const T fm2 = f[idx + om2], fm1 = f[idx + om1], f0 = f[idx], fp1 = f[idx + op1],
+          fp2 = f[idx + op2];
+  // every candidate is formed (selects, not branches, so no load is sunk
+  // into a branch)
+  const T r_lo = (fp1 - f0) / h, r_hi = (f0 - fm1) / h;
+  const T r_c2 = (fp1 - fm1) / (T(2) * h);
+  const T r_c4 = (-fp2 + T(8) * fp1 - T(8) * fm1 + fm2) / (T(12) * h);
+  const T r = (i == 1 || i == n - 2) ? r_c2 : r_c4;
+  return n == 1 ? T(0) : (i == 0 ? r_lo : (i == n - 1 ? r_hi : r));
 }
 
 template <typename T>
