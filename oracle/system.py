@@ -22,7 +22,7 @@ from . import elastic as el
 from . import fields as fl
 from . import torque as tq
 from .demag import Demag
-from .rk import Stepper, new_dt
+from .rk import TABLEAUS, Stepper, new_dt
 
 TERMS = ("demag", "exch", "afm_nn", "afm_cell", "dmi", "anis_u", "anis_c",
          "zeeman", "mel")
@@ -41,7 +41,8 @@ class Problem:
         self.axis = None
         if p.get("grain") is not None:
             self.axis = np.moveaxis(np.asarray(p["grain_axes"])[p["grain"]], -1, 0)
-        self.stepper = Stepper(self.rhs, self.normalise, self.err_norm)
+        self.tableau = TABLEAUS[p.get("solver", "dp45")]
+        self.stepper = Stepper(self.rhs, self.normalise, self.err_norm, self.tableau)
 
     # ----------------------------------------------------------- fields --
     def strain(self, u):
@@ -197,17 +198,17 @@ class Problem:
         return y
 
     def run_fixed(self, y, t0, dt, nsteps):
-        """nsteps DP45 steps of size dt with no step control."""
+        """nsteps steps of size dt with no step control."""
         t = t0
         for i in range(nsteps):
-            y, k7, _ = self.stepper.step(t, y, dt)
-            self.stepper.accept(k7)
+            y, knext, _ = self.stepper.step(t, y, dt)
+            self.stepper.accept(knext)
             t = t0 + (i + 1) * dt
         return y, t
 
     def run(self, y, t0, t_end, tol=1e-5, dt0=1e-14, dt_min=1e-20,
             sample_every=None, sample=None, max_steps=10 ** 9):
-        """Adaptive DP45 from t0 to t_end; returns (y, t, info, samples).
+        """Adaptive stepping from t0 to t_end; returns (y, t, info, samples).
 
         A step that would pass the next output time (t0 + k*sample_every,
         or t_end) is shortened to land on it exactly.  An output time closer
@@ -231,10 +232,10 @@ class Problem:
             remaining = target - t
             land = dt >= remaining
             h = remaining if land else dt
-            ynew, k7, err = self.stepper.step(t, y, h)
+            ynew, knext, err = self.stepper.step(t, y, h)
             if err <= tol:
                 y = ynew
-                self.stepper.accept(k7)
+                self.stepper.accept(knext)
                 t = target if land else t + h
                 steps += 1
                 if land and sample_every and t == next_out:
@@ -244,7 +245,7 @@ class Problem:
                     next_out = out_time(k)
             else:
                 rejects += 1
-            dt = new_dt(h, err, tol)
+            dt = new_dt(h, err, tol, self.tableau.q)
             if dt < dt_min:
                 raise RuntimeError("time step underflow")
         return y, t, dict(steps=steps, rejects=rejects, dt=dt), samples

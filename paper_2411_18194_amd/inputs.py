@@ -79,6 +79,7 @@ def base_params(n, cell, nsub=1):
         "grain": None,
         "grain_axes": None,
         "elastic": None,
+        "solver": "dp45",
     }
 
 

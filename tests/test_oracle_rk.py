@@ -1,8 +1,11 @@
 """Pins for the oracle's time integration and torques (not GPU).
 
-* The Dormand-Prince tableau satisfies the order conditions of a 5th-order
-  method (b) and of a 4th-order method (b*), with row sums c_i.
-* 5th-order convergence on a smooth ODE (error ratio ~32 per halving).
+* Every pair of the solver table meets Butcher's order conditions (all
+  rooted trees, exact in fractions) up to exactly its printed convergence
+  order (b) and error-estimate order (b*), with row sums c_i; first-same-
+  as-last pairs end on b.
+* Each pair converges at its printed order on a smooth ODE, and its error
+  estimate scales as h^(q+1).
 * A single spin in a static field B z follows the closed-form damped
   precession phi = phi0 + g' B t, tan(theta/2) = tan(theta0/2) exp(-a g' B t),
   g' = gamma/(1+a^2); the precession frequency is gamma B/(2 pi (1+a^2)).
@@ -29,67 +32,148 @@ from oracle.system import Problem
 from paper_2411_18194_amd import inputs
 
 
-def test_order_conditions():
+# ------------------------------------------------ Butcher order conditions --
+# Rooted trees in canonical form (a tree is the sorted tuple of its
+# subtrees); every tree of order n + 1 arises by attaching a leaf to some
+# node of a tree of order n.
+
+def _canon(t):
+    return tuple(sorted(_canon(c) for c in t))
+
+
+def _grow(t):
+    out = {_canon(t + ((),))}
+    for i, c in enumerate(t):
+        for g in _grow(c):
+            out.add(_canon(t[:i] + (g,) + t[i + 1:]))
+    return out
+
+
+def _trees(n):
+    level = {()}
+    for _ in range(n - 1):
+        level = set().union(*(_grow(t) for t in level))
+    return sorted(level)
+
+
+def _order(t):
+    return 1 + sum(_order(c) for c in t)
+
+
+def _gamma(t):
+    g = _order(t)
+    for c in t:
+        g *= _gamma(c)
+    return g
+
+
+def _phi(tab, t):
+    """Elementary weights Phi_i(t) of every stage i."""
+    s = tab.stages
+    out = [F(1)] * s
+    for c in t:
+        pc = _phi(tab, c)
+        for i in range(s):
+            out[i] *= sum((tab.a[i][j] * pc[j] for j in range(i)), F(0))
+    return out
+
+
+def _meets(tab, w, t):
+    return sum(wi * x for wi, x in zip(w, _phi(tab, t))) == F(1, _gamma(t))
+
+
+def test_rooted_tree_counts():
+    # 1, 1, 2, 4, 9, 20 rooted trees of orders 1..6
+    assert [len(_trees(n)) for n in range(1, 7)] == [1, 1, 2, 4, 9, 20]
+
+
+def _printed():
     with open(os.path.join(os.path.dirname(__file__), "golden", "paper_printed.json")) as fh:
-        printed = json.load(fh)["rk_solvers"]["Dormand-Prince"]
-    c, A, b, bs = rk.C, rk.A, rk.B5, rk.B4
-    for i in range(1, 7):
-        assert sum(A[i]) == c[i]
-    # the solver table prints convergence order 5 and error-estimate order 4
-    for w, order in ((b, printed[0]), (bs, printed[1])):
-        s = len(w)
-        cc = c[:s]
-
-        def Ac(v):
-            return [sum((A[i][j] * v[j] for j in range(i)), F(0)) if i > 0 else F(0)
-                    for i in range(s)]
-        assert sum(w) == 1
-        assert sum(wi * ci for wi, ci in zip(w, cc)) == F(1, 2)
-        assert sum(wi * ci ** 2 for wi, ci in zip(w, cc)) == F(1, 3)
-        assert sum(wi * x for wi, x in zip(w, Ac(cc))) == F(1, 6)
-        assert sum(wi * ci ** 3 for wi, ci in zip(w, cc)) == F(1, 4)
-        assert sum(wi * ci * x for wi, ci, x in zip(w, cc, Ac(cc))) == F(1, 8)
-        assert sum(wi * x for wi, x in zip(w, Ac([ci ** 2 for ci in cc]))) == F(1, 12)
-        assert sum(wi * x for wi, x in zip(w, Ac(Ac(cc)))) == F(1, 24)
-        fifth = sum(wi * ci ** 4 for wi, ci in zip(w, cc)) == F(1, 5)
-        assert fifth == (order == 5)
-    # FSAL: the last row is b
-    assert A[6] == rk.B5[:6]
+        return json.load(fh)["rk_solvers"]
 
 
-def test_fifth_order_convergence():
-    def rhs(t, y):
-        return [np.array([y[0][0] * math.cos(t) - y[0][1], y[0][0] + 0.3 * y[0][1]])]
-
-    def run(n):
-        st = rk.Stepper(rhs, lambda y: y, lambda e: 0.0)
-        y = [np.array([1.0, 0.5])]
-        h = 2.0 / n
-        for i in range(n):
-            y, k7, _ = st.step(i * h, y, h)
-            st.accept(k7)
-        return y[0]
-    ref = run(2048)
-    e1 = np.abs(run(16) - ref).max()
-    e2 = np.abs(run(32) - ref).max()
-    assert 26 < e1 / e2 < 40
+SOLVERS = {"heun": "Heun", "bs23": "Bogacki-Shampine", "cashkarp": "Cash-Karp",
+           "rkf45": "Fehlberg", "dp45": "Dormand-Prince"}
 
 
-def _single_spin(alpha, B, th0, t_end, demag=False):
+@pytest.mark.parametrize("name", sorted(SOLVERS))
+def test_order_conditions(name):
+    """b has exactly the printed convergence order and b* the printed
+    error-estimate order: every condition up to that order holds exactly,
+    and one of the next order fails."""
+    tab = rk.TABLEAUS[name]
+    p, q = _printed()[SOLVERS[name]]
+    assert (tab.p, tab.q) == (p, q)
+    s = tab.stages
+    assert len(tab.a) == s and len(tab.b) == s and len(tab.bs) == s
+    for i in range(s):
+        assert len(tab.a[i]) == i and sum(tab.a[i], F(0)) == tab.c[i]
+    for w, order in ((tab.b, p), (tab.bs, q)):
+        for n in range(1, order + 1):
+            for t in _trees(n):
+                assert _meets(tab, w, t), (name, order, t)
+        assert not all(_meets(tab, w, t) for t in _trees(order + 1)), (name, order)
+    if tab.fsal:
+        # the last stage is evaluated at the propagated solution
+        assert tab.c[-1] == 1 and tab.b[-1] == 0 and tuple(tab.a[-1]) == tuple(tab.b[:-1])
+
+
+def _ode(t, y):
+    return [np.array([y[0][0] * math.cos(t) - y[0][1], y[0][0] + 0.3 * y[0][1]])]
+
+
+def _integrate(tab, n, t_end=2.0):
+    st = rk.Stepper(_ode, lambda y: y, lambda e: 0.0, tab)
+    y = [np.array([1.0, 0.5])]
+    h = t_end / n
+    for i in range(n):
+        y, kn, _ = st.step(i * h, y, h)
+        st.accept(kn)
+    return y[0]
+
+
+@pytest.mark.parametrize("name", sorted(SOLVERS))
+def test_convergence_order(name):
+    """Halving the step divides the global error by ~2^p."""
+    tab = rk.TABLEAUS[name]
+    ref = _integrate(rk.DORMAND_PRINCE, 4096)
+    n = {2: 128, 3: 64, 5: 16}[tab.p]
+    e1 = np.abs(_integrate(tab, n) - ref).max()
+    e2 = np.abs(_integrate(tab, 2 * n) - ref).max()
+    assert 0.75 * 2 ** tab.p < e1 / e2 < 1.3 * 2 ** tab.p, (name, e1 / e2)
+
+
+@pytest.mark.parametrize("name", sorted(SOLVERS))
+def test_error_estimate_order(name):
+    """The one-step estimate |h sum e_j k_j| scales as h^(q+1)."""
+    tab = rk.TABLEAUS[name]
+
+    def est(h):
+        st = rk.Stepper(_ode, lambda y: y, lambda e: float(np.abs(e[0]).max()), tab)
+        return st.step(0.3, [np.array([1.0, 0.5])], h)[2]
+    r = est(0.02) / est(0.01)
+    assert 0.75 * 2 ** (tab.q + 1) < r < 1.3 * 2 ** (tab.q + 1), (name, r)
+
+
+def _single_spin(alpha, B, th0, t_end, demag=False, solver="dp45", tol=1e-9):
     p = inputs.base_params((1, 1, 1), (3e-9,) * 3)
-    p.update(Ms=[8e5], alpha=[alpha], B_ext=(0.0, 0.0, B), demag=demag)
+    p.update(Ms=[8e5], alpha=[alpha], B_ext=(0.0, 0.0, B), demag=demag, solver=solver)
     m = np.array([math.sin(th0), 0.0, math.cos(th0)]).reshape(1, 3, 1, 1, 1)
     P = Problem(p)
-    samples = []
-    y, t, info, s = P.run([m], 0.0, t_end, tol=1e-9, dt0=1e-14,
+    y, t, info, s = P.run([m], 0.0, t_end, tol=tol, dt0=1e-14,
                           sample_every=t_end / 20, sample=lambda y: y[0].ravel().copy())
+    assert t == t_end and len(s) == 21
     return p, s
 
 
-@pytest.mark.parametrize("alpha,demag", [(0.0, False), (0.1, False), (0.02, True)])
-def test_single_spin_closed_form(alpha, demag):
+@pytest.mark.parametrize("alpha,demag,solver,tol", [
+    (0.0, False, "dp45", 1e-9), (0.1, False, "dp45", 1e-9), (0.02, True, "dp45", 1e-9),
+    (0.1, False, "heun", 1e-7), (0.1, False, "bs23", 1e-8), (0.1, False, "cashkarp", 1e-8),
+    (0.1, False, "rkf45", 1e-8)])
+def test_single_spin_closed_form(alpha, demag, solver, tol):
+    """Adaptive runs under every pair of the solver table."""
     B, th0 = 0.1, 1.0
-    p, s = _single_spin(alpha, B, th0, 200e-12, demag)
+    p, s = _single_spin(alpha, B, th0, 200e-12, demag, solver, tol)
     gp = p["gamma"] / (1 + alpha ** 2)
     for t, m in s:
         th = 2 * math.atan(math.tan(th0 / 2) * math.exp(-alpha * gp * B * t))
