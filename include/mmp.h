@@ -2,8 +2,8 @@
  * mmp.h - C ABI of the MI355X micromagnetic hot path (libmmp.so).
  *
  * The library evaluates the effective field of a finite-difference
- * micromagnet and integrates the Landau-Lifshitz-Gilbert equation with the
- * Dormand-Prince 5(4) Runge-Kutta pair, following Moreels et al., "mumax+:
+ * micromagnet and integrates the Landau-Lifshitz-Gilbert equation with an
+ * embedded Runge-Kutta pair, following Moreels et al., "mumax+:
  * extensible GPU-accelerated micromagnetics and beyond" (arXiv 2411.18194),
  * Methods section:
  *   dm/dt = tau (Eq. 1), tau = LLG torque (Eq. 2) + Zhang-Li torque;
@@ -13,7 +13,8 @@
  *   interfacial DMI (Eq. 4 special case, boundary condition Eq. 5) +
  *   uniaxial/cubic anisotropy + Zeeman + magnetoelastic field (Eq. 9);
  *   elastodynamics (Eq. 7) with the magnetoelastic force (Eq. 8);
- *   the time solver is the Dormand-Prince pair of Table 2.
+ *   the time solvers are the five embedded pairs of Table 2 (Dormand-Prince
+ *   5(4) by default).
  *
  * Conventions
  *   Units are SI; fields are in tesla.  Host arrays are FP64, structure of
@@ -53,6 +54,15 @@ typedef int32_t mmp_status;
 
 #define MMP_FP32 0
 #define MMP_FP64 1
+
+/* Embedded Runge-Kutta pairs (Table 2 of the paper: convergence order /
+ * error-estimate order).  The higher-order solution is propagated; the
+ * step-size factor is 0.8 (tol/err)^(1/(q+1)) clipped to [0.1, 2]. */
+#define MMP_RK_DP45      0  /* Dormand-Prince 5/4, first same as last     */
+#define MMP_RK_HEUN      1  /* Heun 2/1 (Euler embedded)                  */
+#define MMP_RK_BS23      2  /* Bogacki-Shampine 3/2, first same as last   */
+#define MMP_RK_CASHKARP  3  /* Cash-Karp 5/4                              */
+#define MMP_RK_FEHLBERG  4  /* Fehlberg 5/4, 5th order propagated         */
 
 /* Effective-field terms (bit mask for mmp_eval_heff). */
 #define MMP_T_DEMAG     (1u << 0)  /* magnetostatic field                  */
@@ -115,6 +125,8 @@ typedef struct {
   double tol;             /* adaptive error tolerance (default 1e-5)       */
   double dt0;             /* first adaptive step, s (default 1e-14)        */
   double dt_min;          /* underflow limit, s (default 1e-20)            */
+  int32_t solver;         /* MMP_RK_*: embedded Runge-Kutta pair           */
+  int32_t pad1;
 } mmp_params;
 
 typedef struct {

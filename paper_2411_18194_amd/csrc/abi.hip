@@ -135,6 +135,7 @@ mmp_status mmp_set_params(mmp_grid g, const mmp_params* p) {
   if (p->struct_size != sizeof(mmp_params)) { set_error("mmp_params struct_size mismatch"); return MMP_E_ARG; }
   if (p->precision != MMP_FP32 && p->precision != MMP_FP64) { set_error("bad precision"); return MMP_E_ARG; }
   if (p->nsub != 1 && p->nsub != 2) { set_error("nsub must be 1 or 2"); return MMP_E_ARG; }
+  if (p->solver < 0 || p->solver >= RK_COUNT) { set_error("unknown solver"); return MMP_E_ARG; }
   if (p->ngrains < 0 || p->ngrains > 65536 || (p->ngrains > 0 && (!p->grain || !p->grain_axes))) {
     set_error("bad grain description");
     return MMP_E_ARG;

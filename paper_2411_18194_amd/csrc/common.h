@@ -37,22 +37,73 @@ __device__ __forceinline__ V cconj(V a) { V r; r.x = a.x; r.y = -a.y; return r; 
 template <typename V, typename S>
 __device__ __forceinline__ V cscale(V a, S s) { V r; r.x = a.x * s; r.y = a.y * s; return r; }
 
-// ------------------------------------------------- Dormand-Prince 5(4) --
-// Tableau of Dormand & Prince (1980); Table 2 of the paper lists the pair.
-struct DP {
-  static constexpr double c[7] = {0.0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1.0, 1.0};
-  static constexpr double a[7][6] = {
-      {0, 0, 0, 0, 0, 0},
-      {1.0 / 5, 0, 0, 0, 0, 0},
-      {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
-      {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
-      {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
-      {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
-      {35.0 / 384, 0.0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84},
+// ------------------------------------------------ embedded RK pairs --
+// The five pairs of Table 2, as run on the device.  Stage s (1-based) of an
+// attempt evaluates k_s at stage input s = y_n + h sum_{j<s} a[s-1][j] k_j;
+// the input of the last stage ns is the propagated solution y_{n+1} (row
+// ns-1 of a is b) and its slope becomes the next step's k_1.  For the pairs
+// that are first-same-as-last that stage is their own; for the others it is
+// the evaluation the next step would start with, so it is appended with
+// c = 1, a = b and e = 0 and the number of evaluations per step is
+// unchanged.  e = b - b* weighs the error estimate, q is its order.
+// Coefficients: Heun; Bogacki & Shampine (1989); Cash & Karp (1990);
+// Fehlberg (1969), 5th order propagated; Dormand & Prince (1980).
+struct RKTab {
+  int ns;
+  int q;
+  double c[7];
+  double a[7][6];
+  double e[7];
+};
+
+enum { RK_DP45 = 0, RK_HEUN = 1, RK_BS23 = 2, RK_CASHKARP = 3, RK_FEHLBERG = 4, RK_COUNT = 5 };
+
+struct RK {
+  static constexpr RKTab t[RK_COUNT] = {
+      {7, 4,
+       {0.0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1.0, 1.0},
+       {{0, 0, 0, 0, 0, 0},
+        {1.0 / 5, 0, 0, 0, 0, 0},
+        {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+        {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
+        {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
+        {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
+        {35.0 / 384, 0.0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}},
+       {71.0 / 57600, 0.0, -71.0 / 16695, 71.0 / 1920, -17253.0 / 339200, 22.0 / 525,
+        -1.0 / 40}},
+      {3, 1,
+       {0.0, 1.0, 1.0, 0, 0, 0, 0},
+       {{0, 0, 0, 0, 0, 0}, {1.0, 0, 0, 0, 0, 0}, {0.5, 0.5, 0, 0, 0, 0}},
+       {-0.5, 0.5, 0, 0, 0, 0, 0}},
+      {4, 2,
+       {0.0, 1.0 / 2, 3.0 / 4, 1.0, 0, 0, 0},
+       {{0, 0, 0, 0, 0, 0},
+        {1.0 / 2, 0, 0, 0, 0, 0},
+        {0.0, 3.0 / 4, 0, 0, 0, 0},
+        {2.0 / 9, 1.0 / 3, 4.0 / 9, 0, 0, 0}},
+       {-5.0 / 72, 1.0 / 12, 1.0 / 9, -1.0 / 8, 0, 0, 0}},
+      {7, 4,
+       {0.0, 1.0 / 5, 3.0 / 10, 3.0 / 5, 1.0, 7.0 / 8, 1.0},
+       {{0, 0, 0, 0, 0, 0},
+        {1.0 / 5, 0, 0, 0, 0, 0},
+        {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+        {3.0 / 10, -9.0 / 10, 6.0 / 5, 0, 0, 0},
+        {-11.0 / 54, 5.0 / 2, -70.0 / 27, 35.0 / 27, 0, 0},
+        {1631.0 / 55296, 175.0 / 512, 575.0 / 13824, 44275.0 / 110592, 253.0 / 4096, 0},
+        {37.0 / 378, 0.0, 250.0 / 621, 125.0 / 594, 0.0, 512.0 / 1771}},
+       {-277.0 / 64512, 0.0, 6925.0 / 370944, -6925.0 / 202752, -277.0 / 14336, 277.0 / 7084,
+        0.0}},
+      {7, 4,
+       {0.0, 1.0 / 4, 3.0 / 8, 12.0 / 13, 1.0, 1.0 / 2, 1.0},
+       {{0, 0, 0, 0, 0, 0},
+        {1.0 / 4, 0, 0, 0, 0, 0},
+        {3.0 / 32, 9.0 / 32, 0, 0, 0, 0},
+        {1932.0 / 2197, -7200.0 / 2197, 7296.0 / 2197, 0, 0, 0},
+        {439.0 / 216, -8.0, 3680.0 / 513, -845.0 / 4104, 0, 0},
+        {-8.0 / 27, 2.0, -3544.0 / 2565, 1859.0 / 4104, -11.0 / 40, 0},
+        {16.0 / 135, 0.0, 6656.0 / 12825, 28561.0 / 56430, -9.0 / 50, 2.0 / 55}},
+       {1.0 / 360, 0.0, -128.0 / 4275, -2197.0 / 75240, 1.0 / 50, 2.0 / 55, 0.0}},
   };
-  // e = b(5th) - b*(4th)
-  static constexpr double e[7] = {71.0 / 57600, 0.0, -71.0 / 16695, 71.0 / 1920,
-                                  -17253.0 / 339200, 22.0 / 525, -1.0 / 40};
 };
 
 // ------------------------------------------------------- step control --
@@ -97,6 +148,8 @@ struct Table {
   T* un; T* unew; T* vn; T* vnew;
   T* ku[7]; T* kv[7];
   T* usa; T* usb; T* vsa; T* vsb;
+  int ns;    // stages per attempt of the pair in use (RKTab::ns)
+  int rk;    // index of that pair in RK::t
 };
 
 // ------------------------------------------------------------ helpers --
@@ -151,18 +204,18 @@ __device__ __forceinline__ int xcd_remap(int b, int nb_pad) {
 
 namespace mmp {
 
-// Input of RK stage s (1..7): y_n, then sa/sb alternating, then y_new.
+// Input of RK stage s (1..ns): y_n, then sa/sb alternating, then y_new.
 template <typename T>
 __device__ __forceinline__ const T* stage_in(const Table<T>* tbl, int s) {
   if (s == 1) return tbl->yn;
-  if (s == 7) return tbl->ynew;
+  if (s == tbl->ns) return tbl->ynew;
   return (s & 1) ? tbl->sb : tbl->sa;
 }
 // Buffer the stage-s kernel writes the next stage's input into.
 template <typename T>
 __device__ __forceinline__ T* stage_out(const Table<T>* tbl, int s) {
   const int n = s + 1;
-  if (n == 7) return tbl->ynew;
+  if (n == tbl->ns) return tbl->ynew;
   return (n & 1) ? tbl->sb : tbl->sa;
 }
 

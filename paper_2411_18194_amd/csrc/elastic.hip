@@ -36,25 +36,25 @@ __device__ __forceinline__ T d1(const T* __restrict__ f, long idx, int i, int n,
 template <typename T>
 __device__ __forceinline__ const T* u_in(const Table<T>* t, int s) {
   if (s == 0 || s == 1) return t->un;
-  if (s == 7) return t->unew;
+  if (s == t->ns) return t->unew;
   return (s & 1) ? t->usb : t->usa;
 }
 template <typename T>
 __device__ __forceinline__ const T* v_in(const Table<T>* t, int s) {
   if (s == 0 || s == 1) return t->vn;
-  if (s == 7) return t->vnew;
+  if (s == t->ns) return t->vnew;
   return (s & 1) ? t->vsb : t->vsa;
 }
 template <typename T>
 __device__ __forceinline__ T* u_out(const Table<T>* t, int s) {
   const int n = s + 1;
-  if (n == 7) return t->unew;
+  if (n == t->ns) return t->unew;
   return (n & 1) ? t->usb : t->usa;
 }
 template <typename T>
 __device__ __forceinline__ T* v_out(const Table<T>* t, int s) {
   const int n = s + 1;
-  if (n == 7) return t->vnew;
+  if (n == t->ns) return t->vnew;
   return (n & 1) ? t->vsb : t->vsa;
 }
 
@@ -122,7 +122,7 @@ __global__ void k_stress(ElasticArgs<T> a, int eval) {
         for (int j = 0; j < 3; ++j) s[voigt(k, j)] = T(0);
     }
     if (a.trac_amp != 0.0 && a.nx >= 2 && x == 0) {
-      const double ts = a.ctrl ? a.ctrl->t + (a.stage > 0 ? DP::c[a.stage - 1] * a.ctrl->h : 0.0)
+      const double ts = a.ctrl ? a.ctrl->t + (a.stage > 0 ? RK::t[a.tbl->rk].c[a.stage - 1] * a.ctrl->h : 0.0)
                                : 0.0;
       s[4] = (T)(a.trac_amp * sin(a.trac_omega * ts));
     }
@@ -186,7 +186,8 @@ __global__ void k_force(ElasticArgs<T> a) {
     KV[c * N + i] = kv[c];
   }
   const double h = a.ctrl->h;
-  if (stage < 7) {
+  const RKTab& rk = RK::t[a.tbl->rk];
+  if (stage < a.tbl->ns) {
     T* uo = u_out(a.tbl, stage);
     T* vo = v_out(a.tbl, stage);
     const T* un = a.tbl->un;
@@ -194,16 +195,16 @@ __global__ void k_force(ElasticArgs<T> a) {
     for (int c = 0; c < 3; ++c) {
       T au = un[c * N + i], av = vn[c * N + i];
       for (int j = 0; j < stage - 1; ++j) {
-        const T cj = (T)(DP::a[stage][j] * h);
+        const T cj = (T)(rk.a[stage][j] * h);
         au += cj * a.tbl->ku[j][c * N + i];
         av += cj * a.tbl->kv[j][c * N + i];
       }
-      const T cs = (T)(DP::a[stage][stage - 1] * h);
+      const T cs = (T)(rk.a[stage][stage - 1] * h);
       uo[c * N + i] = au + cs * ku[c];
       vo[c * N + i] = av + cs * kv[c];
     }
   } else if (a.fuse2) {
-    const T c21 = (T)(DP::a[1][0] * h);
+    const T c21 = (T)(rk.a[1][0] * h);
     for (int c = 0; c < 3; ++c) {
       a.tbl->usa[c * N + i] = u[c * N + i] + c21 * ku[c];
       a.tbl->vsa[c * N + i] = v[c * N + i] + c21 * kv[c];
@@ -216,7 +217,7 @@ __global__ void k_elastic_combine2(const Table<T>* tbl, const Ctrl* ctrl, long n
   if (ctrl_stopped(ctrl)) return;
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n3) return;
-  const T c = (T)(DP::a[1][0] * ctrl->h);
+  const T c = (T)(RK::t[tbl->rk].a[1][0] * ctrl->h);
   tbl->usa[i] = tbl->un[i] + c * tbl->ku[0][i];
   tbl->vsa[i] = tbl->vn[i] + c * tbl->kv[0][i];
 }

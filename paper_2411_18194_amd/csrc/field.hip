@@ -11,7 +11,8 @@
 // and the torque tau = LLG (Eq. 2) + Zhang-Li, then, in a Runge-Kutta
 // stage, writes k_s and immediately the next stage input
 // y_{s+1} = normalise(y_n + h sum_j a_{s+1,j} k_j) (all point-wise), or at
-// the last stage the FP64 error norm |sum_j e_j k_j| (Dormand-Prince 5(4)).
+// the last stage the FP64 error norm |sum_j e_j k_j| of the embedded pair in
+// use (Table 2).
 //
 // Boundaries: a missing neighbour is the cell itself (Neumann), except in a
 // layer with interfacial DMI, where the ghost is m -/+ d (dm/dn) with the
@@ -68,23 +69,28 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
   const T* __restrict__ m = EVAL ? a.tbl->yn : stage_in(a.tbl, stage);
 
   double h = 0.0;
+  int ns = 0;
   T ca[6] = {0, 0, 0, 0, 0, 0};
+  double ew[7] = {0, 0, 0, 0, 0, 0, 0};
   const T* kin[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   T* kout = nullptr;
   T* ynext = nullptr;
   const T* yn = nullptr;
   if (!EVAL) {
     h = a.ctrl->h;
+    ns = a.tbl->ns;
+    const RKTab& rk = RK::t[a.tbl->rk];
     kout = a.tbl->k[stage - 1];
     yn = a.tbl->yn;
     for (int j = 0; j < stage - 1; ++j) kin[j] = a.tbl->k[j];
-    if (stage < 7) {
+    if (stage < ns) {
       ynext = stage_out(a.tbl, stage);
-      for (int j = 0; j < stage; ++j) ca[j] = (T)(DP::a[stage][j] * h);
+      for (int j = 0; j < stage; ++j) ca[j] = (T)(rk.a[stage][j] * h);
     } else {
       if (fuse2) ynext = a.tbl->sa;
-      ca[0] = (T)(DP::a[1][0] * h);
-      for (int j = 0; j < 6; ++j) kin[j] = a.tbl->k[j];
+      ca[0] = (T)(rk.a[1][0] * h);
+      for (int j = 0; j < ns - 1; ++j) kin[j] = a.tbl->k[j];
+      for (int j = 0; j < ns; ++j) ew[j] = rk.e[j];
     }
   }
 
@@ -321,7 +327,7 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
           kout[base] = tau[0];
           kout[base + N] = tau[1];
           kout[base + 2 * N] = tau[2];
-          if (stage < 7) {
+          if (stage < ns) {
             T v[3];
             if constexpr (NSUB == 1) {
               // the slopes this stage needs are loaded first (uniform
@@ -357,29 +363,31 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
             ynext[base + N] = v[1] * inv;
             ynext[base + 2 * N] = v[2] * inv;
           } else if (!fuse2) {
+            // error weights: e_j of the earlier slopes (zero weights skip
+            // their loads), then e_ns of this stage's own slope
             double ev[3];
             if constexpr (NSUB == 1) {
               T kv[6][3];
 #pragma unroll
               for (int j = 0; j < 6; ++j)
-                if (DP::e[j] != 0.0)
+                if (j < ns - 1 && ew[j] != 0.0)
 #pragma unroll
                   for (int c = 0; c < 3; ++c) kv[j][c] = kin[j][base + c * N];
 #pragma unroll
               for (int c = 0; c < 3; ++c) {
-                double acc = DP::e[6] * (double)tau[c];
+                double acc = 0.0;
 #pragma unroll
                 for (int j = 0; j < 6; ++j)
-                  if (DP::e[j] != 0.0) acc += DP::e[j] * (double)kv[j][c];
-                ev[c] = acc;
+                  if (j < ns - 1 && ew[j] != 0.0) acc += ew[j] * (double)kv[j][c];
+                ev[c] = acc + ew[ns - 1] * (double)tau[c];
               }
             } else {
 #pragma unroll
               for (int c = 0; c < 3; ++c) {
-                double acc = DP::e[6] * (double)tau[c];
-                for (int j = 0; j < 6; ++j)
-                  if (DP::e[j] != 0.0) acc += DP::e[j] * (double)kin[j][base + c * N];
-                ev[c] = acc;
+                double acc = 0.0;
+                for (int j = 0; j < ns - 1; ++j)
+                  if (ew[j] != 0.0) acc += ew[j] * (double)kin[j][base + c * N];
+                ev[c] = acc + ew[ns - 1] * (double)tau[c];
               }
             }
             const double nrm = sqrt(ev[0] * ev[0] + ev[1] * ev[1] + ev[2] * ev[2]);
@@ -419,7 +427,7 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
       }
       if (threadIdx.x < kNE) a.epart[(long)w * kNE + threadIdx.x] = red[threadIdx.x][0];
     }
-  } else if (stage == 7 && !fuse2) {
+  } else if (stage == ns && !fuse2) {
     __shared__ double red[256];
     red[threadIdx.x] = emax;
     __syncthreads();
@@ -484,7 +492,7 @@ __device__ __forceinline__ void combine2_cell(const Table<T>* tbl, const Ctrl* c
                                               long i) {
   const long s = i / Ncell, cell = i - s * Ncell;
   const long base = s * 3 * Ncell + cell;
-  const T c = (T)(DP::a[1][0] * ctrl->h);
+  const T c = (T)(RK::t[tbl->rk].a[1][0] * ctrl->h);
   const T* yn = tbl->yn;
   const T* k1 = tbl->k[0];
   T v[3];
@@ -540,12 +548,14 @@ __device__ __forceinline__ void control_block(Ctrl* c, Table<T>* tbl, const doub
   if (acc) {
     T* t;
     t = tbl->yn; tbl->yn = tbl->ynew; tbl->ynew = t;
-    t = tbl->k[0]; tbl->k[0] = tbl->k[6]; tbl->k[6] = t;
+    // the last stage's slope (at y_{n+1}) is the next step's k_1
+    const int l = tbl->ns - 1;
+    t = tbl->k[0]; tbl->k[0] = tbl->k[l]; tbl->k[l] = t;
     if (elastic) {
       t = tbl->un; tbl->un = tbl->unew; tbl->unew = t;
       t = tbl->vn; tbl->vn = tbl->vnew; tbl->vnew = t;
-      t = tbl->ku[0]; tbl->ku[0] = tbl->ku[6]; tbl->ku[6] = t;
-      t = tbl->kv[0]; tbl->kv[0] = tbl->kv[6]; tbl->kv[6] = t;
+      t = tbl->ku[0]; tbl->ku[0] = tbl->ku[l]; tbl->ku[l] = t;
+      t = tbl->kv[0]; tbl->kv[0] = tbl->kv[l]; tbl->kv[l] = t;
     }
     c->steps += 1;
     if (c->fixed) {
@@ -568,7 +578,7 @@ __device__ __forceinline__ void control_block(Ctrl* c, Table<T>* tbl, const doub
   }
   if (!c->fixed) {
     double fac = 2.0;
-    if (err > 0.0) fac = 0.8 * pow(c->tol / err, 0.2);
+    if (err > 0.0) fac = 0.8 * pow(c->tol / err, 1.0 / (RK::t[tbl->rk].q + 1));
     fac = fmin(2.0, fmax(0.1, fac));
     c->dt = h * fac;
     if (c->dt < c->dt_min) {

@@ -1,6 +1,7 @@
 // Grid driver: device buffers, parameter coefficients, and the enqueueing
 // of Dormand-Prince steps whose control lives on the device.
 #include <algorithm>
+#include <cstddef>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -9,6 +10,10 @@
 #include "grid.h"
 
 namespace mmp {
+
+// the pair's stage count and index are written to the device table together
+static_assert(offsetof(Table<float>, rk) == offsetof(Table<float>, ns) + sizeof(int), "");
+static_assert(offsetof(Table<double>, rk) == offsetof(Table<double>, ns) + sizeof(int), "");
 
 // Plans chosen by the autotuner, per (nx, ny, nz, real bytes, demag on,
 // device); new grids of a tuned shape start from the tuned plan.
@@ -553,6 +558,12 @@ struct Grid final : GridBase {
     a.nby = (ny + kTileY - 1) / kTileY;
     fa = a;
     set_field_zc(field_zc > 0 ? field_zc : default_field_zc());
+    // the pair in use: its stage count and index, read by every stage kernel
+    {
+      const int v[2] = {RK::t[p.solver].ns, p.solver};
+      MMP_HIP_TRY(hipMemcpy(reinterpret_cast<char*>(dtbl.p) + offsetof(Table<T>, ns), v,
+                            sizeof(v), hipMemcpyHostToDevice));
+    }
     // elastic arguments
     ElasticArgs<T> e{};
     e.nx = nx; e.ny = ny; e.nz = nz; e.nsub = p.nsub; e.N = N;
@@ -659,9 +670,10 @@ struct Grid final : GridBase {
     if (p.elastic) launch_elastic_combine2<T>(dtbl.p, dctrl.p, N, stream, &prof);
   }
 
-  // one attempt: stages 2..7 + control (+ sampling, + next stage-2 input)
+  // one attempt: stages 2..ns + control (+ sampling, + next stage-2 input)
   void attempt(bool fixed_mode, bool sampling) {
-    for (int s = 2; s <= 7; ++s) stage(s, fixed_mode && s == 7);
+    const int ns = RK::t[p.solver].ns;
+    for (int s = 2; s <= ns; ++s) stage(s, fixed_mode && s == ns);
     launch_control<T>(dctrl.p, dtbl.p, errpart.p, nblk, p.elastic ? 1 : 0, stream, &prof);
     if (sampling)
       launch_sample<T>(dctrl.p, dtbl.p, p.nsub, N, spart.p, nsamp_blk, samp_t.p, samp_m.p,
@@ -1071,7 +1083,9 @@ struct Batch final : BatchBase {
 
   bool accepts(const GridBase* g) const override {
     const auto* t = dynamic_cast<const Grid<T>*>(g);
-    return t && t->params_set && !t->p.demag && !t->p.elastic && t->p.nsub == nsub;
+    // one stage sequence serves every member: the Dormand-Prince pair
+    return t && t->params_set && !t->p.demag && !t->p.elastic && t->p.nsub == nsub &&
+           t->p.solver == RK_DP45;
   }
   int size() const override { return (int)mem.size(); }
   int in_flight() const override { return count; }
@@ -1168,7 +1182,9 @@ struct Batch final : BatchBase {
   }
 
   void attempt() {
-    for (int s = 2; s <= 7; ++s) launch_field_multi<T>(d_args.p, d_work.p, nwork, nsub, s, 0, st);
+    constexpr int ns = RK::t[RK_DP45].ns;
+    for (int s = 2; s <= ns; ++s)
+      launch_field_multi<T>(d_args.p, d_work.p, nwork, nsub, s, 0, st);
     launch_step_multi<T>(d_step.p, (int)mem.size(), max_cells, st);
   }
 

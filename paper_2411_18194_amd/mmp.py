@@ -28,6 +28,8 @@ TERM_BITS = {"demag": T_DEMAG, "exch": T_EXCH, "afm_nn": T_AFM_NN, "afm_cell": T
 ENERGY_NAMES = ("demag", "exch", "afm_nn", "afm_cell", "dmi", "anis_u", "anis_c", "zeeman",
                 "mel", "elastic")
 PENDING = 1
+# embedded Runge-Kutta pairs (MMP_RK_*)
+SOLVERS = {"dp45": 0, "heun": 1, "bs23": 2, "cashkarp": 3, "rkf45": 4}
 
 
 class MMPError(RuntimeError):
@@ -54,7 +56,8 @@ class Params(C.Structure):
                 ("pad0", C.c_int32), ("rho", C.c_double), ("C11", C.c_double),
                 ("C12", C.c_double), ("C44", C.c_double), ("eta", C.c_double),
                 ("trac_amp", C.c_double), ("trac_freq", C.c_double), ("tol", C.c_double),
-                ("dt0", C.c_double), ("dt_min", C.c_double)]
+                ("dt0", C.c_double), ("dt_min", C.c_double), ("solver", C.c_int32),
+                ("pad1", C.c_int32)]
 
 
 class StepInfo(C.Structure):
@@ -214,6 +217,7 @@ def make_params(p: dict, precision=FP32, tol=1e-5, dt0=1e-14, dt_min=1e-20):
         P.rho = el["rho"]; P.C11 = el["C11"]; P.C12 = el["C12"]; P.C44 = el["C44"]
         P.eta = el["eta"]; P.trac_amp = el["trac_amp"]; P.trac_freq = el["trac_freq"]
     P.tol, P.dt0, P.dt_min = tol, dt0, dt_min
+    P.solver = SOLVERS[p.get("solver", "dp45")]
     return P, keep
 
 
