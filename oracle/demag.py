@@ -11,6 +11,16 @@ scipy.fft.rfftn; the product is transformed back and cropped to [0, n).
 
 ``direct_sum`` is the same convolution written as the plain double sum; the
 tests use it on tiny grids to pin the FFT path.
+
+Periodic boundaries ("DMI and boundary conditions": periodic boundaries
+also change the magnetostatic field; the paper gives no formula, so this is
+a reading, listed with the others): along an axis with R >= 1 image
+repetitions the convolution is cyclic with period n (no padding), and the
+kernel at the offset X (the nearest image, -n/2 < X <= n/2) is the sum of
+N(X + k n d) over k = -R..R.  At X = n/2 (n even) the offsets +n/2 and
+-n/2 are the same cyclic index; it holds their mean, which keeps every
+component's parity (zero for a component odd along that axis) and the
+spectrum real.  ``direct_sum_periodic`` writes this out as a double sum.
 """
 from __future__ import annotations
 
@@ -18,7 +28,7 @@ import numpy as np
 import scipy.fft as sfft
 
 from .constants import MU0
-from .tensor import PARITY, COMPONENTS, demag_tensor
+from .tensor import PARITY, COMPONENTS, demag_tensor, tensor_at
 
 
 def pad_len(n: int) -> int:
@@ -63,17 +73,62 @@ def wrapped_kernel(N6, n, P):
     return K
 
 
+def _axis_terms(i, n, P, R):
+    """(offset in cells, weight) pairs that make up kernel index i of one axis."""
+    if R == 0:
+        if P == 1:
+            return [(0, 1.0)]
+        if i < n:
+            return [(i, 1.0)]
+        if i > P - n:
+            return [(i - P, 1.0)]
+        return []
+    if 2 * i == n:
+        return [(s * (n // 2) + k * n, 0.5) for s in (1, -1) for k in range(-R, R + 1)]
+    X = i if 2 * i < n else i - n
+    return [(X + k * n, 1.0) for k in range(-R, R + 1)]
+
+
+def periodic_kernel(n, d, P, pbc):
+    """The tensor on the cyclic grid of shape P = (Px, Py, Pz), shape
+    (6, Pz, Py, Px), with image sums on the periodic axes."""
+    idx, off, wt = [], [], []
+    terms = [[_axis_terms(i, n[a], P[a], pbc[a]) for i in range(P[a])] for a in range(3)]
+    for iz in range(P[2]):
+        for iy in range(P[1]):
+            for ix in range(P[0]):
+                for oz, wz in terms[2][iz]:
+                    for oy, wy in terms[1][iy]:
+                        for ox, wx in terms[0][ix]:
+                            idx.append((iz, iy, ix))
+                            off.append((ox * d[0], oy * d[1], oz * d[2]))
+                            wt.append(wx * wy * wz)
+    K = np.zeros((6, P[2], P[1], P[0]))
+    if not idx:
+        return K
+    idx = np.array(idx)
+    off = np.array(off)
+    vals = tensor_at(off[:, 0], off[:, 1], off[:, 2], d) * np.array(wt)[None]
+    for c in range(6):
+        np.add.at(K[c], (idx[:, 0], idx[:, 1], idx[:, 2]), vals[c])
+    return K
+
+
 class Demag:
     """Precomputed tensor spectrum for one grid; call ``field(M)``."""
 
-    def __init__(self, n, d, N6=None, workers=None):
+    def __init__(self, n, d, N6=None, workers=None, pbc=(0, 0, 0)):
         self.n = tuple(n)
         self.d = tuple(d)
-        self.P = tuple(pad_len(v) for v in self.n)
-        self.N6 = demag_tensor(self.n, self.d) if N6 is None else N6
+        self.pbc = tuple(pbc)
+        self.P = tuple(v if r > 0 else pad_len(v) for v, r in zip(self.n, self.pbc))
         self.workers = workers
-        Px, Py, Pz = self.P
-        K = wrapped_kernel(self.N6, self.n, self.P)
+        if any(self.pbc):
+            self.N6 = None
+            K = periodic_kernel(self.n, self.d, self.P, self.pbc)
+        else:
+            self.N6 = demag_tensor(self.n, self.d) if N6 is None else N6
+            K = wrapped_kernel(self.N6, self.n, self.P)
         self.Kf = sfft.rfftn(K, axes=(1, 2, 3), workers=workers)
 
     def field(self, M):
@@ -112,6 +167,47 @@ def direct_sum(M, N6):
                             Nm = np.array([[nn[0], nn[3], nn[4]],
                                            [nn[3], nn[1], nn[5]],
                                            [nn[4], nn[5], nn[2]]])
+                            acc += Nm @ M[:, zj, yj, xj]
+                B[:, zi, yi, xi] = -MU0 * acc
+    return B
+
+
+def direct_sum_periodic(M, d, pbc):
+    """The periodic convolution as a plain double sum over cell pairs and
+    images (tiny grids): per axis the nearest-image offset of i - j, image
+    sums over k = -R..R, the mean of +-n/2 at the half-period offset."""
+    _, nz, ny, nx = M.shape
+    n = (nx, ny, nz)
+    B = np.zeros_like(M, dtype=np.float64)
+
+    def terms(a, delta):
+        R, L = pbc[a], n[a]
+        if R == 0:
+            return [(delta, 1.0)]
+        X = delta % L
+        if 2 * X == L:
+            return [(X + k * L, 0.5) for k in range(-R, R + 1)] + \
+                   [(X - L + k * L, 0.5) for k in range(-R, R + 1)]
+        if 2 * X > L:
+            X -= L
+        return [(X + k * L, 1.0) for k in range(-R, R + 1)]
+
+    for zi in range(nz):
+        for yi in range(ny):
+            for xi in range(nx):
+                acc = np.zeros(3)
+                for zj in range(nz):
+                    for yj in range(ny):
+                        for xj in range(nx):
+                            Nm = np.zeros((3, 3))
+                            for oz, wz in terms(2, zi - zj):
+                                for oy, wy in terms(1, yi - yj):
+                                    for ox, wx in terms(0, xi - xj):
+                                        v = tensor_at([ox * d[0]], [oy * d[1]], [oz * d[2]], d)[:, 0]
+                                        w = wx * wy * wz
+                                        Nm += w * np.array([[v[0], v[3], v[4]],
+                                                            [v[3], v[1], v[5]],
+                                                            [v[4], v[5], v[2]]])
                             acc += Nm @ M[:, zj, yj, xj]
                 B[:, zi, yi, xi] = -MU0 * acc
     return B

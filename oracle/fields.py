@@ -17,6 +17,11 @@ ghost = m + d*dm on a + face and m - d*dm on a - face.  The same ghosts feed
 the exchange and DMI stencils.  z faces stay plain Neumann (no z
 derivatives in this DMI).
 
+Periodic boundaries ("DMI and boundary conditions": open, Neumann or
+periodic): on a periodic axis the ghost of a boundary cell is the cell at
+the opposite end, for the exchange, inter-sublattice and DMI stencils alike,
+and no DMI boundary condition applies on that axis's faces.
+
 Uniaxial anisotropy: (2 Ku1/Ms)(u.m) u + (4 Ku2/Ms)(u.m)^3 u.
 Cubic anisotropy: -(2 Kc1/Ms) sum_k a_k (a_l^2 + a_n^2) c_k with
 a_k = m.c_k in the frame (c1, c2, c1 x c2).
@@ -32,14 +37,32 @@ from __future__ import annotations
 import numpy as np
 
 
-def ghosted(m, d, D=None, A=None, dmi_layer=None):
+def ghost_pad(m, periodic=(False, False, False)):
+    """One ghost cell on every side: a copy of the boundary cell, or on a
+    periodic axis the cell at the opposite end."""
+    g = np.pad(m, ((0, 0), (1, 1), (1, 1), (1, 1)), mode="edge")
+    px, py, pz = periodic
+    if px:
+        g[:, :, :, 0] = g[:, :, :, -2]
+        g[:, :, :, -1] = g[:, :, :, 1]
+    if py:
+        g[:, :, 0, :] = g[:, :, -2, :]
+        g[:, :, -1, :] = g[:, :, 1, :]
+    if pz:
+        g[:, 0, :, :] = g[:, -2, :, :]
+        g[:, -1, :, :] = g[:, 1, :, :]
+    return g
+
+
+def ghosted(m, d, D=None, A=None, dmi_layer=None, periodic=(False, False, False)):
     """Return m with one ghost cell on every side, shape (3, nz+2, ny+2, nx+2).
 
     ``D``/``A`` give the interfacial DMI boundary condition in the layer
-    ``dmi_layer`` (or every layer when ``dmi_layer`` is None and D != 0).
+    ``dmi_layer`` (or every layer when ``dmi_layer`` is None and D != 0) on
+    the faces of the axes that are not periodic.
     """
     dx, dy, dz = d
-    g = np.pad(m, ((0, 0), (1, 1), (1, 1), (1, 1)), mode="edge")
+    g = ghost_pad(m, periodic)
     if D is None or D == 0.0 or A is None or A == 0.0:
         return g
     k = -D / (2.0 * A)
@@ -47,12 +70,14 @@ def ghosted(m, d, D=None, A=None, dmi_layer=None):
     for iz in layers:
         zg = iz + 1
         # x faces: dx m = k (mz, 0, -mx)
-        for xb, xg, sgn in ((0, 0, -1.0), (m.shape[3] - 1, m.shape[3] + 1, 1.0)):
+        for xb, xg, sgn in (() if periodic[0] else
+                            ((0, 0, -1.0), (m.shape[3] - 1, m.shape[3] + 1, 1.0))):
             mb = m[:, iz, :, xb]
             dm = np.stack([k * mb[2], np.zeros_like(mb[0]), -k * mb[0]])
             g[:, zg, 1:-1, xg] = mb + sgn * dx * dm
         # y faces: dy m = k (0, mz, -my)
-        for yb, yg, sgn in ((0, 0, -1.0), (m.shape[2] - 1, m.shape[2] + 1, 1.0)):
+        for yb, yg, sgn in (() if periodic[1] else
+                            ((0, 0, -1.0), (m.shape[2] - 1, m.shape[2] + 1, 1.0))):
             mb = m[:, iz, yb, :]
             dm = np.stack([np.zeros_like(mb[0]), k * mb[2], -k * mb[1]])
             g[:, zg, yg, 1:-1] = mb + sgn * dy * dm
@@ -87,19 +112,20 @@ def dmi_layer_mask(shape_zyx, dmi_layer):
     return mask
 
 
-def exchange_field(m, Ms, A, d, D=0.0, dmi_layer=None):
-    """(2A/Ms) lap m with Neumann (or DMI) ghosts."""
+def exchange_field(m, Ms, A, d, D=0.0, dmi_layer=None, periodic=(False, False, False)):
+    """(2A/Ms) lap m with Neumann (or DMI, or periodic) ghosts."""
     if Ms == 0.0:
         return np.zeros_like(m)
-    g = ghosted(m, d, D, A, dmi_layer)
+    g = ghosted(m, d, D, A, dmi_layer, periodic)
     return (2.0 * A / Ms) * laplacian(g, d)
 
 
-def afm_nn_field(mp, Ms, A12, d):
-    """(A12/Ms) lap m' with plain Neumann ghosts (second term of Eq. 3)."""
+def afm_nn_field(mp, Ms, A12, d, periodic=(False, False, False)):
+    """(A12/Ms) lap m' with plain Neumann (or periodic) ghosts (second term of
+    Eq. 3)."""
     if Ms == 0.0:
         return np.zeros_like(mp)
-    g = ghosted(mp, d)
+    g = ghosted(mp, d, periodic=periodic)
     return (A12 / Ms) * laplacian(g, d)
 
 
@@ -110,11 +136,11 @@ def afm_cell_field(mp, Ms, A0, a):
     return (4.0 * A0 / (Ms * a * a)) * mp
 
 
-def dmi_field(m, Ms, A, D, d, dmi_layer=None):
-    """Interfacial DMI field with the natural-BC ghosts."""
+def dmi_field(m, Ms, A, D, d, dmi_layer=None, periodic=(False, False, False)):
+    """Interfacial DMI field with the natural-BC (or periodic) ghosts."""
     if Ms == 0.0 or D == 0.0:
         return np.zeros_like(m)
-    g = ghosted(m, d, D, A, dmi_layer)
+    g = ghosted(m, d, D, A, dmi_layer, periodic)
     ddx = central_dx(g, d)
     ddy = central_dy(g, d)
     B = np.stack([ddx[2], ddy[2], -ddx[0] - ddy[1]])

@@ -37,7 +37,14 @@ class Problem:
         self.V = self.d[0] * self.d[1] * self.d[2]
         if p["nsub"] == 2 and any(v != 0.0 for v in p["Dint"]):
             raise ValueError("interfacial DMI is implemented for one sublattice")
-        self.demag = Demag(self.n, self.d, N6, demag_workers) if p["demag"] else None
+        # periodic boundaries: image repetitions per axis (0 = open)
+        self.pbc = tuple(int(v) for v in p.get("pbc", (0, 0, 0)))
+        if any(v < 0 for v in self.pbc) or self.pbc[2] != 0:
+            raise ValueError("periodic boundaries are supported along x and y")
+        if any(self.pbc) and p["elastic"] is not None:
+            raise ValueError("periodic boundaries are not combined with elasticity")
+        self.periodic = tuple(v > 0 for v in self.pbc)
+        self.demag = Demag(self.n, self.d, N6, demag_workers, self.pbc) if p["demag"] else None
         self.axis = None
         if p.get("grain") is not None:
             self.axis = np.moveaxis(np.asarray(p["grain_axes"])[p["grain"]], -1, 0)
@@ -61,18 +68,18 @@ class Problem:
             return Bd.copy() if Ms != 0.0 else np.zeros_like(ms)
         if name == "exch":
             return fl.exchange_field(ms, Ms, p["A11"][s], d, p["Dint"][s],
-                                     p["dmi_layer"])
+                                     p["dmi_layer"], self.periodic)
         if name == "afm_nn":
             if other is None:
                 return np.zeros_like(ms)
-            return fl.afm_nn_field(other, Ms, p["A12"], d)
+            return fl.afm_nn_field(other, Ms, p["A12"], d, self.periodic)
         if name == "afm_cell":
             if other is None:
                 return np.zeros_like(ms)
             return fl.afm_cell_field(other, Ms, p["A0"], p["latcon"])
         if name == "dmi":
             return fl.dmi_field(ms, Ms, p["A11"][s], p["Dint"][s], d,
-                                p["dmi_layer"])
+                                p["dmi_layer"], self.periodic)
         if name == "anis_u":
             ax = self.axis if self.axis is not None else p["anis_u"][s]
             return fl.uniaxial_field(ms, Ms, p["Ku1"][s], p["Ku2"][s], ax)
@@ -164,7 +171,8 @@ class Problem:
             out[s] = tq.llg_torque(m[s], B[s], p["gamma"], p["alpha"][s])
             uu = tq.drift_velocity(p["zl_P"][s], p["j"], p["Ms"][s])
             if np.any(uu):
-                out[s] += tq.zhang_li_torque(m[s], uu, p["alpha"][s], p["zl_xi"][s], self.d)
+                out[s] += tq.zhang_li_torque(m[s], uu, p["alpha"][s], p["zl_xi"][s], self.d,
+                                             self.periodic)
         return out
 
     def rhs(self, t, y):

@@ -17,6 +17,7 @@ from __future__ import annotations
 import numpy as np
 
 from .constants import MU_B, QE
+from .fields import ghost_pad
 
 
 def cross(a, b):
@@ -38,9 +39,10 @@ def drift_velocity(P, j, Ms):
     return P * MU_B * np.asarray(j, dtype=np.float64) / (QE * Ms)
 
 
-def directional_derivative(m, u, d):
-    """(u.grad) m with clamped neighbours and 2d central differences."""
-    g = np.pad(m, ((0, 0), (1, 1), (1, 1), (1, 1)), mode="edge")
+def directional_derivative(m, u, d, periodic=(False, False, False)):
+    """(u.grad) m with clamped (or, on periodic axes, wrapped) neighbours and
+    2d central differences."""
+    g = ghost_pad(m, periodic)
     out = np.zeros_like(m)
     if u[0] != 0.0:
         out += u[0] * (g[:, 1:-1, 1:-1, 2:] - g[:, 1:-1, 1:-1, :-2]) / (2.0 * d[0])
@@ -51,10 +53,10 @@ def directional_derivative(m, u, d):
     return out
 
 
-def zhang_li_torque(m, u, alpha, xi, d):
+def zhang_li_torque(m, u, alpha, xi, d, periodic=(False, False, False)):
     if not np.any(u):
         return np.zeros_like(m)
-    dm = directional_derivative(m, u, d)
+    dm = directional_derivative(m, u, d, periodic)
     mxdm = cross(m, dm)
     return -1.0 / (1.0 + alpha * alpha) * (
         (1.0 + xi * alpha) * cross(m, mxdm) + (xi - alpha) * mxdm)

@@ -80,6 +80,7 @@ def base_params(n, cell, nsub=1):
         "grain_axes": None,
         "elastic": None,
         "solver": "dp45",
+        "pbc": (0, 0, 0),
     }
 
 
