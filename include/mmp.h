@@ -126,7 +126,17 @@ typedef struct {
   double dt0;             /* first adaptive step, s (default 1e-14)        */
   double dt_min;          /* underflow limit, s (default 1e-20)            */
   int32_t solver;         /* MMP_RK_*: embedded Runge-Kutta pair           */
-  int32_t pad1;
+  int32_t pbc[3];         /* periodic boundaries: image repetitions R per
+                             axis, 0 = open.  R > 0 along x or y makes that
+                             axis periodic for the exchange, DMI and
+                             Zhang-Li stencils (neighbours wrap, no DMI
+                             boundary condition on its faces) and for the
+                             demag field (cyclic convolution of period n,
+                             kernel summed over the images k = -R..R, the
+                             half-period offset holding the mean of +-n/2).
+                             A periodic axis with demag needs n = 1 or n
+                             even and 7-smooth, <= 4096; pbc[2] must be 0;
+                             not combined with elasticity; R <= 1024       */
 } mmp_params;
 
 typedef struct {

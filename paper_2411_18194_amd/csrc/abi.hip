@@ -136,6 +136,14 @@ mmp_status mmp_set_params(mmp_grid g, const mmp_params* p) {
   if (p->precision != MMP_FP32 && p->precision != MMP_FP64) { set_error("bad precision"); return MMP_E_ARG; }
   if (p->nsub != 1 && p->nsub != 2) { set_error("nsub must be 1 or 2"); return MMP_E_ARG; }
   if (p->solver < 0 || p->solver >= RK_COUNT) { set_error("unknown solver"); return MMP_E_ARG; }
+  if (p->pbc[0] < 0 || p->pbc[1] < 0 || p->pbc[0] > 1024 || p->pbc[1] > 1024 || p->pbc[2] != 0) {
+    set_error("pbc: repetitions 0..1024 along x and y, 0 along z");
+    return MMP_E_ARG;
+  }
+  if ((p->pbc[0] || p->pbc[1]) && p->elastic) {
+    set_error("periodic boundaries are not combined with elasticity");
+    return MMP_E_ARG;
+  }
   if (p->ngrains < 0 || p->ngrains > 65536 || (p->ngrains > 0 && (!p->grain || !p->grain_axes))) {
     set_error("bad grain description");
     return MMP_E_ARG;

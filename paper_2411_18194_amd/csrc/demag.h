@@ -30,12 +30,17 @@ struct DemagPlan {
   int nk = 0;                       // 2-D fused y pass: kx columns per block
   int tk = 0;                       // mixed-radix z pass: ky columns per block
   int zq = 1, zw = 1, zt = 0;       // register z pass: lanes per column, waves hint, threads
+  // image repetitions per axis; > 0 makes the axis periodic (x and y only):
+  // P = n, no zero padding, the kernel summed over the images
+  int rep[3] = {0, 0, 0};
   size_t s1_elems = 0, s2_elems = 0, k_elems = 0;
 };
 
 // Plan with the default launch shapes for the given pads (nullptr: the
-// smallest even 7-smooth pads).  Returns 0, or -1 for an unsupported pad.
-int demag_plan(int nx, int ny, int nz, int real_bytes, const int* pads, DemagPlan* p);
+// smallest even 7-smooth pads, n on a periodic axis) and image repetitions
+// rep (nullptr: open boundaries).  Returns 0, or -1 for an unsupported pad.
+int demag_plan(int nx, int ny, int nz, int real_bytes, const int* pads, DemagPlan* p,
+               const int* rep = nullptr);
 // 0 if every launch shape of p is within the kernels' limits.
 int demag_plan_check(const DemagPlan& p, int real_bytes);
 

@@ -311,9 +311,12 @@ static int threads_for(long elems) {
 // complex elements one block may hold in LDS (64 KiB)
 static long lds_cap(int real_bytes) { return 65536 / (2 * real_bytes); }
 
-static bool pad_ok(int n, int P) {
+// An open axis is zero-padded to P >= 2n - 1; a periodic one is cyclic
+// with P = n.  P is 1 or even and 7-smooth, at most 4096.
+static bool pad_ok(int n, int P, bool periodic = false) {
   if (n == 1) return P == 1;
-  if (P < 2 * n - 1 || (P & 1) || P > 4096) return false;
+  if (periodic ? P != n : P < 2 * n - 1) return false;
+  if ((P & 1) || P > 4096) return false;
   int r[16];
   const int nr = fft_radices(P, r);
   return nr >= 0 && nr <= 15;
@@ -358,15 +361,22 @@ int demag_plan_check(const DemagPlan& p, int real_bytes) {
   return 0;
 }
 
-int demag_plan(int nx, int ny, int nz, int real_bytes, const int* pads, DemagPlan* p) {
+int demag_plan(int nx, int ny, int nz, int real_bytes, const int* pads, DemagPlan* p,
+               const int* rep) {
   DemagPlan d;
   d.nx = nx; d.ny = ny; d.nz = nz;
+  if (rep)
+    for (int a = 0; a < 3; ++a) d.rep[a] = rep[a];
+  if (d.rep[2] != 0) return -1;
+  const bool px = d.rep[0] > 0, py = d.rep[1] > 0;
   if (pads) {
-    if (!pad_ok(nx, pads[0]) || !pad_ok(ny, pads[1]) || !pad_ok(nz, pads[2])) return -1;
+    if (!pad_ok(nx, pads[0], px) || !pad_ok(ny, pads[1], py) || !pad_ok(nz, pads[2])) return -1;
     d.Px = pads[0]; d.Py = pads[1]; d.Pz = pads[2];
   } else {
-    d.Px = smooth_pad(nx); d.Py = smooth_pad(ny); d.Pz = smooth_pad(nz);
-    if (!pad_ok(nx, d.Px) || !pad_ok(ny, d.Py) || !pad_ok(nz, d.Pz)) return -1;
+    d.Px = px ? nx : smooth_pad(nx);
+    d.Py = py ? ny : smooth_pad(ny);
+    d.Pz = smooth_pad(nz);
+    if (!pad_ok(nx, d.Px, px) || !pad_ok(ny, d.Py, py) || !pad_ok(nz, d.Pz)) return -1;
   }
   d.Hx = d.Px / 2 + 1; d.Hy = d.Py / 2 + 1; d.Hz = d.Pz / 2 + 1;
   int rr[3][16];
@@ -451,7 +461,7 @@ void demag_pass(int pass, const DemagPlan& p, const DemagBufs<T>& b, const Table
         a.nx = p.nx; a.ny = p.ny; a.nz = p.nz; a.Hx = p.Hx; a.ldy = p.ldy; a.ty = ty;
         a.lnl = 0;
         while ((2 << a.lnl) < ty) ++a.lnl;
-        launch_x4<T>(p.Px, inv, g, x_threads(p, ty), lds, st, a);
+        launch_x4<T>(p.Px, inv, p.rep[0] > 0, g, x_threads(p, ty), lds, st, a);
       } else {
         XArgs<T> a;
         a.tbl = tbl; a.ctrl = ctrl; a.stage = stage; a.ms0 = ms0; a.ms1 = ms1; a.nsub = nsub;
@@ -472,7 +482,7 @@ void demag_pass(int pass, const DemagPlan& p, const DemagBufs<T>& b, const Table
         M4Args<T> a;
         a.ctrl = ctrl; a.S1 = b.S1; a.K = b.K; a.tw4 = b.tw4y;
         a.ny = p.ny; a.Hx = p.Hx; a.Hy = p.Hy; a.ldy = p.ldy; a.nk = p.nk;
-        launch_m4<T>(p.Py, g, m2_threads(p), lds, st, a);
+        launch_m4<T>(p.Py, p.rep[1] > 0, g, m2_threads(p), lds, st, a);
       } else {
         M2Args<T> a;
         a.ctrl = ctrl; a.S1 = b.S1; a.K = b.K; a.tw = b.twy;
@@ -498,7 +508,7 @@ void demag_pass(int pass, const DemagPlan& p, const DemagBufs<T>& b, const Table
         a.ctrl = ctrl; a.in = in; a.out = out; a.tw4 = b.tw4y;
         a.nlines = nlines; a.nvalid_in = nvi; a.ld_in = ldi; a.nvalid_out = nvo; a.ld_out = ldo;
         a.nl = nl;
-        launch_y4<T>(p.Py, inv, g, y_threads(p, nl), lds, st, a);
+        launch_y4<T>(p.Py, inv, p.rep[1] > 0, g, y_threads(p, nl), lds, st, a);
       } else {
         YArgs<T> a;
         a.ctrl = ctrl; a.in = in; a.out = out; a.tw = b.twy;

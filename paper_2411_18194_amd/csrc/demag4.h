@@ -63,12 +63,17 @@ constexpr bool zreg_waves_ok(int real_bytes, int pz, int zq, int zw) {
          (zw == 1 || ((zw == 2 || zw == 4) && zreg_data_vgprs(real_bytes, pz, zq) * zw <= 384));
 }
 
+// full: the forward transform's input fills its whole length (a periodic
+// axis); otherwise the upper half of a forward line is zero padding.
 template <typename T>
-void launch_y4(int L, bool inv, dim3 g, int thr, size_t lds, hipStream_t st, const Y4Args<T>& a);
+void launch_y4(int L, bool inv, bool full, dim3 g, int thr, size_t lds, hipStream_t st,
+               const Y4Args<T>& a);
 template <typename T>
-void launch_x4(int L, bool inv, dim3 g, int thr, size_t lds, hipStream_t st, const X4Args<T>& a);
+void launch_x4(int L, bool inv, bool full, dim3 g, int thr, size_t lds, hipStream_t st,
+               const X4Args<T>& a);
 template <typename T>
-void launch_m4(int L, dim3 g, int thr, size_t lds, hipStream_t st, const M4Args<T>& a);
+void launch_m4(int L, bool full, dim3 g, int thr, size_t lds, hipStream_t st,
+               const M4Args<T>& a);
 template <typename T>
 void launch_z4(int PZ, int q, int w, dim3 g, int thr, hipStream_t st, const Z4Args<T>& a);
 

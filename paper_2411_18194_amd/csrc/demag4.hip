@@ -94,7 +94,9 @@ __device__ __forceinline__ void load2(const cpx<T>* i, cpx<T>& a, cpx<T>& b) {
 }
 
 // ------------------------------------------------------------ y lines --
-template <typename T, int L1, int L2, bool INV>
+// FULL: the input line fills the whole transform length (a periodic axis);
+// otherwise a forward line is zero-padded to at least twice its data.
+template <typename T, int L1, int L2, bool INV, bool FULL>
 __global__ __launch_bounds__(256) void k4_ffty(Y4Args<T> a) {
   using V = cpx<T>;
   if (ctrl_stopped(a.ctrl)) return;
@@ -109,7 +111,8 @@ __global__ __launch_bounds__(256) void k4_ffty(Y4Args<T> a) {
   // afterwards, so they all go out before the first wait
   const V* in = a.in + (long)(valid ? gl : 0) * a.ld_in;
   V v[L1];
-  constexpr int NLOAD = (!INV && L1 >= 2) ? L1 / 2 : L1;
+  constexpr bool HZ = !INV && !FULL;
+  constexpr int NLOAD = (HZ && L1 >= 2) ? L1 / 2 : L1;
 #pragma unroll
   for (int n1 = 0; n1 < NLOAD; ++n1) {
     const int idx = L2 * n1 + t;
@@ -118,7 +121,7 @@ __global__ __launch_bounds__(256) void k4_ffty(Y4Args<T> a) {
 #pragma unroll
   for (int n1 = 0; n1 < NLOAD; ++n1)
     if (!valid || L2 * n1 + t >= a.nvalid_in) v[n1] = cmk<T>(0, 0);
-  fs_step1<T, L1, L2, INV, !INV>(v, line, a.tw4, t);
+  fs_step1<T, L1, L2, INV, HZ>(v, line, a.tw4, t);
   __syncthreads();
   V u[L1 / L2][L2];
   fs_step3<T, L1, L2, INV>(u, line, t);
@@ -135,7 +138,7 @@ __global__ __launch_bounds__(256) void k4_ffty(Y4Args<T> a) {
 }
 
 // ------------------------------------------------------------- x rows --
-template <typename T, int L1, int L2>
+template <typename T, int L1, int L2, bool FULL>
 __global__ __launch_bounds__(256) void k4_fftx_fwd(X4Args<T> a) {
   using V = cpx<T>;
   if (ctrl_stopped(a.ctrl)) return;
@@ -153,7 +156,7 @@ __global__ __launch_bounds__(256) void k4_fftx_fwd(X4Args<T> a) {
   const int ya = y0 + 2 * q, yb = ya + 1;
   V* line = lds + q * L;
   V v[L1];
-  constexpr int NLOAD = L1 >= 2 ? L1 / 2 : L1;
+  constexpr int NLOAD = (!FULL && L1 >= 2) ? L1 / 2 : L1;
   // rows ya, yb (clamped to row 0 past ny, column 0 past nx): every load is
   // unconditional so they all go out before the first wait
   const long ra = (long)(ya < a.ny ? ya : 0) * a.nx, rb = (long)(yb < a.ny ? yb : 0) * a.nx;
@@ -179,7 +182,7 @@ __global__ __launch_bounds__(256) void k4_fftx_fwd(X4Args<T> a) {
     const bool inx = L2 * n1 + t < a.nx;
     v[n1] = cmk<T>(inx && ya < a.ny ? xa[n1] : T(0), inx && yb < a.ny ? xb[n1] : T(0));
   }
-  fs_step1<T, L1, L2, false, true>(v, line, a.tw4, t);
+  fs_step1<T, L1, L2, false, !FULL>(v, line, a.tw4, t);
   __syncthreads();
   V u[L1 / L2][L2];
   fs_step3<T, L1, L2, false>(u, line, t);
@@ -263,7 +266,7 @@ __global__ __launch_bounds__(256) void k4_fftx_inv(X4Args<T> a) {
 }
 
 // ---------------------------------------------- 2-D fused y + multiply --
-template <typename T, int L1, int L2>
+template <typename T, int L1, int L2, bool FULL>
 __global__ __launch_bounds__(256) void k4_ffty_mul2d(M4Args<T> a) {
   using V = cpx<T>;
   if (ctrl_stopped(a.ctrl)) return;
@@ -277,13 +280,13 @@ __global__ __launch_bounds__(256) void k4_ffty_mul2d(M4Args<T> a) {
   V* line = lds + ln * L;
   V* io = a.S1 + ((long)c * a.Hx + kx) * a.ldy;
   V v[L1];
-  constexpr int NLOAD = L1 >= 2 ? L1 / 2 : L1;
+  constexpr int NLOAD = (!FULL && L1 >= 2) ? L1 / 2 : L1;
 #pragma unroll
   for (int n1 = 0; n1 < NLOAD; ++n1) {
     const int y = L2 * n1 + t;
     v[n1] = (valid && y < a.ny) ? io[y] : cmk<T>(0, 0);
   }
-  fs_step1<T, L1, L2, false, true>(v, line, a.tw4, t);
+  fs_step1<T, L1, L2, false, !FULL>(v, line, a.tw4, t);
   __syncthreads();
   V u[L1 / L2][L2];
   fs_step3<T, L1, L2, false>(u, line, t);
@@ -534,49 +537,55 @@ __global__ __launch_bounds__(256) void k4_fftz_mul(Z4Args<T> a) {
   X(1) X(2) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
 
 template <typename T, int L>
-static void ly(bool inv, dim3 g, int thr, size_t lds, hipStream_t st, const Y4Args<T>& a) {
+static void ly(bool inv, bool full, dim3 g, int thr, size_t lds, hipStream_t st,
+               const Y4Args<T>& a) {
   constexpr int L1 = Split<L>::L1, L2 = Split<L>::L2;
-  if (inv) hipLaunchKernelGGL((k4_ffty<T, L1, L2, true>), g, dim3(thr), lds, st, a);
-  else hipLaunchKernelGGL((k4_ffty<T, L1, L2, false>), g, dim3(thr), lds, st, a);
+  if (inv) hipLaunchKernelGGL((k4_ffty<T, L1, L2, true, false>), g, dim3(thr), lds, st, a);
+  else if (full) hipLaunchKernelGGL((k4_ffty<T, L1, L2, false, true>), g, dim3(thr), lds, st, a);
+  else hipLaunchKernelGGL((k4_ffty<T, L1, L2, false, false>), g, dim3(thr), lds, st, a);
 }
 
 template <typename T>
-void launch_y4(int L, bool inv, dim3 g, int thr, size_t lds, hipStream_t st,
+void launch_y4(int L, bool inv, bool full, dim3 g, int thr, size_t lds, hipStream_t st,
                const Y4Args<T>& a) {
   switch (L) {
-#define X(n) case n: ly<T, n>(inv, g, thr, lds, st, a); break;
+#define X(n) case n: ly<T, n>(inv, full, g, thr, lds, st, a); break;
     MMP_L_CASES(X)
 #undef X
   }
 }
 
 template <typename T, int L>
-static void lx(bool inv, dim3 g, int thr, size_t lds, hipStream_t st, const X4Args<T>& a) {
+static void lx(bool inv, bool full, dim3 g, int thr, size_t lds, hipStream_t st,
+               const X4Args<T>& a) {
   constexpr int L1 = Split<L>::L1, L2 = Split<L>::L2;
   if (inv) hipLaunchKernelGGL((k4_fftx_inv<T, L1, L2>), g, dim3(thr), lds, st, a);
-  else hipLaunchKernelGGL((k4_fftx_fwd<T, L1, L2>), g, dim3(thr), lds, st, a);
+  else if (full) hipLaunchKernelGGL((k4_fftx_fwd<T, L1, L2, true>), g, dim3(thr), lds, st, a);
+  else hipLaunchKernelGGL((k4_fftx_fwd<T, L1, L2, false>), g, dim3(thr), lds, st, a);
 }
 
 template <typename T>
-void launch_x4(int L, bool inv, dim3 g, int thr, size_t lds, hipStream_t st,
+void launch_x4(int L, bool inv, bool full, dim3 g, int thr, size_t lds, hipStream_t st,
                const X4Args<T>& a) {
   switch (L) {
-#define X(n) case n: lx<T, n>(inv, g, thr, lds, st, a); break;
+#define X(n) case n: lx<T, n>(inv, full, g, thr, lds, st, a); break;
     MMP_L_CASES(X)
 #undef X
   }
 }
 
 template <typename T, int L>
-static void lm(dim3 g, int thr, size_t lds, hipStream_t st, const M4Args<T>& a) {
+static void lm(bool full, dim3 g, int thr, size_t lds, hipStream_t st, const M4Args<T>& a) {
   constexpr int L1 = Split<L>::L1, L2 = Split<L>::L2;
-  hipLaunchKernelGGL((k4_ffty_mul2d<T, L1, L2>), g, dim3(thr), lds, st, a);
+  if (full) hipLaunchKernelGGL((k4_ffty_mul2d<T, L1, L2, true>), g, dim3(thr), lds, st, a);
+  else hipLaunchKernelGGL((k4_ffty_mul2d<T, L1, L2, false>), g, dim3(thr), lds, st, a);
 }
 
 template <typename T>
-void launch_m4(int L, dim3 g, int thr, size_t lds, hipStream_t st, const M4Args<T>& a) {
+void launch_m4(int L, bool full, dim3 g, int thr, size_t lds, hipStream_t st,
+               const M4Args<T>& a) {
   switch (L) {
-#define X(n) case n: lm<T, n>(g, thr, lds, st, a); break;
+#define X(n) case n: lm<T, n>(full, g, thr, lds, st, a); break;
     MMP_L_CASES(X)
 #undef X
   }
@@ -619,9 +628,11 @@ void launch_z4(int PZ, int q, int w, dim3 g, int thr, hipStream_t st, const Z4Ar
 }
 
 #define INST(T)                                                                              \
-  template void launch_y4<T>(int, bool, dim3, int, size_t, hipStream_t, const Y4Args<T>&);  \
-  template void launch_x4<T>(int, bool, dim3, int, size_t, hipStream_t, const X4Args<T>&);  \
-  template void launch_m4<T>(int, dim3, int, size_t, hipStream_t, const M4Args<T>&);        \
+  template void launch_y4<T>(int, bool, bool, dim3, int, size_t, hipStream_t,              \
+                             const Y4Args<T>&);                                             \
+  template void launch_x4<T>(int, bool, bool, dim3, int, size_t, hipStream_t,              \
+                             const X4Args<T>&);                                             \
+  template void launch_m4<T>(int, bool, dim3, int, size_t, hipStream_t, const M4Args<T>&);  \
   template void launch_z4<T>(int, int, int, dim3, int, hipStream_t, const Z4Args<T>&);
 INST(float)
 INST(double)

@@ -33,6 +33,7 @@ struct FieldArgs {
   T bext[3];
   int dmi_layer;
   int has_demag, has_dmi, has_anis_u, has_anis_c, has_mel;
+  int per_x, per_y;           // periodic axes: neighbours wrap, no DMI boundary
   const uint16_t* grain;
   const T* gaxes;
   const T* Bd;

@@ -17,7 +17,9 @@
 // Boundaries: a missing neighbour is the cell itself (Neumann), except in a
 // layer with interfacial DMI, where the ghost is m -/+ d (dm/dn) with the
 // natural boundary condition 2A dn m = -D (z x n) x m (Eq. 5 for one
-// sublattice).  Zhang-Li uses clamped central differences.
+// sublattice).  Zhang-Li uses clamped central differences.  Along a
+// periodic axis (x or y) the neighbour of a boundary cell is the cell at the
+// opposite end, for every stencil, and no boundary condition applies.
 #include "field.h"
 
 namespace mmp {
@@ -106,8 +108,11 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
     // A missing neighbour is the cell itself, so every neighbour load is an
     // unconditional load from a clamped offset: no branches between the
     // loads, which then all go out before the first wait.
-    const long dxm = x > 0 ? -1 : 0, dxp = x + 1 < a.nx ? 1 : 0;
-    const long dym = y > 0 ? -(long)a.nx : 0, dyp = y + 1 < a.ny ? (long)a.nx : 0;
+    // (on a periodic axis the cell at the opposite end)
+    const long dxm = x > 0 ? -1 : (a.per_x ? a.nx - 1 : 0);
+    const long dxp = x + 1 < a.nx ? 1 : (a.per_x ? 1 - a.nx : 0);
+    const long dym = y > 0 ? -(long)a.nx : (a.per_y ? (long)(a.ny - 1) * a.nx : 0);
+    const long dyp = y + 1 < a.ny ? (long)a.nx : (a.per_y ? -(long)(a.ny - 1) * a.nx : 0);
     const long dz0 = z0 > 0 ? -plane : 0;
 #pragma unroll
     for (int s = 0; s < NSUB; ++s)
@@ -165,17 +170,18 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
           gxm[c] = xm[s][c]; gxp[c] = xp[s][c]; gym[c] = ym[s][c]; gyp[c] = yp[s][c];
         }
         if (dmil) {
+          // boundary condition of Eq. 5 on the faces of the open axes
           const T k = C.kdmi;
-          if (x == 0) {
+          if (x == 0 && !a.per_x) {
             gxm[0] = mm[0] - a.dx * k * mm[2]; gxm[1] = mm[1]; gxm[2] = mm[2] + a.dx * k * mm[0];
           }
-          if (x + 1 == a.nx) {
+          if (x + 1 == a.nx && !a.per_x) {
             gxp[0] = mm[0] + a.dx * k * mm[2]; gxp[1] = mm[1]; gxp[2] = mm[2] - a.dx * k * mm[0];
           }
-          if (y == 0) {
+          if (y == 0 && !a.per_y) {
             gym[0] = mm[0]; gym[1] = mm[1] - a.dy * k * mm[2]; gym[2] = mm[2] + a.dy * k * mm[1];
           }
-          if (y + 1 == a.ny) {
+          if (y + 1 == a.ny && !a.per_y) {
             gyp[0] = mm[0]; gyp[1] = mm[1] + a.dy * k * mm[2]; gyp[2] = mm[2] - a.dy * k * mm[1];
           }
         }

@@ -17,7 +17,7 @@ static_assert(offsetof(Table<double>, rk) == offsetof(Table<double>, ns) + sizeo
 
 // Plans chosen by the autotuner, per (nx, ny, nz, real bytes, demag on,
 // device); new grids of a tuned shape start from the tuned plan.
-using PlanKey = std::tuple<int, int, int, int, int, int>;
+using PlanKey = std::tuple<int, int, int, int, int, int, int, int>;
 struct TunedPlan {
   DemagPlan demag;
   double demag_ms;
@@ -68,7 +68,7 @@ struct Grid final : GridBase {
   bool demag_built = false;
   // layout of the current allocation
   bool allocated = false;
-  int a_nsub = 0, a_elastic = 0, a_demag = 0;
+  int a_nsub = 0, a_elastic = 0, a_demag = 0, a_pbc[2] = {0, 0};
   bool k1_valid = false;
   double t_host = 0.0, dt_host = 0.0;
   FieldArgs<T> fa{};
@@ -152,8 +152,10 @@ struct Grid final : GridBase {
       }
     }
     if (p.demag) {
-      if (!cached && demag_plan(nx, ny, nz, (int)sizeof(T), nullptr, &np) != 0) {
-        set_error("demag pad exceeds 4096 along an axis");
+      if (!cached && demag_plan(nx, ny, nz, (int)sizeof(T), nullptr, &np, p.pbc) != 0) {
+        set_error("unsupported demag pads: each open axis pads to at most 4096, a periodic "
+                  "axis needs n = 1 or n even and 7-smooth");
+        free_all();
         return MMP_E_ARG;
       }
       rc |= Bd.alloc(3 * (size_t)N);
@@ -186,6 +188,7 @@ struct Grid final : GridBase {
     MMP_HIP_TRY(hipStreamSynchronize(stream));
     allocated = true;
     a_nsub = p.nsub; a_elastic = p.elastic; a_demag = p.demag;
+    a_pbc[0] = p.pbc[0]; a_pbc[1] = p.pbc[1];
     state_set = false;
     return 0;
   }
@@ -287,7 +290,8 @@ struct Grid final : GridBase {
   int field_zc = 0;  // z planes per field-kernel thread (0: not chosen yet)
 
   PlanKey plan_key() const {
-    return PlanKey(nx, ny, nz, (int)sizeof(T), p.demag ? 1 : 0, current_device());
+    return PlanKey(nx, ny, nz, (int)sizeof(T), p.demag ? 1 : 0, current_device(), p.pbc[0],
+                   p.pbc[1]);
   }
 
   // enough waves to cover the chip a few times over, but marches of at
@@ -343,7 +347,7 @@ struct Grid final : GridBase {
     }
     if (p.demag) {
       DemagPlan np;
-      if (demag_plan(nx, ny, nz, (int)sizeof(T), in->pad, &np) != 0) {
+      if (demag_plan(nx, ny, nz, (int)sizeof(T), in->pad, &np, p.pbc) != 0) {
         set_error("unsupported pads: each must be 1 for a single cell, else even, 7-smooth, "
                   ">= 2n-1 and <= 4096");
         return MMP_E_ARG;
@@ -442,7 +446,11 @@ struct Grid final : GridBase {
       return k;
     };
     int cx[2], cy[2], cz[2];
-    const int nxc = pads_for(nx, cx), nyc = pads_for(ny, cy), nzc = pads_for(nz, cz);
+    int nxc = pads_for(nx, cx), nyc = pads_for(ny, cy);
+    const int nzc = pads_for(nz, cz);
+    // a periodic axis has the one cyclic length n
+    if (p.pbc[0] > 0) { cx[0] = nx; nxc = 1; }
+    if (p.pbc[1] > 0) { cy[0] = ny; nyc = 1; }
     const T ms0 = (T)p.sub[0].Ms, ms1 = (T)(p.nsub == 2 ? p.sub[1].Ms : 0.0);
     MMP_HIP_TRY(hipStreamSynchronize(stream));
     DemagPlan best{};
@@ -452,7 +460,7 @@ struct Grid final : GridBase {
         for (int k = 0; k < nzc; ++k) {
           const int pads[3] = {cx[i], cy[j], cz[k]};
           DemagPlan c;
-          if (demag_plan(nx, ny, nz, (int)sizeof(T), pads, &c) != 0) continue;
+          if (demag_plan(nx, ny, nz, (int)sizeof(T), pads, &c, p.pbc) != 0) continue;
           const bool cur = c.Px == plan.Px && c.Py == plan.Py && c.Pz == plan.Pz;
           DemagBufs<T> tb = db;
           Buf<cpx<T>> s1, s2, twb;
@@ -503,7 +511,7 @@ struct Grid final : GridBase {
           return MMP_E_ARG;
         }
     if (!allocated || a_nsub != p.nsub || a_elastic != (p.elastic != 0) ||
-        a_demag != (p.demag != 0)) {
+        a_demag != (p.demag != 0) || a_pbc[0] != p.pbc[0] || a_pbc[1] != p.pbc[1]) {
       p.elastic = p.elastic != 0;
       p.demag = p.demag != 0;
       const int rc = alloc_layout();
@@ -556,6 +564,8 @@ struct Grid final : GridBase {
     a.V = d[0] * d[1] * d[2];
     a.nbx = (nx + kTileX - 1) / kTileX;
     a.nby = (ny + kTileY - 1) / kTileY;
+    a.per_x = p.pbc[0] > 0 ? 1 : 0;
+    a.per_y = p.pbc[1] > 0 ? 1 : 0;
     fa = a;
     set_field_zc(field_zc > 0 ? field_zc : default_field_zc());
     // the pair in use: its stage count and index, read by every stage kernel

@@ -48,7 +48,7 @@ int64_t estimate_bytes(const mmp_request& r, int precision) {
   int64_t b = (4 + 7) * (int64_t)ns * 3 * N * rb;  // state, stages, k
   if (r.params.demag) {
     DemagPlan p;
-    if (demag_plan(r.nx, r.ny, r.nz, (int)rb, nullptr, &p) == 0)
+    if (demag_plan(r.nx, r.ny, r.nz, (int)rb, nullptr, &p, r.params.pbc) == 0)
       b += (int64_t)(p.s1_elems + p.s2_elems) * 2 * rb + (int64_t)p.k_elems * rb + 3 * N * rb +
            6 * N * 8 /* FP64 tensor during the build */ +
            (int64_t)6 * r.nz * (r.ny + p.Hy) * p.Hx * 8;

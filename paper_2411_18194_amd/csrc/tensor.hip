@@ -15,6 +15,10 @@
 //                derivatives of 1/R from the Cartesian recurrence
 //                n R^2 a_k = (2n-1) sum_i x_i a_{k-e_i} - (n-1) sum_i a_{k-2e_i},
 //                a_k = (-1)^|k|/k! d^k (1/R).
+// Along a periodic axis (x or y) the kernel is cyclic with the grid's period
+// and holds, at each cyclic offset, the sum over the images k = -R..R (the
+// mean of +n/2 and -n/2 at the half period); the transform then runs over
+// the cyclic offsets only.
 // Each component has a definite parity per axis, so its DFT on the padded
 // grid is a product of cosine/sine sums evaluated here directly in FP64
 // (exact integer phase indexes into FP64 trig tables), then scaled by
@@ -88,6 +92,7 @@ struct TensorArgs {
   int bx, by, bz;      // box of offsets this launch covers
   int nq;              // quadrature points per axis (2n)
   double qt[24], qw[24];
+  int rx, ry;          // image repetitions along x and y (0: open axis)
 };
 
 __global__ void k_tensor_near(TensorArgs a) {
@@ -154,15 +159,9 @@ __device__ __forceinline__ int aidx(int p, int q, int r) {
   return n * (n + 1) * (n + 2) / 6 + p * (2 * n + 3 - p) / 2 + q;
 }
 
-__global__ void k_tensor_far(TensorArgs a) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long N = (long)a.nx * a.ny * a.nz;
-  if (i >= N) return;
-  const int X = (int)(i % a.nx), Y = (int)((i / a.nx) % a.ny), Z = (int)(i / ((long)a.nx * a.ny));
-  const double x = X * a.dx, y = Y * a.dy, z = Z * a.dz;
+// 4th-moment expansion at offset (x, y, z), |R| >= 40 max(d)
+__device__ void tensor_far_at(double x, double y, double z, const TensorArgs& a, double* o6) {
   const double R2 = x * x + y * y + z * z;
-  const double r = sqrt(R2) / a.dmax;
-  if (r < kRFar) return;
   // a_k = (-1)^|k|/k! d^k (1/R) for |k| <= 6
   double A[84];
   A[aidx(0, 0, 0)] = 1.0 / sqrt(R2);
@@ -186,7 +185,6 @@ __global__ void k_tensor_far(TensorArgs a) {
   const int comp_i[6] = {0, 1, 2, 0, 0, 1};
   const int comp_j[6] = {0, 1, 2, 1, 2, 2};
   const double pref = -(a.dx * a.dy * a.dz) / (4.0 * kPi);
-  const long o = i;
   for (int c = 0; c < 6; ++c) {
     int base[3] = {0, 0, 0};
     base[comp_i[c]]++;
@@ -205,8 +203,81 @@ __global__ void k_tensor_far(TensorArgs a) {
     acc += d[0] * d[0] * d[1] * d[1] / 144.0 * D(2, 2, 0) +
            d[0] * d[0] * d[2] * d[2] / 144.0 * D(2, 0, 2) +
            d[1] * d[1] * d[2] * d[2] / 144.0 * D(0, 2, 2);
-    a.n6[c * N + o] = pref * acc;
+    o6[c] = pref * acc;
   }
+}
+
+__global__ void k_tensor_far(TensorArgs a) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long N = (long)a.nx * a.ny * a.nz;
+  if (i >= N) return;
+  const int X = (int)(i % a.nx), Y = (int)((i / a.nx) % a.ny), Z = (int)(i / ((long)a.nx * a.ny));
+  const double x = X * a.dx, y = Y * a.dy, z = Z * a.dz;
+  const double r = sqrt(x * x + y * y + z * z) / a.dmax;
+  if (r < kRFar) return;
+  double o6[6];
+  tensor_far_at(x, y, z, a, o6);
+  for (int c = 0; c < 6; ++c) a.n6[c * N + i] = o6[c];
+}
+
+// The tensor at any offset, regime by distance; the middle regime's
+// quadrature runs in the calling thread.
+__device__ void tensor_at(double x, double y, double z, const TensorArgs& a, double* o6) {
+  const double r = sqrt(x * x + y * y + z * z) / a.dmax;
+  if (r < kRNear) {
+    o6[0] = second_difference<false>(x, y, z, a.dx, a.dy, a.dz);
+    o6[1] = second_difference<false>(y, x, z, a.dy, a.dx, a.dz);
+    o6[2] = second_difference<false>(z, y, x, a.dz, a.dy, a.dx);
+    o6[3] = second_difference<true>(x, y, z, a.dx, a.dy, a.dz);
+    o6[4] = second_difference<true>(x, z, y, a.dx, a.dz, a.dy);
+    o6[5] = second_difference<true>(y, z, x, a.dy, a.dz, a.dx);
+  } else if (r < kRFar) {
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    const int nq = a.nq;
+    for (int ic = 0; ic < nq; ++ic)
+      for (int ib = 0; ib < nq; ++ib)
+        for (int ia = 0; ia < nq; ++ia) {
+          const double w = a.qw[ia] * a.qw[ib] * a.qw[ic];
+          const double sx = x + a.qt[ia] * a.dx, sy = y + a.qt[ib] * a.dy,
+                       sz = z + a.qt[ic] * a.dz;
+          const double s2 = sx * sx + sy * sy + sz * sz;
+          const double inv5 = w / (s2 * s2 * sqrt(s2));
+          acc[0] += (3.0 * sx * sx - s2) * inv5;
+          acc[1] += (3.0 * sy * sy - s2) * inv5;
+          acc[2] += (3.0 * sz * sz - s2) * inv5;
+          acc[3] += 3.0 * sx * sy * inv5;
+          acc[4] += 3.0 * sx * sz * inv5;
+          acc[5] += 3.0 * sy * sz * inv5;
+        }
+    const double pref = -(a.dx * a.dy * a.dz) / (4.0 * kPi);
+    for (int c = 0; c < 6; ++c) o6[c] = pref * acc[c];
+  } else {
+    tensor_far_at(x, y, z, a, o6);
+  }
+}
+
+// Periodic axes: the tensor at offsets 0 <= X <= nx/2 (and/or Y) summed over
+// the images X + k nx, k = -rx..rx; at the half period (X = nx/2, nx even)
+// the offsets +X and -X are one cyclic index holding their mean, so a
+// component odd along that axis is zero there.  Open axes cover 0 <= X < n.
+__global__ void k_tensor_images(TensorArgs a) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nbox = (long)a.bx * a.by * a.bz;
+  if (i >= nbox) return;
+  const int X = (int)(i % a.bx), Y = (int)((i / a.bx) % a.by), Z = (int)(i / ((long)a.bx * a.by));
+  double sum[6] = {0, 0, 0, 0, 0, 0};
+  for (int ky = -a.ry; ky <= a.ry; ++ky)
+    for (int kx = -a.rx; kx <= a.rx; ++kx) {
+      double o6[6];
+      tensor_at((X + (double)kx * a.nx) * a.dx, (Y + (double)ky * a.ny) * a.dy, Z * a.dz, a, o6);
+      for (int c = 0; c < 6; ++c) sum[c] += o6[c];
+    }
+  const bool hx = a.rx > 0 && 2 * X == a.nx, hy = a.ry > 0 && 2 * Y == a.ny;
+  const int oddx[6] = {0, 0, 0, 1, 1, 0}, oddy[6] = {0, 0, 0, 1, 0, 1};
+  const long N = (long)a.nx * a.ny * a.nz;
+  const long o = ((long)Z * a.ny + Y) * a.nx + X;
+  for (int c = 0; c < 6; ++c)
+    a.n6[c * N + o] = ((hx && oddx[c]) || (hy && oddy[c])) ? 0.0 : sum[c];
 }
 
 // --------------------------------------------------- trig transforms ----
@@ -224,9 +295,16 @@ __constant__ int kOddX[6] = {0, 0, 0, 1, 1, 0};
 __constant__ int kOddY[6] = {0, 0, 0, 1, 0, 1};
 __constant__ int kOddZ[6] = {0, 0, 0, 0, 1, 1};
 
-// F1[c][Z][Y][kx] = sum_X w_X N[c][Z][Y][X] trig(kx X)
+// weight of offset X in a cosine/sine sum over X >= 0: offsets +X and -X
+// both, except X = 0 and, on a periodic axis, the half period X = n/2
+__device__ __forceinline__ double offset_weight(int X, int n, int per) {
+  return (X == 0 || (per && 2 * X == n)) ? 1.0 : 2.0;
+}
+
+// F1[c][Z][Y][kx] = sum_X w_X N[c][Z][Y][X] trig(kx X); a periodic axis
+// sums 0 <= X <= nx/2 (the cyclic offsets), an open one 0 <= X < nx
 __global__ void k_trig_x(const double* n6, double* f1, const double* cs, const double* sn,
-                         int nx, int ny, int nz, int Px, int Hx) {
+                         int nx, int ny, int nz, int Px, int Hx, int per) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long tot = 6L * nz * ny * Hx;
   if (i >= tot) return;
@@ -235,17 +313,16 @@ __global__ void k_trig_x(const double* n6, double* f1, const double* cs, const d
   const int c = (int)(row / ((long)nz * ny));
   const double* tab = kOddX[c] ? sn : cs;
   const double* in = n6 + row * nx;
+  const int xe = per ? nx / 2 + 1 : nx;
   double acc = 0.0;
-  for (int X = 0; X < nx; ++X) {
-    const double w = X == 0 ? 1.0 : 2.0;
-    acc += w * in[X] * tab[(int)(((long)kx * X) % Px)];
-  }
+  for (int X = 0; X < xe; ++X)
+    acc += offset_weight(X, nx, per) * in[X] * tab[(int)(((long)kx * X) % Px)];
   f1[i] = acc;
 }
 
 // F2[c][Z][ky][kx] = sum_Y w_Y F1[c][Z][Y][kx] trig(ky Y), ky <= Py/2
 __global__ void k_trig_y(const double* f1, double* f2, const double* cs, const double* sn,
-                         int ny, int nz, int Py, int Hx, int Hy) {
+                         int ny, int nz, int Py, int Hx, int Hy, int per) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long tot = 6L * nz * Hy * Hx;
   if (i >= tot) return;
@@ -255,11 +332,10 @@ __global__ void k_trig_y(const double* f1, double* f2, const double* cs, const d
   const int c = (int)(cz / nz);
   const double* tab = kOddY[c] ? sn : cs;
   const double* in = f1 + cz * ny * Hx + kx;
+  const int ye = per ? ny / 2 + 1 : ny;
   double acc = 0.0;
-  for (int Y = 0; Y < ny; ++Y) {
-    const double w = Y == 0 ? 1.0 : 2.0;
-    acc += w * in[(long)Y * Hx] * tab[(int)(((long)ky * Y) % Py)];
-  }
+  for (int Y = 0; Y < ye; ++Y)
+    acc += offset_weight(Y, ny, per) * in[(long)Y * Hx] * tab[(int)(((long)ky * Y) % Py)];
   f2[i] = acc;
 }
 
@@ -367,10 +443,35 @@ int demag_tensor_only(int nx, int ny, int nz, double dx, double dy, double dz, d
   return fill_tensor(nx, ny, nz, dx, dy, dz, n6, st);
 }
 
+// The image-summed tensor of a grid periodic along x and/or y.
+static int fill_tensor_images(int nx, int ny, int nz, double dx, double dy, double dz, int rx,
+                              int ry, double* n6, hipStream_t st) {
+  TensorArgs a{};
+  a.nx = nx; a.ny = ny; a.nz = nz;
+  a.dx = dx; a.dy = dy; a.dz = dz;
+  a.dmax = std::fmax(dx, std::fmax(dy, dz));
+  const double dmin = std::fmin(dx, std::fmin(dy, dz));
+  const int n = (a.dmax / dmin <= 1.25) ? 8 : 12;
+  a.nq = 2 * n;
+  triangle_rule(n, a.qt, a.qw);
+  a.n6 = n6;
+  a.rx = rx; a.ry = ry;
+  a.bx = rx > 0 ? nx / 2 + 1 : nx;
+  a.by = ry > 0 ? ny / 2 + 1 : ny;
+  a.bz = nz;
+  const long nb = (long)a.bx * a.by * a.bz;
+  hipLaunchKernelGGL(k_tensor_images, dim3((unsigned)((nb + 63) / 64)), dim3(64), 0, st, a);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 template <typename T>
 int demag_kernel_build(const DemagPlan& p, double dx, double dy, double dz, double* n6, T* kout,
                        hipStream_t st) {
-  if (fill_tensor(p.nx, p.ny, p.nz, dx, dy, dz, n6, st)) return -1;
+  if (p.rep[0] > 0 || p.rep[1] > 0) {
+    if (fill_tensor_images(p.nx, p.ny, p.nz, dx, dy, dz, p.rep[0], p.rep[1], n6, st)) return -1;
+  } else if (fill_tensor(p.nx, p.ny, p.nz, dx, dy, dz, n6, st)) {
+    return -1;
+  }
   double *f1 = nullptr, *f2 = nullptr, *tabs = nullptr;
   const size_t n1 = (size_t)6 * p.nz * p.ny * p.Hx;
   const size_t n2 = (size_t)6 * p.nz * p.Hy * p.Hx;
@@ -387,9 +488,9 @@ int demag_kernel_build(const DemagPlan& p, double dx, double dy, double dz, doub
   hipLaunchKernelGGL(k_trig_table, dim3((p.Py + 255) / 256), dim3(256), 0, st, cy, sy, p.Py);
   hipLaunchKernelGGL(k_trig_table, dim3((p.Pz + 255) / 256), dim3(256), 0, st, cz, sz, p.Pz);
   hipLaunchKernelGGL(k_trig_x, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st, n6, f1, cx,
-                     sx, p.nx, p.ny, p.nz, p.Px, p.Hx);
+                     sx, p.nx, p.ny, p.nz, p.Px, p.Hx, p.rep[0] > 0 ? 1 : 0);
   hipLaunchKernelGGL(k_trig_y, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, f1, f2, cy,
-                     sy, p.ny, p.nz, p.Py, p.Hx, p.Hy);
+                     sy, p.ny, p.nz, p.Py, p.Hx, p.Hy, p.rep[1] > 0 ? 1 : 0);
   const double scale = -kMu0 / ((double)p.Px * p.Py * p.Pz);
   hipLaunchKernelGGL((k_trig_z<T>), dim3((unsigned)((p.k_elems + 255) / 256)), dim3(256), 0, st,
                      f2, kout, (double*)nullptr, cz, sz, p.nz, p.Pz, p.Hx, p.Hy, p.Hz, scale);
