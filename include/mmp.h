@@ -137,6 +137,9 @@ typedef struct {
                              A periodic axis with demag needs n = 1 or n
                              even and 7-smooth, <= 4096; pbc[2] must be 0;
                              not combined with elasticity; R <= 1024       */
+  double rayleigh;        /* elastic strain-rate damping: stress gains
+                             rayleigh * C : eps(v) (stiffness-proportional
+                             Rayleigh damping, s; 0 = none)                */
 } mmp_params;
 
 typedef struct {

@@ -181,7 +181,7 @@ class Problem:
             return [self.torque(m)]
         u, v = y[1], y[2]
         e = self.p["elastic"]
-        f = el.elastic_force(u, self.d, self.n, t, e)
+        f = el.elastic_force(u, self.d, self.n, t, e, v)
         for s in range(self.nsub):
             if self.p["Ms"][s] != 0.0:
                 f = f + el.magnetoelastic_force(m[s], self.p["B1"][s], self.p["B2"][s], self.d)

@@ -150,6 +150,7 @@ mmp_status mmp_set_params(mmp_grid g, const mmp_params* p) {
   }
   if (p->nsub == 2 && p->A0 != 0.0 && !(p->latcon > 0)) { set_error("latcon must be > 0"); return MMP_E_ARG; }
   if (p->elastic && !(p->rho > 0)) { set_error("rho must be > 0"); return MMP_E_ARG; }
+  if (!(p->rayleigh >= 0.0)) { set_error("rayleigh must be >= 0"); return MMP_E_ARG; }
   if (p->dmi_layer < -1 || p->dmi_layer >= g->nz) { set_error("bad dmi_layer"); return MMP_E_ARG; }
   const long N = (long)g->nx * g->ny * g->nz;
   if (p->ngrains > 0)

@@ -21,6 +21,8 @@ struct ElasticArgs {
   int stage;                     // 1..7, or 0 = evaluate at (un, vn)
   int fuse2;
   T* eps;                        // [6][N] strain of the stage input
+  T* epsv;                       // [6][N] strain rate (strain of v), beta != 0
+  T beta;                        // Rayleigh stiffness coefficient, s
   T* sig;                        // [6][N] stress with traction rows
   double* epart;                 // [nblk] elastic energy partials (eval)
   double V;

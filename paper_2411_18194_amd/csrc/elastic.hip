@@ -6,7 +6,8 @@
 // bulk, 2nd-order central one cell in from a face, 1st-order one-sided on a
 // face cell (the paper uses lower-order schemes near and at boundaries); an
 // axis with one cell has no derivative.  Strain is the symmetrised
-// gradient of u, stress the cubic law; on each face of an axis with more
+// gradient of u, stress the cubic law plus the viscous stress beta C : eps(v)
+// of stiffness-proportional Rayleigh damping; on each face of an axis with more
 // than one cell the face cell's stress row along that axis is the traction
 // (zero, i.e. traction-free), and the drive sigma_xz = A sin(w t) on x = 0
 // is applied last.  The force is the divergence of that stress plus the
@@ -79,6 +80,22 @@ __global__ void k_strain(ElasticArgs<T> a) {
   a.eps[3 * N + i] = T(0.5) * (g[0][1] + g[1][0]);
   a.eps[4 * N + i] = T(0.5) * (g[0][2] + g[2][0]);
   a.eps[5 * N + i] = T(0.5) * (g[1][2] + g[2][1]);
+  if (a.beta != T(0)) {
+    // strain rate: the same operator on the velocity
+    const T* v = v_in(a.tbl, a.stage);
+    for (int j = 0; j < 3; ++j) {
+      const T* vj = v + j * N;
+      g[0][j] = d1(vj, i, x, a.nx, sx, a.dx);
+      g[1][j] = d1(vj, i, y, a.ny, sy, a.dy);
+      g[2][j] = d1(vj, i, z, a.nz, sz, a.dz);
+    }
+    a.epsv[i] = g[0][0];
+    a.epsv[N + i] = g[1][1];
+    a.epsv[2 * N + i] = g[2][2];
+    a.epsv[3 * N + i] = T(0.5) * (g[0][1] + g[1][0]);
+    a.epsv[4 * N + i] = T(0.5) * (g[0][2] + g[2][0]);
+    a.epsv[5 * N + i] = T(0.5) * (g[1][2] + g[2][1]);
+  }
 }
 
 // Voigt slot of (row, col)
@@ -113,6 +130,17 @@ __global__ void k_stress(ElasticArgs<T> a, int eval) {
       double kv = 0.0;
       for (int c = 0; c < 3; ++c) kv += (double)v[c * N + i] * v[c * N + i];
       e_el = (0.5 * w + 0.5 * a.rho * kv) * a.V;
+    }
+    if (a.beta != T(0)) {
+      // viscous stress beta C : eps(v) (stiffness-proportional Rayleigh damping)
+      T r[6];
+      for (int c = 0; c < 6; ++c) r[c] = a.epsv[c * N + i];
+      s[0] += a.beta * (a.C11 * r[0] + a.C12 * (r[1] + r[2]));
+      s[1] += a.beta * (a.C11 * r[1] + a.C12 * (r[0] + r[2]));
+      s[2] += a.beta * (a.C11 * r[2] + a.C12 * (r[0] + r[1]));
+      s[3] += a.beta * (T(2) * a.C44 * r[3]);
+      s[4] += a.beta * (T(2) * a.C44 * r[4]);
+      s[5] += a.beta * (T(2) * a.C44 * r[5]);
     }
     const int pos[3] = {x, y, z};
     const int n[3] = {a.nx, a.ny, a.nz};

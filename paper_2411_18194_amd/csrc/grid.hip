@@ -53,7 +53,7 @@ template <typename T>
 struct Grid final : GridBase {
   // state and stages
   Buf<T> y[2], sa, sb, k[7];
-  Buf<T> u[2], v[2], usa, usb, vsa, vsb, ku[7], kv[7], eps, sig;
+  Buf<T> u[2], v[2], usa, usb, vsa, vsb, ku[7], kv[7], eps, epsv, sig;
   Buf<T> Bd, gax;
   Buf<uint16_t> gid;
   Buf<double> errpart, epart, eout, spart, samp_t, samp_m, elpart;
@@ -89,7 +89,7 @@ struct Grid final : GridBase {
   void free_all() {
     drop_graphs();
     for (auto* b : {&y[0], &y[1], &sa, &sb, &u[0], &u[1], &v[0], &v[1], &usa, &usb, &vsa, &vsb,
-                    &eps, &sig, &Bd, &gax, &K})
+                    &eps, &epsv, &sig, &Bd, &gax, &K})
       b->release();
     for (int i = 0; i < 7; ++i) { k[i].release(); ku[i].release(); kv[i].release(); }
     gid.release();
@@ -125,6 +125,7 @@ struct Grid final : GridBase {
       rc |= usa.alloc(n3); rc |= usb.alloc(n3); rc |= vsa.alloc(n3); rc |= vsb.alloc(n3);
       for (int i = 0; i < 7; ++i) { rc |= ku[i].alloc(n3); rc |= kv[i].alloc(n3); }
       rc |= eps.alloc(6 * (size_t)N);
+      rc |= epsv.alloc(6 * (size_t)N);
       rc |= sig.alloc(6 * (size_t)N);
     }
     // partial sums for the smallest z chunk (one plane per thread)
@@ -588,6 +589,7 @@ struct Grid final : GridBase {
       e.mel[s] = (p.sub[s].Ms != 0.0 && (p.sub[s].B1 != 0.0 || p.sub[s].B2 != 0.0)) ? 1 : 0;
     }
     e.tbl = dtbl.p; e.ctrl = dctrl.p; e.eps = eps.p; e.sig = sig.p; e.epart = elpart.p;
+    e.epsv = epsv.p; e.beta = (T)p.rayleigh;
     e.V = a.V; e.rho = p.rho;
     ea = e;
     drop_graphs();

@@ -57,7 +57,7 @@ class Params(C.Structure):
                 ("C12", C.c_double), ("C44", C.c_double), ("eta", C.c_double),
                 ("trac_amp", C.c_double), ("trac_freq", C.c_double), ("tol", C.c_double),
                 ("dt0", C.c_double), ("dt_min", C.c_double), ("solver", C.c_int32),
-                ("pbc", C.c_int32 * 3)]
+                ("pbc", C.c_int32 * 3), ("rayleigh", C.c_double)]
 
 
 class StepInfo(C.Structure):
@@ -216,6 +216,7 @@ def make_params(p: dict, precision=FP32, tol=1e-5, dt0=1e-14, dt_min=1e-20):
         P.elastic = 1
         P.rho = el["rho"]; P.C11 = el["C11"]; P.C12 = el["C12"]; P.C44 = el["C44"]
         P.eta = el["eta"]; P.trac_amp = el["trac_amp"]; P.trac_freq = el["trac_freq"]
+        P.rayleigh = el.get("rayleigh", 0.0)
     P.tol, P.dt0, P.dt_min = tol, dt0, dt_min
     P.solver = SOLVERS[p.get("solver", "dp45")]
     P.pbc[:] = [int(v) for v in p.get("pbc", (0, 0, 0))]

@@ -101,3 +101,51 @@ def test_energy_conservation_free_pulse():
     y, t = P.run_fixed(y, 0.0, 2e-14, 500)
     E1 = P.energies(y[0], y[1], y[2])["elastic"]
     assert E1 == pytest.approx(E0, rel=1e-5)
+
+
+def test_printed_rayleigh_damping_ratio():
+    """A free-free standing shear wave of 24 nm wavelength decays with the
+    damping ratio beta*omega/2 of stiffness-proportional (Kelvin-Voigt)
+    damping, and the printed coefficient gives the printed ~5 %."""
+    dx = 1e-9
+    lam = NIO["rayleigh_shear_wavelength_m"]
+    nx = int(round(2 * lam / dx))                  # two wavelengths, free ends
+    p = _nio_bar(nx, dx)
+    beta = NIO["rayleigh_stiffness_coefficient_s"]
+    p["elastic"] = dict(p["elastic"], trac_amp=0.0, rayleigh=beta)
+    P = Problem(p)
+    m = np.zeros((1, 3, 1, 1, nx))
+    m[0, 2] = 1.0
+    y = P.initial_state(m)
+    k = 2 * math.pi / lam
+    phi = np.cos(k * (np.arange(nx) + 0.5) * dx)
+    y[1][2, 0, 0, :] = 1e-12 * phi
+    dt = 2e-14
+    amp, ts = [], []
+    t = 0.0
+    for _ in range(120):
+        y, t = P.run_fixed(y, t, dt, 5)
+        amp.append(float(y[1][2, 0, 0, :] @ phi / (phi @ phi)))
+        ts.append(t)
+    amp, ts = np.array(amp), np.array(ts)
+    # local extrema of the modal amplitude: their spacing is half a damped
+    # period, the log of their magnitudes falls at rate zeta*omega
+    ext = [i for i in range(1, len(amp) - 1)
+           if (amp[i] - amp[i - 1]) * (amp[i + 1] - amp[i]) < 0]
+    te, ae = ts[ext], np.log(np.abs(amp[ext]))
+    omega = math.pi / np.mean(np.diff(te))
+    slope = np.polyfit(te, ae, 1)[0]
+    zeta = -slope / omega
+    c = math.sqrt(NIO["C44_Pa"] / NIO["rho_kg_m3"])
+    assert omega == pytest.approx(k * c, rel=0.03)
+    assert zeta == pytest.approx(beta * k * c / 2, rel=0.08)
+    assert zeta == pytest.approx(NIO["rayleigh_damping_ratio_about"], abs=0.008)
+    # without the viscous stress the same wave does not decay
+    p["elastic"] = dict(p["elastic"], rayleigh=0.0)
+    P0 = Problem(p)
+    y0 = P0.initial_state(m)
+    y0[1][2, 0, 0, :] = 1e-12 * phi
+    y0, _ = P0.run_fixed(y0, 0.0, dt, 600)
+    E = P0.energies(y0[0], y0[1], y0[2])["elastic"]
+    assert E > 0.98 * P0.energies(m, 1e-12 * np.stack([0 * phi, 0 * phi, phi])[:, None, None, :],
+                                  np.zeros((3, 1, 1, nx)))["elastic"]
