@@ -69,7 +69,8 @@ typedef int32_t mmp_status;
 #define MMP_T_EXCH      (1u << 1)  /* 2 A11/Ms lap m   (Eq. 3, term 1)     */
 #define MMP_T_AFM_NN    (1u << 2)  /* A12/Ms lap m'    (Eq. 3, term 2)     */
 #define MMP_T_AFM_CELL  (1u << 3)  /* 4 A0/(Ms a^2) m' (Eq. 3, term 3)     */
-#define MMP_T_DMI       (1u << 4)  /* interfacial DMI                      */
+#define MMP_T_DMI       (1u << 4)  /* DMI: interfacial (one sublattice),
+                                      homogeneous d.(m1 x m2) (two)        */
 #define MMP_T_ANIS_U    (1u << 5)  /* uniaxial anisotropy                  */
 #define MMP_T_ANIS_C    (1u << 6)  /* cubic anisotropy                     */
 #define MMP_T_ZEEMAN    (1u << 7)  /* external field                       */
@@ -140,6 +141,9 @@ typedef struct {
   double rayleigh;        /* elastic strain-rate damping: stress gains
                              rayleigh * C : eps(v) (stiffness-proportional
                              Rayleigh damping, s; 0 = none)                */
+  double dmi_homo[3];     /* homogeneous DMI vector d of a two-sublattice
+                             magnet, J/m^3: energy density d.(m1 x m2)
+                             per cell, reported with the DMI term          */
 } mmp_params;
 
 typedef struct {

@@ -22,6 +22,10 @@ periodic): on a periodic axis the ghost of a boundary cell is the cell at
 the opposite end, for the exchange, inter-sublattice and DMI stencils alike,
 and no DMI boundary condition applies on that axis's faces.
 
+Homogeneous DMI of a two-sublattice magnet: energy density d.(m1 x m2)
+(the pair counted once; summing both orders would cancel it), fields
+-(m2 x d)/Ms1 and -(d x m1)/Ms2.  It is reported with the DMI term.
+
 Uniaxial anisotropy: (2 Ku1/Ms)(u.m) u + (4 Ku2/Ms)(u.m)^3 u.
 Cubic anisotropy: -(2 Kc1/Ms) sum_k a_k (a_l^2 + a_n^2) c_k with
 a_k = m.c_k in the frame (c1, c2, c1 x c2).
@@ -146,6 +150,18 @@ def dmi_field(m, Ms, A, D, d, dmi_layer=None, periodic=(False, False, False)):
     B = np.stack([ddx[2], ddy[2], -ddx[0] - ddy[1]])
     mask = dmi_layer_mask(m.shape[1:], dmi_layer)
     return (2.0 * D / Ms) * B * mask[None]
+
+
+def homogeneous_dmi_field(m, mp, Ms, dvec, first):
+    """Homogeneous DMI between the two sublattices of a cell ("DMI and
+    boundary conditions"): energy density d . (m^(1) x m^(2)), the pair
+    counted once.  B^(1) = -(m^(2) x d)/Ms1, B^(2) = -(d x m^(1))/Ms2;
+    ``first`` selects the sublattice m belongs to, mp is the other one."""
+    if Ms == 0.0 or not np.any(dvec):
+        return np.zeros_like(m)
+    d = np.asarray(dvec, dtype=np.float64)[:, None, None, None]
+    c = np.cross(mp, d, axis=0)          # m' x d
+    return (-c if first else c) / Ms
 
 
 def uniaxial_field(m, Ms, Ku1, Ku2, u):

@@ -78,8 +78,12 @@ class Problem:
                 return np.zeros_like(ms)
             return fl.afm_cell_field(other, Ms, p["A0"], p["latcon"])
         if name == "dmi":
-            return fl.dmi_field(ms, Ms, p["A11"][s], p["Dint"][s], d,
-                                p["dmi_layer"], self.periodic)
+            B = fl.dmi_field(ms, Ms, p["A11"][s], p["Dint"][s], d,
+                             p["dmi_layer"], self.periodic)
+            if other is not None:
+                B = B + fl.homogeneous_dmi_field(ms, other, Ms, p.get("dmi_homo", (0, 0, 0)),
+                                                 s == 0)
+            return B
         if name == "anis_u":
             ax = self.axis if self.axis is not None else p["anis_u"][s]
             return fl.uniaxial_field(ms, Ms, p["Ku1"][s], p["Ku2"][s], ax)

@@ -14,6 +14,7 @@ struct SubC {
   T ms;                       // Ms (demag source)
   T cex, cnn, ccell;          // 2A11/Ms, A12/Ms, 4A0/(Ms a^2)
   T cdmi, kdmi;               // 2D/Ms, ghost slope -D/(2 A11)
+  T dh[3];                    // homogeneous DMI: -d/Ms1 (first), +d/Ms2 (second)
   T cku1, cku2, u[3];         // 2Ku1/Ms, 4Ku2/Ms, axis
   T ckc, c1[3], c2[3], c3[3]; // 2Kc1/Ms, cubic frame
   T cmel1, cmel2;             // 2B1/Ms, 2B2/Ms
@@ -34,6 +35,7 @@ struct FieldArgs {
   int dmi_layer;
   int has_demag, has_dmi, has_anis_u, has_anis_c, has_mel;
   int per_x, per_y;           // periodic axes: neighbours wrap, no DMI boundary
+  int has_dmih;               // homogeneous inter-sublattice DMI
   const uint16_t* grain;
   const T* gaxes;
   const T* Bd;

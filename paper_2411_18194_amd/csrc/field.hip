@@ -7,7 +7,8 @@
 // hide the latency of the dependent loads; longer ones re-read fewer
 // z neighbours.  Per cell and sublattice it forms
 //   B = B_demag + exchange (Eq. 3: 2A11/Ms lap m, A12/Ms lap m', 4A0/(Ms a^2) m')
-//     + interfacial DMI + uniaxial/cubic anisotropy + Zeeman + B_mel (Eq. 9)
+//     + interfacial DMI (one sublattice) or homogeneous DMI d.(m1 x m2) (two)
+//     + uniaxial/cubic anisotropy + Zeeman + B_mel (Eq. 9)
 // and the torque tau = LLG (Eq. 2) + Zhang-Li, then, in a Runge-Kutta
 // stage, writes k_s and immediately the next stage input
 // y_{s+1} = normalise(y_n + h sum_j a_{s+1,j} k_j) (all point-wise), or at
@@ -237,6 +238,12 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
             }
           }
           if (EVAL) eacc[3] += -0.5 * C.Ms_d * dot3d(mm, bt);
+          // homogeneous DMI d.(m1 x m2): B = m' x dh, dh = -/+ d/Ms
+          if (a.has_dmih) {
+            cross3(cur[o], C.dh, bt);
+            add(4, bt);
+            if (EVAL) eacc[4] += -0.5 * C.Ms_d * dot3d(mm, bt);
+          }
         }
         // demag
         if (a.has_demag && C.nonzero) {

@@ -204,6 +204,8 @@ struct Grid final : GridBase {
     s.ccell = (T)(nz ? 4.0 * p.A0 / (Ms * p.latcon * p.latcon) : 0.0);
     s.cdmi = (T)(nz ? 2.0 * b.Dint / Ms : 0.0);
     s.kdmi = (T)((b.A11 != 0.0 && b.Dint != 0.0) ? -b.Dint / (2.0 * b.A11) : 0.0);
+    for (int c = 0; c < 3; ++c)
+      s.dh[c] = (T)(nz && p.nsub == 2 ? (&b == &p.sub[0] ? -1.0 : 1.0) * p.dmi_homo[c] / Ms : 0.0);
     s.cku1 = (T)(nz ? 2.0 * b.Ku1 / Ms : 0.0);
     s.cku2 = (T)(nz ? 4.0 * b.Ku2 / Ms : 0.0);
     for (int c = 0; c < 3; ++c) s.u[c] = (T)b.anis_u[c];
@@ -565,6 +567,8 @@ struct Grid final : GridBase {
     a.V = d[0] * d[1] * d[2];
     a.nbx = (nx + kTileX - 1) / kTileX;
     a.nby = (ny + kTileY - 1) / kTileY;
+    a.has_dmih = (p.nsub == 2 && (p.dmi_homo[0] != 0.0 || p.dmi_homo[1] != 0.0 ||
+                                  p.dmi_homo[2] != 0.0)) ? 1 : 0;
     a.per_x = p.pbc[0] > 0 ? 1 : 0;
     a.per_y = p.pbc[1] > 0 ? 1 : 0;
     fa = a;

@@ -81,6 +81,7 @@ def base_params(n, cell, nsub=1):
         "elastic": None,
         "solver": "dp45",
         "pbc": (0, 0, 0),
+        "dmi_homo": (0.0, 0.0, 0.0),
     }
 
 

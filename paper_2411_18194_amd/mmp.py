@@ -57,7 +57,8 @@ class Params(C.Structure):
                 ("C12", C.c_double), ("C44", C.c_double), ("eta", C.c_double),
                 ("trac_amp", C.c_double), ("trac_freq", C.c_double), ("tol", C.c_double),
                 ("dt0", C.c_double), ("dt_min", C.c_double), ("solver", C.c_int32),
-                ("pbc", C.c_int32 * 3), ("rayleigh", C.c_double)]
+                ("pbc", C.c_int32 * 3), ("rayleigh", C.c_double),
+                ("dmi_homo", C.c_double * 3)]
 
 
 class StepInfo(C.Structure):
@@ -220,6 +221,7 @@ def make_params(p: dict, precision=FP32, tol=1e-5, dt0=1e-14, dt_min=1e-20):
     P.tol, P.dt0, P.dt_min = tol, dt0, dt_min
     P.solver = SOLVERS[p.get("solver", "dp45")]
     P.pbc[:] = [int(v) for v in p.get("pbc", (0, 0, 0))]
+    P.dmi_homo[:] = [float(v) for v in p.get("dmi_homo", (0.0, 0.0, 0.0))]
     return P, keep
 
 

@@ -49,6 +49,13 @@ def _afm_demag():
     return p, inputs.random_unit(inputs.rng(13), 2, p["n"])
 
 
+def _afm_dmih():
+    # homogeneous inter-sublattice DMI with demag and a current
+    p, m = _afm_demag()
+    p.update(dmi_homo=(1.5e5, -0.8e5, 2.2e5))
+    return p, m
+
+
 def _c4_crop_u():
     p, m = inputs.config_c4_crop()
     nx, ny, nz = p["n"]
@@ -91,6 +98,7 @@ CASES = {
     "ragged3d": _ragged3d,
     "ragged2d": _ragged2d,
     "afm_demag": _afm_demag,
+    "afm_dmih": _afm_dmih,
     "tiny111": lambda: _tiny((1, 1, 1)),
     "tiny213": lambda: _tiny((2, 1, 3)),
     "tiny171": lambda: _tiny((1, 7, 1)),
@@ -158,7 +166,7 @@ def test_eval_heff_per_term(name, prec):
 
 
 @pytest.mark.parametrize("prec", [mmp.FP64, mmp.FP32])
-@pytest.mark.parametrize("name", ["c3crop", "afm_demag", "c2crop"])
+@pytest.mark.parametrize("name", ["c3crop", "afm_demag", "c2crop", "afm_dmih"])
 def test_torque_parity(name, prec):
     p, m = CASES[name]()
     if prec == mmp.FP32:
@@ -192,7 +200,7 @@ def test_magnetoelastic_parity(prec):
     g.close()
 
 
-@pytest.mark.parametrize("name", ["c2crop", "ragged3d", "afm_demag", "c3crop"])
+@pytest.mark.parametrize("name", ["c2crop", "ragged3d", "afm_demag", "c3crop", "afm_dmih"])
 def test_fixed_steps_fp64(name):
     p, m = CASES[name]()
     P = Problem(p)

@@ -171,3 +171,23 @@ def test_dmi_edge_canting_bvp():
     # cell centre) to the continuum profile
     assert errs[1] < 0.005 * abs(sol.sol(0.0)[0])
     assert errs[0] / errs[1] > 1.7
+
+
+def test_homogeneous_dmi():
+    """d.(m1 x m2): the energy gradient is the field, and the closed forms
+    for m1 = x, m2 = y, d = D z: energy D V per cell, B1 = -D/Ms1 x,
+    B2 = -D/Ms2 y."""
+    p = inputs.base_params((4, 3, 2), (2e-9, 2e-9, 1e-9), nsub=2)
+    p.update(Ms=[4e5, 3e5], dmi_homo=(2e5, -1e5, 3e5))
+    m = inputs.random_unit(inputs.rng(6), 2, p["n"])
+    _energy_gradient_check(p, m, ("dmi",))
+    D = 7e5
+    p.update(dmi_homo=(0.0, 0.0, D))
+    m = np.zeros((2, 3, 2, 3, 4))
+    m[0, 0] = 1.0
+    m[1, 1] = 1.0
+    P = Problem(p)
+    B = P.eval_heff(m, ("dmi",))
+    assert np.allclose(B[0, 0], -D / 4e5, rtol=1e-15) and np.allclose(B[0, 1:], 0)
+    assert np.allclose(B[1, 1], -D / 3e5, rtol=1e-15) and np.allclose(B[1, [0, 2]], 0)
+    assert P.energies(m)["dmi"] == pytest.approx(D * P.V * 24, rel=1e-14)
