@@ -20,6 +20,7 @@ import numpy as np
 
 from . import elastic as el
 from . import fields as fl
+from . import dmi
 from . import torque as tq
 from .demag import Demag
 from .rk import TABLEAUS, Stepper, new_dt
@@ -44,6 +45,17 @@ class Problem:
         if any(self.pbc) and p["elastic"] is not None:
             raise ValueError("periodic boundaries are not combined with elasticity")
         self.periodic = tuple(v > 0 for v in self.pbc)
+        # boundary condition of the stencils: "open" (ghost = boundary cell,
+        # or the Eq. 5 ghosts of the interfacial DMI) or "eq6" (Eq. 6 with
+        # the general DMI tensors of Eq. 4)
+        self.eq6 = p.get("bc", "open") == "eq6"
+        W, W12 = p.get("dmi_W"), p.get("dmi_W12")
+        self.W = np.zeros((self.nsub, 3, 3)) if W is None else np.asarray(W, dtype=np.float64)
+        self.W12 = np.zeros((3, 3)) if W12 is None else np.asarray(W12, dtype=np.float64)
+        if (np.any(self.W) or np.any(self.W12)) and not self.eq6:
+            raise ValueError("DMI tensors need the Eq. 6 boundary condition (bc='eq6')")
+        if self.eq6 and any(v != 0.0 for v in p["Dint"]):
+            raise ValueError("with bc='eq6' give the interfacial DMI as a tensor")
         self.demag = Demag(self.n, self.d, N6, demag_workers, self.pbc) if p["demag"] else None
         self.axis = None
         if p.get("grain") is not None:
@@ -66,6 +78,8 @@ class Problem:
             if Bd is None:
                 Bd = self.demag_field(m)
             return Bd.copy() if Ms != 0.0 else np.zeros_like(ms)
+        if self.eq6 and name in ("exch", "afm_nn", "dmi"):
+            return self._eq6_term(name, m, s)
         if name == "exch":
             return fl.exchange_field(ms, Ms, p["A11"][s], d, p["Dint"][s],
                                      p["dmi_layer"], self.periodic)
@@ -97,6 +111,26 @@ class Problem:
             return fl.magnetoelastic_field(ms, Ms, p["B1"][s], p["B2"][s],
                                            self.strain(u))
         raise KeyError(name)
+
+    def _eq6_term(self, name, m, s):
+        """Exchange, inter-sublattice exchange or DMI over the Eq. 6 ghosts."""
+        p, d = self.p, self.d
+        Ms = p["Ms"][s]
+        if Ms == 0.0:
+            return np.zeros_like(m[s])
+        g = dmi.eq6_ghosts(np.asarray(m), d, p["A11"], p["A12"], self.W, self.periodic)
+        o = 1 - s if self.nsub == 2 else None
+        if name == "exch":
+            return (2.0 * p["A11"][s] / Ms) * fl.laplacian(g[s], d)
+        if name == "afm_nn":
+            if o is None:
+                return np.zeros_like(m[s])
+            return (p["A12"] / Ms) * fl.laplacian(g[o], d)
+        B = dmi.tensor_field(g[s], None if o is None else g[o], Ms, self.W[s], self.W12, d)
+        if o is not None:
+            B = B + fl.homogeneous_dmi_field(m[s], m[o], Ms, p.get("dmi_homo", (0, 0, 0)),
+                                             s == 0)
+        return B
 
     def demag_field(self, m):
         M = sum(self.p["Ms"][s] * m[s] for s in range(self.nsub))

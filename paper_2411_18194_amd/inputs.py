@@ -82,6 +82,9 @@ def base_params(n, cell, nsub=1):
         "solver": "dp45",
         "pbc": (0, 0, 0),
         "dmi_homo": (0.0, 0.0, 0.0),
+        "bc": "open",
+        "dmi_W": None,
+        "dmi_W12": None,
     }
 
 
