@@ -144,6 +144,21 @@ typedef struct {
   double dmi_homo[3];     /* homogeneous DMI vector d of a two-sublattice
                              magnet, J/m^3: energy density d.(m1 x m2)
                              per cell, reported with the DMI term          */
+  int32_t bc_eq6;         /* 1: the Neumann condition of Eq. 6 on every
+                             open face (A12 coupling of the two
+                             sublattices' normal derivatives and the DMI
+                             tensor term, solved per boundary cell) feeds
+                             the exchange, A12 and DMI stencils, and the
+                             DMI tensors below are on; 0: a missing
+                             neighbour is the cell itself (Eq. 5 ghosts
+                             for the interfacial Dint)                     */
+  int32_t pad2;
+  double dmi_W[2][3][3];  /* DMI tensor of each sublattice (Eq. 4) as
+                             three vectors W_i: D_ijk = sum_a eps_ajk W_ia
+                             (W_ix = D_i,yz, W_iy = D_i,zx, W_iz = D_i,xy),
+                             J/m^2; needs bc_eq6; interfacial D:
+                             W_x = (0, D, 0), W_y = (-D, 0, 0)             */
+  double dmi_W12[3][3];   /* inter-sublattice DMI tensor, same form        */
 } mmp_params;
 
 typedef struct {

@@ -151,6 +151,21 @@ mmp_status mmp_set_params(mmp_grid g, const mmp_params* p) {
   if (p->nsub == 2 && p->A0 != 0.0 && !(p->latcon > 0)) { set_error("latcon must be > 0"); return MMP_E_ARG; }
   if (p->elastic && !(p->rho > 0)) { set_error("rho must be > 0"); return MMP_E_ARG; }
   if (!(p->rayleigh >= 0.0)) { set_error("rayleigh must be >= 0"); return MMP_E_ARG; }
+  {
+    bool tens = false;
+    for (int s = 0; s < 2; ++s)
+      for (int i = 0; i < 3; ++i)
+        for (int c = 0; c < 3; ++c)
+          tens = tens || p->dmi_W[s][i][c] != 0.0 || (s == 0 && p->dmi_W12[i][c] != 0.0);
+    if (tens && !p->bc_eq6) {
+      set_error("DMI tensors need the Eq. 6 boundary condition (bc_eq6 = 1)");
+      return MMP_E_ARG;
+    }
+    if (p->bc_eq6 && (p->sub[0].Dint != 0.0 || (p->nsub == 2 && p->sub[1].Dint != 0.0))) {
+      set_error("with bc_eq6 give the interfacial DMI as a tensor");
+      return MMP_E_ARG;
+    }
+  }
   if (p->dmi_layer < -1 || p->dmi_layer >= g->nz) { set_error("bad dmi_layer"); return MMP_E_ARG; }
   const long N = (long)g->nx * g->ny * g->nz;
   if (p->ngrains > 0)

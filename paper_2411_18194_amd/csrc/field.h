@@ -36,6 +36,12 @@ struct FieldArgs {
   int has_demag, has_dmi, has_anis_u, has_anis_c, has_mel;
   int per_x, per_y;           // periodic axes: neighbours wrap, no DMI boundary
   int has_dmih;               // homogeneous inter-sublattice DMI
+  // DMI tensors (Eq. 4) with the Neumann condition of Eq. 6 (gdmi != 0):
+  // eW = W^(s) (rows: directions), eA = A11^(s), eA12 = A12 for the ghosts;
+  // cW = -2 W^(s)/Ms^(s), cW12 = -2 W^(12)/Ms^(s) for the field
+  int gdmi;
+  T eW[2][3][3], eA[2], eA12;
+  T cW[2][3][3], cW12[2][3][3];
   const uint16_t* grain;
   const T* gaxes;
   const T* Bd;

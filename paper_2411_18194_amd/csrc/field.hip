@@ -54,9 +54,94 @@ __device__ __forceinline__ double dot3d(const T* a, const T* b) {
   return (double)a[0] * b[0] + (double)a[1] * b[1] + (double)a[2] * b[2];
 }
 
+// Ghosts beyond one face (axis ax, outward side +-1, cell size h) of every
+// sublattice from the Neumann condition of Eq. 6:
+//   2 A11^(s) g_s = A12 (g_s' x m_s) x m_s + m_s x w_s,  w_s = side W^(s)_ax,
+// with (g x m) x m = -Q g, Q = I - m m^T; for two sublattices g2 solves
+// (2 A2 I - A12^2/(2 A1) Q2 Q1) g2 = b2 - A12/(2 A1) Q2 b1 (Cramer's rule),
+// then g1 = (b1 - A12 Q1 g2)/(2 A1).  A sublattice with A11 = 0 keeps a
+// plain copy.  ghost = m + h g.
+template <typename T, int NSUB>
+__device__ void eq6_ghost(const FieldArgs<T>& a, const T (*m)[3], int ax, T side, T h,
+                          T (*out)[3]) {
+  T b[NSUB][3], g[NSUB][3];
+#pragma unroll
+  for (int s = 0; s < NSUB; ++s) {
+    T w[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) w[c] = side * a.eW[s][ax][c];
+    cross3(m[s], w, b[s]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g[s][c] = T(0);
+  }
+  if constexpr (NSUB == 1) {
+    if (a.eA[0] != T(0))
+#pragma unroll
+      for (int c = 0; c < 3; ++c) g[0][c] = b[0][c] / (T(2) * a.eA[0]);
+  } else {
+    const T A1 = a.eA[0], A2 = a.eA[1], A12 = a.eA12;
+    if (A1 != T(0) && A2 != T(0)) {
+      T Q1[3][3], Q2[3][3], M[3][3], r[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          Q1[i][j] = (i == j ? T(1) : T(0)) - m[0][i] * m[0][j];
+          Q2[i][j] = (i == j ? T(1) : T(0)) - m[1][i] * m[1][j];
+        }
+      const T c = A12 * A12 / (T(2) * A1), e = A12 / (T(2) * A1);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        T q2b1 = T(0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) q2b1 += Q2[i][k] * b[0][k];
+        r[i] = b[1][i] - e * q2b1;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          T qq = T(0);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) qq += Q2[i][k] * Q1[k][j];
+          M[i][j] = (i == j ? T(2) * A2 : T(0)) - c * qq;
+        }
+      }
+      const T det = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
+                    M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+                    M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+      const T id = T(1) / det;
+      g[1][0] = id * (r[0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
+                      M[0][1] * (r[1] * M[2][2] - M[1][2] * r[2]) +
+                      M[0][2] * (r[1] * M[2][1] - M[1][1] * r[2]));
+      g[1][1] = id * (M[0][0] * (r[1] * M[2][2] - M[1][2] * r[2]) -
+                      r[0] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+                      M[0][2] * (M[1][0] * r[2] - r[1] * M[2][0]));
+      g[1][2] = id * (M[0][0] * (M[1][1] * r[2] - r[1] * M[2][1]) -
+                      M[0][1] * (M[1][0] * r[2] - r[1] * M[2][0]) +
+                      r[0] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]));
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        T q1g2 = T(0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) q1g2 += Q1[i][k] * g[1][k];
+        g[0][i] = (b[0][i] - A12 * q1g2) / (T(2) * A1);
+      }
+    } else if (A1 != T(0)) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) g[0][c] = b[0][c] / (T(2) * A1);
+    } else if (A2 != T(0)) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) g[1][c] = b[1][c] / (T(2) * A2);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < NSUB; ++s)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[s][c] = m[s][c] + h * g[s][c];
+}
+
 // Block w (tile-major over z chunks) of one grid; stage and fuse2 come from
 // the launch so that one argument block serves every stage.
-template <typename T, int NSUB, bool EVAL>
+// GDMI: general DMI tensors with the Eq. 6 ghosts on every stencil.
+template <typename T, int NSUB, bool EVAL, bool GDMI = false>
 __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, const int stage,
                                             const int fuse2) {
   const int ntile = a.nbx * a.nby;
@@ -159,6 +244,25 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
         uax[2] = a.gaxes[3 * g + 2];
       }
       const bool dmil = NSUB == 1 && a.has_dmi && (a.dmi_layer < 0 || z == a.dmi_layer);
+      // neighbours seen by the exchange and DMI stencils: the loaded ones, or
+      // the Eq. 6 ghosts on the faces of the open axes (z neighbours are
+      // copied: the rotating z registers must keep the cells themselves)
+      T sxm[NSUB][3], sxp[NSUB][3], sym[NSUB][3], syp[NSUB][3], szm[NSUB][3], szp[NSUB][3];
+#pragma unroll
+      for (int s = 0; s < NSUB; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          sxm[s][c] = xm[s][c]; sxp[s][c] = xp[s][c]; sym[s][c] = ym[s][c];
+          syp[s][c] = yp[s][c]; szm[s][c] = zm[s][c]; szp[s][c] = zp[s][c];
+        }
+      if constexpr (GDMI) {
+        if (x == 0 && !a.per_x) eq6_ghost<T, NSUB>(a, cur, 0, T(-1), a.dx, sxm);
+        if (x + 1 == a.nx && !a.per_x) eq6_ghost<T, NSUB>(a, cur, 0, T(1), a.dx, sxp);
+        if (y == 0 && !a.per_y) eq6_ghost<T, NSUB>(a, cur, 1, T(-1), a.dy, sym);
+        if (y + 1 == a.ny && !a.per_y) eq6_ghost<T, NSUB>(a, cur, 1, T(1), a.dy, syp);
+        if (z == 0) eq6_ghost<T, NSUB>(a, cur, 2, T(-1), a.dz, szm);
+        if (z + 1 == a.nz) eq6_ghost<T, NSUB>(a, cur, 2, T(1), a.dz, szp);
+      }
 
 #pragma unroll
       for (int s = 0; s < NSUB; ++s) {
@@ -168,7 +272,7 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
         T gxm[3], gxp[3], gym[3], gyp[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          gxm[c] = xm[s][c]; gxp[c] = xp[s][c]; gym[c] = ym[s][c]; gyp[c] = yp[s][c];
+          gxm[c] = sxm[s][c]; gxp[c] = sxp[s][c]; gym[c] = sym[s][c]; gyp[c] = syp[s][c];
         }
         if (dmil) {
           // boundary condition of Eq. 5 on the faces of the open axes
@@ -200,7 +304,7 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
         for (int c = 0; c < 3; ++c) {
           const T l = ((gxm[c] - mm[c]) + (gxp[c] - mm[c])) * a.idx2 +
                       ((gym[c] - mm[c]) + (gyp[c] - mm[c])) * a.idy2 +
-                      ((zm[s][c] - mm[c]) + (zp[s][c] - mm[c])) * a.idz2;
+                      ((szm[s][c] - mm[c]) + (szp[s][c] - mm[c])) * a.idz2;
           bt[c] = C.cex * l;
         }
         add(1, bt);
@@ -213,15 +317,44 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
           add(4, bt);
           if (EVAL) eacc[4] += -0.5 * C.Ms_d * dot3d(mm, bt);
         }
+        // DMI tensors (Eq. 4): B = sum_i d_i m x cW_i + d_i m' x cW'_i,
+        // cW = -2 W/Ms, central differences over the Eq. 6 ghosts
+        if constexpr (GDMI) {
+          T dm[3][3], dmo[3][3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            dm[0][c] = (sxp[s][c] - sxm[s][c]) * a.i2dx;
+            dm[1][c] = (syp[s][c] - sym[s][c]) * a.i2dy;
+            dm[2][c] = (szp[s][c] - szm[s][c]) * a.i2dz;
+            if (NSUB == 2) {
+              const int o = 1 - s;
+              dmo[0][c] = (sxp[o][c] - sxm[o][c]) * a.i2dx;
+              dmo[1][c] = (syp[o][c] - sym[o][c]) * a.i2dy;
+              dmo[2][c] = (szp[o][c] - szm[o][c]) * a.i2dz;
+            }
+          }
+          T acc[3] = {0, 0, 0}, tmp[3];
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            cross3(dm[i], a.cW[s][i], tmp);
+            acc[0] += tmp[0]; acc[1] += tmp[1]; acc[2] += tmp[2];
+            if (NSUB == 2) {
+              cross3(dmo[i], a.cW12[s][i], tmp);
+              acc[0] += tmp[0]; acc[1] += tmp[1]; acc[2] += tmp[2];
+            }
+          }
+          add(4, acc);
+          if (EVAL) eacc[4] += -0.5 * C.Ms_d * dot3d(mm, acc);
+        }
         // two-sublattice exchange
         if (NSUB == 2) {
           const int o = 1 - s;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             const T mo = cur[o][c];
-            const T l = ((xm[o][c] - mo) + (xp[o][c] - mo)) * a.idx2 +
-                        ((ym[o][c] - mo) + (yp[o][c] - mo)) * a.idy2 +
-                        ((zm[o][c] - mo) + (zp[o][c] - mo)) * a.idz2;
+            const T l = ((sxm[o][c] - mo) + (sxp[o][c] - mo)) * a.idx2 +
+                        ((sym[o][c] - mo) + (syp[o][c] - mo)) * a.idy2 +
+                        ((szm[o][c] - mo) + (szp[o][c] - mo)) * a.idz2;
             bt[c] = C.cnn * l;
           }
           add(2, bt);
@@ -452,10 +585,10 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
   }
 }
 
-template <typename T, int NSUB, bool EVAL>
+template <typename T, int NSUB, bool EVAL, bool GDMI = false>
 __global__ __launch_bounds__(256) void k_field(const FieldArgs<T> a) {
   if (ctrl_stopped(a.ctrl)) return;
-  field_block<T, NSUB, EVAL>(a, xcd_remap(blockIdx.x, a.nb_pad), a.stage, a.fuse2);
+  field_block<T, NSUB, EVAL, GDMI>(a, xcd_remap(blockIdx.x, a.nb_pad), a.stage, a.fuse2);
 }
 
 // Many grids in one launch: block b runs block work[b].y of grid work[b].x
@@ -489,7 +622,15 @@ template <typename T>
 void launch_field(const FieldArgs<T>& a, bool eval, hipStream_t st, Prof* prof) {
   ProfScope ps(prof, P_FIELD, st);
   const dim3 g(a.nb_pad), b(256);
-  if (a.nsub == 1) {
+  if (a.gdmi) {
+    if (a.nsub == 1) {
+      if (eval) hipLaunchKernelGGL((k_field<T, 1, true, true>), g, b, 0, st, a);
+      else hipLaunchKernelGGL((k_field<T, 1, false, true>), g, b, 0, st, a);
+    } else {
+      if (eval) hipLaunchKernelGGL((k_field<T, 2, true, true>), g, b, 0, st, a);
+      else hipLaunchKernelGGL((k_field<T, 2, false, true>), g, b, 0, st, a);
+    }
+  } else if (a.nsub == 1) {
     if (eval) hipLaunchKernelGGL((k_field<T, 1, true>), g, b, 0, st, a);
     else hipLaunchKernelGGL((k_field<T, 1, false>), g, b, 0, st, a);
   } else {

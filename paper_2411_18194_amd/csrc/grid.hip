@@ -569,6 +569,20 @@ struct Grid final : GridBase {
     a.nby = (ny + kTileY - 1) / kTileY;
     a.has_dmih = (p.nsub == 2 && (p.dmi_homo[0] != 0.0 || p.dmi_homo[1] != 0.0 ||
                                   p.dmi_homo[2] != 0.0)) ? 1 : 0;
+    a.gdmi = p.bc_eq6 ? 1 : 0;
+    a.eA12 = (T)(p.nsub == 2 ? p.A12 : 0.0);
+    for (int s = 0; s < 2; ++s) {
+      const bool on = s < p.nsub;
+      const double Ms = on ? p.sub[s].Ms : 0.0;
+      a.eA[s] = (T)(on ? p.sub[s].A11 : 0.0);
+      for (int i = 0; i < 3; ++i)
+        for (int c = 0; c < 3; ++c) {
+          a.eW[s][i][c] = (T)(on ? p.dmi_W[s][i][c] : 0.0);
+          a.cW[s][i][c] = (T)(on && Ms != 0.0 ? -2.0 * p.dmi_W[s][i][c] / Ms : 0.0);
+          a.cW12[s][i][c] =
+              (T)(on && Ms != 0.0 && p.nsub == 2 ? -2.0 * p.dmi_W12[i][c] / Ms : 0.0);
+        }
+    }
     a.per_x = p.pbc[0] > 0 ? 1 : 0;
     a.per_y = p.pbc[1] > 0 ? 1 : 0;
     fa = a;
@@ -1101,7 +1115,7 @@ struct Batch final : BatchBase {
     const auto* t = dynamic_cast<const Grid<T>*>(g);
     // one stage sequence serves every member: the Dormand-Prince pair
     return t && t->params_set && !t->p.demag && !t->p.elastic && t->p.nsub == nsub &&
-           t->p.solver == RK_DP45;
+           t->p.solver == RK_DP45 && !t->p.bc_eq6;
   }
   int size() const override { return (int)mem.size(); }
   int in_flight() const override { return count; }

@@ -58,7 +58,8 @@ class Params(C.Structure):
                 ("trac_amp", C.c_double), ("trac_freq", C.c_double), ("tol", C.c_double),
                 ("dt0", C.c_double), ("dt_min", C.c_double), ("solver", C.c_int32),
                 ("pbc", C.c_int32 * 3), ("rayleigh", C.c_double),
-                ("dmi_homo", C.c_double * 3)]
+                ("dmi_homo", C.c_double * 3), ("bc_eq6", C.c_int32), ("pad2", C.c_int32),
+                ("dmi_W", ((C.c_double * 3) * 3) * 2), ("dmi_W12", (C.c_double * 3) * 3)]
 
 
 class StepInfo(C.Structure):
@@ -222,6 +223,18 @@ def make_params(p: dict, precision=FP32, tol=1e-5, dt0=1e-14, dt_min=1e-20):
     P.solver = SOLVERS[p.get("solver", "dp45")]
     P.pbc[:] = [int(v) for v in p.get("pbc", (0, 0, 0))]
     P.dmi_homo[:] = [float(v) for v in p.get("dmi_homo", (0.0, 0.0, 0.0))]
+    P.bc_eq6 = 1 if p.get("bc", "open") == "eq6" else 0
+    if p.get("dmi_W") is not None:
+        W = np.asarray(p["dmi_W"], dtype=np.float64)
+        for s_ in range(W.shape[0]):
+            for i in range(3):
+                for c in range(3):
+                    P.dmi_W[s_][i][c] = float(W[s_, i, c])
+    if p.get("dmi_W12") is not None:
+        W = np.asarray(p["dmi_W12"], dtype=np.float64)
+        for i in range(3):
+            for c in range(3):
+                P.dmi_W12[i][c] = float(W[i, c])
     return P, keep
 
 
