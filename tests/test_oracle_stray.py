@@ -1,0 +1,56 @@
+"""Pins for the oracle's stray field above the magnet (not GPU).
+
+* The FFT path equals the plain double sum over target and source cells.
+* At a height dz/2 + k dz the layer sits on the grid's own lattice: the
+  field equals the demag field (oracle Demag, pinned on its own) of the grid
+  extended by k + 1 empty layers, in its top layer.
+* Far above one magnetised cell the field is the point dipole's,
+  mu0 Ms V (3 (m.r) r/r^5 - m/r^3)/(4 pi), to O((d/r)^2).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.constants import MU0
+from oracle.demag import Demag
+from oracle.stray import stray_direct, stray_field
+from paper_2411_18194_amd import inputs
+
+
+def test_fft_equals_direct_sum():
+    d = (2e-9, 3e-9, 1.5e-9)
+    M = inputs.rng(90).standard_normal((3, 2, 3, 4)) * 5e5
+    for h in (0.75e-9, 7e-9):
+        B1, B2 = stray_field(M, d, h), stray_direct(M, d, h)
+        assert np.abs(B1 - B2).max() <= 1e-13 * np.abs(B2).max()
+
+
+@pytest.mark.parametrize("k", [0, 2])
+def test_on_lattice_equals_demag(k):
+    n, d = (6, 5, 3), (2e-9, 2e-9, 3e-9)
+    M = inputs.rng(91).standard_normal((3, n[2], n[1], n[0])) * 4e5
+    B = stray_field(M, d, d[2] / 2 + k * d[2])
+    nz2 = n[2] + k + 1
+    Mx = np.zeros((3, nz2, n[1], n[0]))
+    Mx[:, :n[2]] = M
+    ref = Demag((n[0], n[1], nz2), d).field(Mx)[:, -1]
+    assert np.abs(B - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_dipole_far_field():
+    n, d = (5, 5, 1), (1e-9, 1e-9, 1e-9)
+    Ms = 8e5
+    mdir = np.array([0.3, -0.5, 0.8])
+    mdir /= np.linalg.norm(mdir)
+    M = np.zeros((3, 1, 5, 5))
+    M[:, 0, 2, 2] = Ms * mdir
+    h = 40e-9
+    B = stray_field(M, d, h)
+    zt = 0.5e-9 + h
+    for (yt, xt) in ((2, 2), (0, 4), (4, 1)):
+        r = np.array([(xt - 2) * d[0], (yt - 2) * d[1], zt])
+        rn = np.linalg.norm(r)
+        mom = Ms * d[0] * d[1] * d[2] * mdir
+        ref = MU0 / (4 * math.pi) * (3 * r * (mom @ r) / rn ** 5 - mom / rn ** 3)
+        assert np.abs(B[:, yt, xt] - ref).max() <= 2e-3 * np.abs(ref).max()
