@@ -255,6 +255,18 @@ mmp_status mmp_grid_bytes(mmp_grid g, int64_t* bytes);
  * (xx, yy, zz, xy, xz, yz)[z][y][x] (offset (x dx, y dy, z dz)). */
 mmp_status mmp_get_demag_tensor(mmp_grid g, double* n6);
 
+/* Stray field of the magnet's current state in a layer of cells of the
+ * grid's cell size whose centres lie `height` metres above the top surface
+ * (paper: the stray field imaged above a film, "Stray field imaging of the
+ * non-collinear antiferromagnet Mn3Sn"; the magnetostatic field of
+ * "Magnetostatic field", B = -mu0 sum_j N(r - r_j) M_j with the cell-pair
+ * tensor at the layer's vertical offsets).  b_out: 3*nx*ny doubles
+ * [comp][y][x], tesla, caller-owned.  MMP_E_ARG for height < dz/2 (the
+ * layer would overlap the magnet).  A direct FP64 sum over all cell pairs
+ * on the device (cost ~ (nx ny)^2 nz); allocates its tensor table
+ * (6 nz (2nx-1)(2ny-1) doubles) for the call.  Synchronous. */
+mmp_status mmp_stray_field(mmp_grid g, double height, double* b_out);
+
 /* ------------------------------------------------------------- plan -- */
 
 /* Launch plan of a grid.

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libmmp.so")
 ARCH = os.environ.get("MMP_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["abi.hip", "grid.hip", "field.hip", "demag.hip", "demag4.hip", "tensor.hip", "elastic.hip",
-           "server.hip"]
+           "server.hip", "stray.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -84,6 +84,11 @@ template <typename T>
 int demag_kernel_build(const DemagPlan& p, double dx, double dy, double dz, double* n6,
                        T* kout, hipStream_t st);
 
+// The tensor from every cell of the grid to a layer of cells centred at
+// height zt (layer 0 of the grid centred at 0): 6*nz*(2ny-1)*(2nx-1)
+// doubles [c][z][Y + ny - 1][X + nx - 1] (device).
+int stray_kernel_build(int nx, int ny, int nz, double dx, double dy, double dz, double zt,
+                       double* k6, hipStream_t st);
 int demag_tensor_only(int nx, int ny, int nz, double dx, double dy, double dz, double* n6,
                       hipStream_t st);
 

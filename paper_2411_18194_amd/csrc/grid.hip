@@ -8,6 +8,7 @@
 #include <tuple>
 
 #include "grid.h"
+#include "stray.h"
 
 namespace mmp {
 
@@ -1064,6 +1065,48 @@ struct Grid final : GridBase {
     if (rc || e != hipSuccess) { set_error("tensor build failed"); return MMP_E_HIP; }
     return 0;
   }
+  // stray field in the layer of cells centred `height` above the top
+  // surface (synchronous; host output [3][ny][nx])
+  int stray(double height, double* out) override {
+    if (int rc = ensure_ready()) return rc;
+    if (!(height >= 0.5 * d[2])) {
+      set_error("stray field: height must be >= dz/2 (the layer clears the magnet)");
+      return MMP_E_ARG;
+    }
+    const size_t nk = (size_t)6 * nz * (2 * ny - 1) * (2 * nx - 1);
+    const size_t no = (size_t)3 * nx * ny;
+    double *k6 = nullptr, *dout = nullptr;
+    MMP_HIP_TRY(hipStreamSynchronize(stream));
+    if (hipMalloc(&k6, nk * sizeof(double)) != hipSuccess) {
+      set_error("stray field: device allocation failed");
+      return MMP_E_NOMEM;
+    }
+    if (hipMalloc(&dout, no * sizeof(double)) != hipSuccess) {
+      (void)hipFree(k6);
+      set_error("stray field: device allocation failed");
+      return MMP_E_NOMEM;
+    }
+    Table<T> tb{};
+    hipError_t e = hipMemcpy(&tb, dtbl.p, sizeof(tb), hipMemcpyDeviceToHost);
+    const double zt = (nz - 0.5) * d[2] + height;
+    int rc = 0;
+    if (e == hipSuccess && stray_kernel_build(nx, ny, nz, d[0], d[1], d[2], zt, k6, stream)) rc = -1;
+    if (e == hipSuccess && !rc) {
+      launch_stray<T>(tb.yn, p.nsub, p.sub[0].Ms, p.nsub == 2 ? p.sub[1].Ms : 0.0, k6, nx, ny, nz,
+                      dout, stream);
+      e = hipGetLastError();
+      if (e == hipSuccess) e = hipStreamSynchronize(stream);
+      if (e == hipSuccess) e = hipMemcpy(out, dout, no * sizeof(double), hipMemcpyDeviceToHost);
+    }
+    (void)hipFree(k6);
+    (void)hipFree(dout);
+    if (e != hipSuccess || rc) {
+      set_error(std::string("stray field: ") + (rc ? "tensor build failed" : hipGetErrorString(e)));
+      return MMP_E_HIP;
+    }
+    return 0;
+  }
+
 };
 
 GridBase* make_grid(int precision) {

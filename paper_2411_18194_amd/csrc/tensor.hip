@@ -464,6 +464,36 @@ static int fill_tensor_images(int nx, int ny, int nz, double dx, double dy, doub
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// Tensor between the cells of a layer at height z_t (centre, layer 0 of the
+// grid centred at 0) and the grid's cells: k6[c][z][Y + ny - 1][X + nx - 1]
+// = N(X dx, Y dy, z_t - z dz) for |X| < nx, |Y| < ny.
+__global__ void k_tensor_layer(TensorArgs a, double zt, double* k6) {
+  const int wx = 2 * a.nx - 1, wy = 2 * a.ny - 1;
+  const long tot = (long)wx * wy * a.nz;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= tot) return;
+  const int ix = (int)(i % wx), iy = (int)((i / wx) % wy), z = (int)(i / ((long)wx * wy));
+  double o6[6];
+  tensor_at((ix - (a.nx - 1)) * a.dx, (iy - (a.ny - 1)) * a.dy, zt - z * a.dz, a, o6);
+  for (int c = 0; c < 6; ++c) k6[(long)c * tot + i] = o6[c];
+}
+
+int stray_kernel_build(int nx, int ny, int nz, double dx, double dy, double dz, double zt,
+                       double* k6, hipStream_t st) {
+  TensorArgs a{};
+  a.nx = nx; a.ny = ny; a.nz = nz;
+  a.dx = dx; a.dy = dy; a.dz = dz;
+  a.dmax = std::fmax(dx, std::fmax(dy, dz));
+  const double dmin = std::fmin(dx, std::fmin(dy, dz));
+  const int n = (a.dmax / dmin <= 1.25) ? 8 : 12;
+  a.nq = 2 * n;
+  triangle_rule(n, a.qt, a.qw);
+  const long tot = (long)(2 * nx - 1) * (2 * ny - 1) * nz;
+  hipLaunchKernelGGL(k_tensor_layer, dim3((unsigned)((tot + 63) / 64)), dim3(64), 0, st, a, zt,
+                     k6);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 template <typename T>
 int demag_kernel_build(const DemagPlan& p, double dx, double dy, double dz, double* n6, T* kout,
                        hipStream_t st) {

@@ -120,7 +120,7 @@ def _plan_dict(pl: Plan) -> dict:
 EXPORTS = ("mmp_grid_create", "mmp_grid_destroy", "mmp_set_params", "mmp_set_state",
            "mmp_get_state", "mmp_eval_heff", "mmp_step", "mmp_run_fixed", "mmp_run",
            "mmp_set_stream", "mmp_set_graphs", "mmp_synchronize", "mmp_grid_bytes", "mmp_get_demag_tensor",
-           "mmp_get_plan", "mmp_set_plan", "mmp_autotune", "mmp_prof_enable", "mmp_prof_count", "mmp_prof_read", "mmp_prof_reset",
+           "mmp_get_plan", "mmp_set_plan", "mmp_autotune", "mmp_stray_field", "mmp_prof_enable", "mmp_prof_count", "mmp_prof_read", "mmp_prof_reset",
            "mmp_server_create", "mmp_submit", "mmp_poll", "mmp_server_destroy",
            "mmp_server_clock", "mmp_last_error")
 
@@ -152,6 +152,7 @@ def load(path: str = LIB_PATH):
         "mmp_synchronize": ([vp], C.c_int32),
         "mmp_grid_bytes": ([vp, C.POINTER(C.c_int64)], C.c_int32),
         "mmp_get_demag_tensor": ([vp, dp], C.c_int32),
+        "mmp_stray_field": ([vp, C.c_double, dp], C.c_int32),
         "mmp_get_plan": ([vp, C.POINTER(Plan)], C.c_int32),
         "mmp_set_plan": ([vp, C.POINTER(Plan)], C.c_int32),
         "mmp_autotune": ([vp, C.POINTER(Plan)], C.c_int32),
@@ -346,6 +347,14 @@ class Grid:
         n6 = np.empty((6, nz, ny, nx))
         _check(self.lib.mmp_get_demag_tensor(self.h, _dptr(n6)))
         return n6
+
+    def stray_field(self, height):
+        """Stray field (3, ny, nx) in tesla in the layer of cells centred
+        `height` above the top surface."""
+        nx, ny, nz = self.n
+        b = np.empty((3, ny, nx))
+        _check(self.lib.mmp_stray_field(self.h, float(height), _dptr(b)))
+        return b
 
     def plan(self) -> dict:
         """The demag plan: pads and launch shapes (see mmp_plan)."""
