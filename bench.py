@@ -258,6 +258,10 @@ def _sequential_fp64(reqs, states):
             "requests": len(reqs), "service_s": [round(x, 3) for x in service]}
 
 
+def _progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def run_serve(count, max_active=8, baseline=0):
     """Relaxation requests (a seeded prefix of the 4000-request stream at
     200/s: 70 % FM with demag, 30 % two-sublattice AFM, 0.5 ns each) served
@@ -268,12 +272,15 @@ def run_serve(count, max_active=8, baseline=0):
     reqs = inputs.request_stream(seed=5, count=count)
     states = [inputs.request_state(r) for r in reqs]
     full = _serve_pass(reqs, states, mmp.FP32, 1.0, max_active)
+    _progress("serving: offered stream done")
     # arrivals at 0.8 x capacity: scale the stream's mean rate (200/s) down
     scale = 200.0 / (0.8 * full["solves_per_s"])
     sus = _serve_pass(reqs, states, mmp.FP32, scale, max_active)
+    _progress("serving: 0.8 x capacity done")
     base = None
     if baseline > 0:
         base = _sequential_fp64(reqs[:baseline], states[:baseline])
+        _progress("serving: sequential FP64 baseline done")
         # the same subsample through the server, for a like-for-like ratio
         sub = _serve_pass(reqs[:baseline], states[:baseline], mmp.FP32, 1.0, max_active)
         base["served_fp32_same_requests"] = {k: round(v, 4) if isinstance(v, float) else v
@@ -306,7 +313,8 @@ def _kernel_class(name):
             return cls
     if base.startswith(("k4_ffty<", "k_ffty<")):
         targs = [a.strip() for a in base.split("<", 1)[1].rstrip(">").split(",")]
-        inv = targs[-1] if base.startswith("k4_ffty<") else targs[1]   # <T, L1, L2, INV> / <T, INV, P2>
+        # <T, L1, L2, INV, FULL> / <T, INV, P2>
+        inv = targs[3] if base.startswith("k4_ffty<") else targs[1]
         return "ffty_inv" if inv == "true" else "ffty_fwd"
     return None
 
@@ -406,6 +414,7 @@ def main():
     from paper_2411_18194_amd import mmp
     tune = not args.no_autotune
     r32 = run_gpu(mmp.FP32, args.steps, args.warmup, prof=not args.no_prof, tune=tune)
+    _progress("FP32 film done")
     out = {
         "metric": METRIC, "value": round(r32["value"], 1), "unit": "cell-field-evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -425,6 +434,7 @@ def main():
         out["roofline"]["profiled_ms_per_step"] = round(r32["prof_ms_per_step"], 4)
     if not args.no_fp64:
         r64 = run_gpu(mmp.FP64, max(3, args.steps // 3), args.warmup, prof=False, tune=tune)
+        _progress("FP64 film done")
         out["fp64"] = {"value": round(r64["value"], 1), "unit": "cell-field-evals/s",
                        "ms_per_step": round(r64["ms_per_step"], 4),
                        "fp32_speedup": round(r32["value"] / r64["value"], 3),
@@ -433,6 +443,7 @@ def main():
         out["serving"] = run_serve(args.serve, baseline=min(args.serve_baseline, args.serve))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
+        _progress("CPU baseline done")
     print(json.dumps(out), flush=True)
 
 

@@ -24,6 +24,34 @@ template <typename T> using cpx = typename C2<T>::type;
 
 template <typename T>
 __device__ __forceinline__ cpx<T> cmk(T re, T im) { cpx<T> r; r.x = re; r.y = im; return r; }
+
+// Loads and stores of data that is read or written once per evaluation
+// (the spectra of the y and z passes, B_d): marked non-temporal, so they do
+// not displace from the caches what is read again soon (the kernel
+// spectrum, the stage state).  The values are unchanged.
+typedef float __attribute__((ext_vector_type(2))) nt_f2;
+typedef float __attribute__((ext_vector_type(4))) nt_f4;
+typedef double __attribute__((ext_vector_type(2))) nt_d2;
+__device__ __forceinline__ float2 ntload(const float2* p) {
+  const nt_f2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f2*>(p));
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ double2 ntload(const double2* p) {
+  const nt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float ntload(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ double ntload(const double* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void ntstore(float2* p, float2 v) {
+  nt_f2 w;
+  w.x = v.x; w.y = v.y;
+  __builtin_nontemporal_store(w, reinterpret_cast<nt_f2*>(p));
+}
+__device__ __forceinline__ void ntstore(double2* p, double2 v) {
+  nt_d2 w;
+  w.x = v.x; w.y = v.y;
+  __builtin_nontemporal_store(w, reinterpret_cast<nt_d2*>(p));
+}
 template <typename V>
 __device__ __forceinline__ V cadd(V a, V b) { V r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
 template <typename V>

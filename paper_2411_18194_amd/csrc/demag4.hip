@@ -69,7 +69,8 @@ __device__ __forceinline__ void fs_step3(cpx<T> (*u)[L2], const cpx<T>* line, in
   }
 }
 
-// two consecutive complex values as one 16-byte access where they fit
+// two consecutive complex values as one 16-byte access where they fit (the
+// load is the x inverse pass's single read of its spectrum: non-temporal)
 template <typename T>
 __device__ __forceinline__ void store2(cpx<T>* o, cpx<T> a, cpx<T> b) {
   if constexpr (sizeof(cpx<T>) == 8) {
@@ -84,12 +85,12 @@ __device__ __forceinline__ void store2(cpx<T>* o, cpx<T> a, cpx<T> b) {
 template <typename T>
 __device__ __forceinline__ void load2(const cpx<T>* i, cpx<T>& a, cpx<T>& b) {
   if constexpr (sizeof(cpx<T>) == 8) {
-    const float4 v = *reinterpret_cast<const float4*>(i);
+    const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(i));
     a = cmk<T>(v.x, v.y);
     b = cmk<T>(v.z, v.w);
   } else {
-    a = i[0];
-    b = i[1];
+    a = ntload(i);
+    b = ntload(i + 1);
   }
 }
 
@@ -116,7 +117,7 @@ __global__ __launch_bounds__(256) void k4_ffty(Y4Args<T> a) {
 #pragma unroll
   for (int n1 = 0; n1 < NLOAD; ++n1) {
     const int idx = L2 * n1 + t;
-    v[n1] = in[idx < a.nvalid_in ? idx : 0];
+    v[n1] = ntload(in + (idx < a.nvalid_in ? idx : 0));
   }
 #pragma unroll
   for (int n1 = 0; n1 < NLOAD; ++n1)
@@ -400,7 +401,7 @@ __device__ __forceinline__ void zcol_inverse_store(cpx<T>* v, cpx<T>* col, long 
   if constexpr (Q == 1) {
 #pragma unroll
     for (int z = 0; z < NH; ++z)
-      if (z < nz) col[z * zs] = t[bitrev<PZ>(z)];
+      if (z < nz) ntstore(col + z * zs, t[bitrev<PZ>(z)]);
   } else {
     V c[NH];
     static_for<0, NH>([&](auto nc) {
@@ -431,7 +432,7 @@ __device__ __forceinline__ void zcol_inverse_store(cpx<T>* v, cpx<T>* col, long 
     base += hi ? S / 2 : 0;
 #pragma unroll
     for (int i = 0; i < S / 2; ++i)
-      if (base + i < nz) col[(base + i) * zs] = c[i];
+      if (base + i < nz) ntstore(col + (base + i) * zs, c[i]);
   }
 }
 
@@ -467,9 +468,9 @@ __device__ __forceinline__ void fftz_mul_body(const Z4Args<T>& a) {
 #pragma unroll
   for (int n = 0; n < NH; ++n) {
     const bool in = n < a.nz;
-    lx[n] = in ? col[n * zs] : cmk<T>(0, 0);
-    ly[n] = in ? col[cs + n * zs] : cmk<T>(0, 0);
-    lz[n] = in ? col[2 * cs + n * zs] : cmk<T>(0, 0);
+    lx[n] = in ? ntload(col + n * zs) : cmk<T>(0, 0);
+    ly[n] = in ? ntload(col + cs + n * zs) : cmk<T>(0, 0);
+    lz[n] = in ? ntload(col + 2 * cs + n * zs) : cmk<T>(0, 0);
   }
   static_for<0, NH>([&](auto nc) {
     constexpr int n = decltype(nc)::value;

@@ -227,9 +227,9 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
         }
       T Bd[3] = {0, 0, 0};
       if (a.has_demag) {
-        Bd[0] = a.Bd[i];
-        Bd[1] = a.Bd[N + i];
-        Bd[2] = a.Bd[2 * N + i];
+        Bd[0] = ntload(a.Bd + i);
+        Bd[1] = ntload(a.Bd + N + i);
+        Bd[2] = ntload(a.Bd + 2 * N + i);
       }
       T ep[6] = {0, 0, 0, 0, 0, 0};
       if (a.has_mel) {
