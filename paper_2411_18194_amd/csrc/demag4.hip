@@ -133,7 +133,11 @@ __global__ __launch_bounds__(256) void k4_ffty(Y4Args<T> a) {
 #pragma unroll
       for (int k2 = 0; k2 < L2; ++k2) {
         const int k = t + L2 * i + L1 * k2;
-        if (k < a.nvalid_out) out[k] = u[i][bitrev<L2>(k2)];
+        if (k < a.nvalid_out) {
+          // the forward spectrum is read once, by the z pass
+          if (INV) out[k] = u[i][bitrev<L2>(k2)];
+          else ntstore(out + k, u[i][bitrev<L2>(k2)]);
+        }
       }
   }
 }
