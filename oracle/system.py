@@ -2,9 +2,12 @@
 
 For each magnet the paper integrates dm/dt = tau (Eq. 1), tau = LLG torque
 (Eq. 2) plus spin-transfer torque, with the effective field summed from the
-terms in ``fields``/``demag`` (Methods, "Micromagnetism").  A two-sublattice
-magnet couples its sublattices through Eq. 3 and shares one demagnetising
-field built from the summed moment.  With elasticity on, the displacement u
+terms in ``fields``/``demag`` (Methods, "Micromagnetism").  A magnet of two
+or three sublattices couples them through Eq. 3 (for three, every pair with
+the same A12 and A0: B^(s) gains sum over s' != s of A12/Ms lap m^(s') +
+4 A0/(Ms a^2) m^(s'), the paper's three exchange-coupled sublattices of the
+non-collinear Mn3Sn demonstration) and shares one demagnetising field built
+from the summed moment.  With elasticity on, the displacement u
 and velocity v join the state (Eq. 7) and the strain feeds Eq. 9 back.
 
 Energies (joules, FP64) follow one rule for every term bilinear in m:
@@ -36,8 +39,12 @@ class Problem:
         self.d = tuple(p["cell"])
         self.nsub = p["nsub"]
         self.V = self.d[0] * self.d[1] * self.d[2]
-        if p["nsub"] == 2 and any(v != 0.0 for v in p["Dint"]):
+        if p["nsub"] >= 2 and any(v != 0.0 for v in p["Dint"]):
             raise ValueError("interfacial DMI is implemented for one sublattice")
+        if p["nsub"] == 3 and (p.get("bc", "open") == "eq6" or p["elastic"] is not None
+                               or any(p.get("dmi_homo", (0, 0, 0)))):
+            raise ValueError("three sublattices: open boundaries, no elasticity, no "
+                             "homogeneous DMI")
         # periodic boundaries: image repetitions per axis (0 = open)
         self.pbc = tuple(int(v) for v in p.get("pbc", (0, 0, 0)))
         if any(v < 0 for v in self.pbc) or self.pbc[2] != 0:
@@ -71,7 +78,9 @@ class Problem:
         p, d = self.p, self.d
         ms = m[s]
         Ms = p["Ms"][s]
-        other = m[1 - s] if self.nsub == 2 else None
+        # the other sublattices (Eq. 3 with one A12 and one A0 for every pair)
+        others = [m[o] for o in range(self.nsub) if o != s]
+        other = others[0] if self.nsub == 2 else None
         if name == "demag":
             if self.demag is None:
                 return np.zeros_like(ms)
@@ -84,13 +93,15 @@ class Problem:
             return fl.exchange_field(ms, Ms, p["A11"][s], d, p["Dint"][s],
                                      p["dmi_layer"], self.periodic)
         if name == "afm_nn":
-            if other is None:
-                return np.zeros_like(ms)
-            return fl.afm_nn_field(other, Ms, p["A12"], d, self.periodic)
+            B = np.zeros_like(ms)
+            for mo in others:
+                B = B + fl.afm_nn_field(mo, Ms, p["A12"], d, self.periodic)
+            return B
         if name == "afm_cell":
-            if other is None:
-                return np.zeros_like(ms)
-            return fl.afm_cell_field(other, Ms, p["A0"], p["latcon"])
+            B = np.zeros_like(ms)
+            for mo in others:
+                B = B + fl.afm_cell_field(mo, Ms, p["A0"], p["latcon"])
+            return B
         if name == "dmi":
             B = fl.dmi_field(ms, Ms, p["A11"][s], p["Dint"][s], d,
                              p["dmi_layer"], self.periodic)

@@ -13,7 +13,7 @@ Problem description (a plain ``dict``, SI units throughout):
 
 ``n``          (nx, ny, nz) cell counts
 ``cell``       (dx, dy, dz) cell size in metres
-``nsub``       1 (ferromagnet) or 2 (two-sublattice antiferro/ferrimagnet)
+``nsub``       1 (ferromagnet), 2 (two-sublattice antiferro/ferrimagnet) or 3
 ``gamma``      gyromagnetic ratio, rad/(s T)
 per-sublattice lists (length ``nsub``):
   ``Ms`` (A/m), ``A11`` (J/m), ``alpha``, ``Ku1``/``Ku2`` (J/m^3),

@@ -191,3 +191,52 @@ def test_homogeneous_dmi():
     assert np.allclose(B[0, 0], -D / 4e5, rtol=1e-15) and np.allclose(B[0, 1:], 0)
     assert np.allclose(B[1, 1], -D / 3e5, rtol=1e-15) and np.allclose(B[1, [0, 2]], 0)
     assert P.energies(m)["dmi"] == pytest.approx(D * P.V * 24, rel=1e-14)
+
+
+def _three(n=(5, 4, 2), d=(2e-9, 3e-9, 1.5e-9)):
+    p = inputs.base_params(n, d, nsub=3)
+    p.update(Ms=[4e5, 3e5, 3.5e5], A11=[1e-11, 8e-12, 9e-12], A12=-4e-12, A0=-2e-11,
+             latcon=0.4e-9)
+    return p
+
+
+def test_three_sublattices_energy_gradient():
+    """Eq. 3 with every pair of three sublattices coupled: the energy
+    gradient is the field for both inter-sublattice terms."""
+    p = _three()
+    m = inputs.random_unit(inputs.rng(8), 3, p["n"])
+    _energy_gradient_check(p, m, ("afm_nn",))
+    _energy_gradient_check(p, m, ("afm_cell",))
+
+
+def test_three_sublattices_reduce_to_two():
+    """With m3 = m2 the first sublattice feels twice the coupling of a
+    two-sublattice magnet with the same A12 and A0."""
+    p3 = _three()
+    m = inputs.random_unit(inputs.rng(9), 3, p3["n"])
+    m[2] = m[1]
+    p2 = dict(p3, nsub=2, Ms=p3["Ms"][:2], A11=p3["A11"][:2])
+    for k in ("alpha", "Ku1", "Ku2", "anis_u", "Kc1", "cub_c1", "cub_c2", "Dint", "B1", "B2",
+              "zl_P", "zl_xi"):
+        p2[k] = p3[k][:2]
+    b3 = Problem(p3).eval_heff(m, ("afm_nn", "afm_cell"))
+    b2 = Problem(p2).eval_heff(m[:2], ("afm_nn", "afm_cell"))
+    assert np.allclose(b3[0], 2 * b2[0], rtol=1e-13, atol=0)
+
+
+def test_three_sublattice_triangular_state_torque_free():
+    """The 120 degree state of three equal sublattices (sum m = 0): the
+    homogeneous exchange field of each is antiparallel to its own m, so the
+    exchange leaves no torque (the non-collinear ground state)."""
+    p = _three((3, 3, 1))
+    p.update(Ms=[4e5] * 3, A11=[1e-11] * 3, alpha=[0.01] * 3)
+    m = np.zeros((3, 3, 1, 3, 3))
+    for s in range(3):
+        ang = 2 * math.pi * s / 3
+        m[s, 0] = math.cos(ang)
+        m[s, 1] = math.sin(ang)
+    P = Problem(p)
+    B = P.eval_heff(m, ("afm_cell",))
+    for s in range(3):
+        assert np.allclose(np.cross(m[s], B[s], axis=0), 0, atol=1e-9 * np.abs(B).max())
+    assert np.abs(P.torque(m)).max() < 1e-9 * P.p["gamma"] * np.abs(B).max()
