@@ -105,10 +105,14 @@ typedef struct {
 typedef struct {
   uint32_t struct_size;   /* sizeof(mmp_params)                           */
   int32_t precision;      /* MMP_FP32 or MMP_FP64                          */
-  int32_t nsub;           /* 1 (ferromagnet) or 2 (two sublattices)        */
+  int32_t nsub;           /* 1 (ferromagnet), 2 (two sublattices) or 3
+                             (three, e.g. a non-collinear antiferromagnet:
+                             every pair coupled by the same A12 and A0;
+                             open boundaries, no elasticity, no
+                             homogeneous DMI)                              */
   int32_t demag;          /* nonzero: magnetostatic field on               */
   double gamma;           /* gyromagnetic ratio, rad/(s T)                 */
-  mmp_sublattice sub[2];
+  mmp_sublattice sub[3];  /* sub[2] only for three sublattices           */
   double A0;              /* homogeneous inter-sublattice exchange, J/m    */
   double A12;             /* inhomogeneous inter-sublattice exchange, J/m  */
   double latcon;          /* lattice constant a, m                         */
@@ -362,7 +366,7 @@ typedef struct {
 typedef struct {
   int32_t status;         /* MMP_OK or an error code                       */
   int32_t nsub;
-  double m_avg[2][3];     /* average m per sublattice at t_relax           */
+  double m_avg[3][3];     /* average m per sublattice at t_relax           */
   double energy;          /* total energy, J                               */
   int64_t steps, rejects;
   double t_submit, t_admit, t_done;  /* seconds on the server's clock      */

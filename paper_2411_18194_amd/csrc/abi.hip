@@ -134,7 +134,12 @@ mmp_status mmp_set_params(mmp_grid g, const mmp_params* p) {
   if (!g || !p) { set_error("null argument"); return MMP_E_ARG; }
   if (p->struct_size != sizeof(mmp_params)) { set_error("mmp_params struct_size mismatch"); return MMP_E_ARG; }
   if (p->precision != MMP_FP32 && p->precision != MMP_FP64) { set_error("bad precision"); return MMP_E_ARG; }
-  if (p->nsub != 1 && p->nsub != 2) { set_error("nsub must be 1 or 2"); return MMP_E_ARG; }
+  if (p->nsub < 1 || p->nsub > 3) { set_error("nsub must be 1, 2 or 3"); return MMP_E_ARG; }
+  if (p->nsub == 3 && (p->elastic || p->bc_eq6 || p->dmi_homo[0] != 0.0 ||
+                       p->dmi_homo[1] != 0.0 || p->dmi_homo[2] != 0.0)) {
+    set_error("three sublattices: open boundaries, no elasticity, no homogeneous DMI");
+    return MMP_E_ARG;
+  }
   if (p->solver < 0 || p->solver >= RK_COUNT) { set_error("unknown solver"); return MMP_E_ARG; }
   if (p->pbc[0] < 0 || p->pbc[1] < 0 || p->pbc[0] > 1024 || p->pbc[1] > 1024 || p->pbc[2] != 0) {
     set_error("pbc: repetitions 0..1024 along x and y, 0 along z");
@@ -161,7 +166,7 @@ mmp_status mmp_set_params(mmp_grid g, const mmp_params* p) {
       set_error("DMI tensors need the Eq. 6 boundary condition (bc_eq6 = 1)");
       return MMP_E_ARG;
     }
-    if (p->bc_eq6 && (p->sub[0].Dint != 0.0 || (p->nsub == 2 && p->sub[1].Dint != 0.0))) {
+    if (p->bc_eq6 && (p->sub[0].Dint != 0.0 || (p->nsub >= 2 && p->sub[1].Dint != 0.0))) {
       set_error("with bc_eq6 give the interfacial DMI as a tensor");
       return MMP_E_ARG;
     }

@@ -60,22 +60,25 @@ struct DemagBufs {
 };
 
 // B_d for the stage input of `stage` (see stage_in) or, with stage == 0, for
-// the array `src` directly.  M = Ms0 m0 + Ms1 m1.
+// the array `src` directly.  M = Ms0 m0 + Ms1 m1 (+ Ms2 m2 for three
+// sublattices).
 template <typename T>
 void demag_field(const DemagPlan& p, const DemagBufs<T>& b, const Table<T>* tbl, int stage,
-                 const Ctrl* ctrl, T ms0, T ms1, int nsub, hipStream_t st, Prof* prof);
+                 const Ctrl* ctrl, T ms0, T ms1, int nsub, hipStream_t st, Prof* prof,
+                 T ms2 = T(0));
 
 // One pass of demag_field on its own (the autotuner times them one by one).
 template <typename T>
 void demag_pass(int pass, const DemagPlan& p, const DemagBufs<T>& b, const Table<T>* tbl,
-                int stage, const Ctrl* ctrl, T ms0, T ms1, int nsub, hipStream_t st);
+                int stage, const Ctrl* ctrl, T ms0, T ms1, int nsub, hipStream_t st,
+                T ms2 = T(0));
 
 // Times the candidate launch shapes of every pass for the pads of *p on the
 // buffers b and keeps the fastest in *p.  Returns the time of one demag
 // evaluation with the chosen shapes in ms (< 0 on a HIP error).
 template <typename T>
 double demag_tune(DemagPlan* p, const DemagBufs<T>& b, const Table<T>* tbl, T ms0, T ms1,
-                  int nsub, hipStream_t st);
+                  int nsub, hipStream_t st, T ms2 = T(0));
 
 // FP64 tensor on the non-negative offsets and its transformed octant
 // spectrum.  n6 (6*N doubles, device) receives the tensor; kout the scaled

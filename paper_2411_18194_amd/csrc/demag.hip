@@ -41,7 +41,7 @@ struct XArgs {
   const Table<T>* tbl;
   const Ctrl* ctrl;
   int stage;
-  T ms0, ms1;
+  T ms0, ms1, ms2;
   int nsub;
   cpx<T>* S1;
   T* Bd;
@@ -70,11 +70,13 @@ __global__ void k_fftx_fwd(XArgs<T> a) {
     if (x < a.nx) {
       if (ya < a.ny) {
         re = a.ms0 * m0[(long)ya * a.nx + x];
-        if (a.nsub == 2) re += a.ms1 * m1[(long)ya * a.nx + x];
+        if (a.nsub >= 2) re += a.ms1 * m1[(long)ya * a.nx + x];
+        if (a.nsub == 3) re += a.ms2 * m1[3 * N + (long)ya * a.nx + x];
       }
       if (yb < a.ny) {
         im = a.ms0 * m0[(long)yb * a.nx + x];
-        if (a.nsub == 2) im += a.ms1 * m1[(long)yb * a.nx + x];
+        if (a.nsub >= 2) im += a.ms1 * m1[(long)yb * a.nx + x];
+        if (a.nsub == 3) im += a.ms2 * m1[3 * N + (long)yb * a.nx + x];
       }
     }
     buf[q * a.Px + x] = cmk<T>(re, im);
@@ -445,7 +447,7 @@ int demag_plan(int nx, int ny, int nz, int real_bytes, const int* pads, DemagPla
 // --------------------------------------------------------------- passes --
 template <typename T>
 void demag_pass(int pass, const DemagPlan& p, const DemagBufs<T>& b, const Table<T>* tbl,
-                int stage, const Ctrl* ctrl, T ms0, T ms1, int nsub, hipStream_t st) {
+                int stage, const Ctrl* ctrl, T ms0, T ms1, int nsub, hipStream_t st, T ms2) {
   using V = cpx<T>;
   switch (pass) {
     case DP_XF:
@@ -457,6 +459,7 @@ void demag_pass(int pass, const DemagPlan& p, const DemagBufs<T>& b, const Table
       if (p.p2x) {
         X4Args<T> a;
         a.tbl = tbl; a.ctrl = ctrl; a.stage = stage; a.ms0 = ms0; a.ms1 = ms1; a.nsub = nsub;
+        a.ms2 = ms2;
         a.S1 = b.S1; a.Bd = b.Bd; a.tw4 = b.tw4x;
         a.nx = p.nx; a.ny = p.ny; a.nz = p.nz; a.Hx = p.Hx; a.ldy = p.ldy; a.ty = ty;
         a.lnl = 0;
@@ -465,6 +468,7 @@ void demag_pass(int pass, const DemagPlan& p, const DemagBufs<T>& b, const Table
       } else {
         XArgs<T> a;
         a.tbl = tbl; a.ctrl = ctrl; a.stage = stage; a.ms0 = ms0; a.ms1 = ms1; a.nsub = nsub;
+        a.ms2 = ms2;
         a.S1 = b.S1; a.Bd = b.Bd; a.tw = b.twx;
         a.nx = p.nx; a.ny = p.ny; a.nz = p.nz; a.Px = p.Px; a.Hx = p.Hx; a.ldy = p.ldy;
         a.ty = ty; a.rad = p.rx;
@@ -563,12 +567,12 @@ static int demag_passes(const DemagPlan& p, int* out) {
 // --------------------------------------------------------------- driver --
 template <typename T>
 void demag_field(const DemagPlan& p, const DemagBufs<T>& b, const Table<T>* tbl, int stage,
-                 const Ctrl* ctrl, T ms0, T ms1, int nsub, hipStream_t st, Prof* prof) {
+                 const Ctrl* ctrl, T ms0, T ms1, int nsub, hipStream_t st, Prof* prof, T ms2) {
   int passes[DP_COUNT];
   const int n = demag_passes(p, passes);
   for (int i = 0; i < n; ++i) {
     ProfScope ps(prof, kPassProf[passes[i]], st);
-    demag_pass<T>(passes[i], p, b, tbl, stage, ctrl, ms0, ms1, nsub, st);
+    demag_pass<T>(passes[i], p, b, tbl, stage, ctrl, ms0, ms1, nsub, st, ms2);
   }
 }
 
@@ -577,7 +581,7 @@ void demag_field(const DemagPlan& p, const DemagBufs<T>& b, const Table<T>* tbl,
 // one warm-up launch; a failed launch reads as infinitely slow.
 template <typename T>
 static double time_pass(int pass, const DemagPlan& p, const DemagBufs<T>& b, const Table<T>* tbl,
-                        T ms0, T ms1, int nsub, hipStream_t st, int reps) {
+                        T ms0, T ms1, int nsub, hipStream_t st, int reps, T ms2) {
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return -1.0;
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -585,9 +589,10 @@ static double time_pass(int pass, const DemagPlan& p, const DemagBufs<T>& b, con
     return -1.0;
   }
   double ms = -1.0;
-  demag_pass<T>(pass, p, b, tbl, 1, nullptr, ms0, ms1, nsub, st);
+  demag_pass<T>(pass, p, b, tbl, 1, nullptr, ms0, ms1, nsub, st, ms2);
   if (hipGetLastError() == hipSuccess && hipEventRecord(e0, st) == hipSuccess) {
-    for (int r = 0; r < reps; ++r) demag_pass<T>(pass, p, b, tbl, 1, nullptr, ms0, ms1, nsub, st);
+    for (int r = 0; r < reps; ++r)
+      demag_pass<T>(pass, p, b, tbl, 1, nullptr, ms0, ms1, nsub, st, ms2);
     float f = 0.f;
     if (hipGetLastError() == hipSuccess && hipEventRecord(e1, st) == hipSuccess &&
         hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&f, e0, e1) == hipSuccess)
@@ -600,7 +605,7 @@ static double time_pass(int pass, const DemagPlan& p, const DemagBufs<T>& b, con
 
 template <typename T>
 double demag_tune(DemagPlan* pp, const DemagBufs<T>& b, const Table<T>* tbl, T ms0, T ms1,
-                  int nsub, hipStream_t st) {
+                  int nsub, hipStream_t st, T ms2) {
   constexpr int rb = (int)sizeof(T);
   DemagPlan best = *pp;
   int passes[DP_COUNT];
@@ -659,7 +664,7 @@ double demag_tune(DemagPlan* pp, const DemagBufs<T>& b, const Table<T>* tbl, T m
     }
     double bt = -1.0;
     for (const DemagPlan& c : cand) {
-      const double t = time_pass<T>(pass, c, b, tbl, ms0, ms1, nsub, st, reps);
+      const double t = time_pass<T>(pass, c, b, tbl, ms0, ms1, nsub, st, reps, ms2);
       if (t < 0.0) continue;
       if (bt < 0.0 || t < bt) {
         bt = t;
@@ -675,11 +680,11 @@ double demag_tune(DemagPlan* pp, const DemagBufs<T>& b, const Table<T>* tbl, T m
 
 #define INST(T)                                                                                 \
   template void demag_field<T>(const DemagPlan&, const DemagBufs<T>&, const Table<T>*, int,      \
-                               const Ctrl*, T, T, int, hipStream_t, Prof*);                     \
+                               const Ctrl*, T, T, int, hipStream_t, Prof*, T);                  \
   template void demag_pass<T>(int, const DemagPlan&, const DemagBufs<T>&, const Table<T>*, int,  \
-                              const Ctrl*, T, T, int, hipStream_t);                             \
+                              const Ctrl*, T, T, int, hipStream_t, T);                          \
   template double demag_tune<T>(DemagPlan*, const DemagBufs<T>&, const Table<T>*, T, T, int,    \
-                                hipStream_t);
+                                hipStream_t, T);
 INST(float)
 INST(double)
 #undef INST

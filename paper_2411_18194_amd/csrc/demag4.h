@@ -11,7 +11,7 @@ struct X4Args {
   const Table<T>* tbl;
   const Ctrl* ctrl;
   int stage;
-  T ms0, ms1;
+  T ms0, ms1, ms2;
   int nsub;
   cpx<T>* S1;
   T* Bd;

@@ -173,13 +173,23 @@ __global__ __launch_bounds__(256) void k4_fftx_fwd(X4Args<T> a) {
     xa[n1] = a.ms0 * m0[ra + xc];
     xb[n1] = a.ms0 * m0[rb + xc];
   }
-  if (a.nsub == 2) {
+  if (a.nsub >= 2) {
 #pragma unroll
     for (int n1 = 0; n1 < NLOAD; ++n1) {
       const int x = L2 * n1 + t;
       const int xc = x < a.nx ? x : 0;
       xa[n1] += a.ms1 * m1[ra + xc];
       xb[n1] += a.ms1 * m1[rb + xc];
+    }
+  }
+  if (a.nsub == 3) {
+    const T* m2 = m1 + 3 * N;
+#pragma unroll
+    for (int n1 = 0; n1 < NLOAD; ++n1) {
+      const int x = L2 * n1 + t;
+      const int xc = x < a.nx ? x : 0;
+      xa[n1] += a.ms2 * m2[ra + xc];
+      xb[n1] += a.ms2 * m2[rb + xc];
     }
   }
 #pragma unroll

@@ -30,7 +30,7 @@ struct FieldArgs {
   int nx, ny, nz, nsub;
   long N;
   T dx, dy, dz, idx2, idy2, idz2, i2dx, i2dy, i2dz;
-  SubC<T> sc[2];
+  SubC<T> sc[3];
   T bext[3];
   int dmi_layer;
   int has_demag, has_dmi, has_anis_u, has_anis_c, has_mel;

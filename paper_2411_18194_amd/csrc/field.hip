@@ -346,21 +346,33 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
           add(4, acc);
           if (EVAL) eacc[4] += -0.5 * C.Ms_d * dot3d(mm, acc);
         }
-        // two-sublattice exchange
-        if (NSUB == 2) {
-          const int o = 1 - s;
+        // inter-sublattice exchange (Eq. 3) with every other sublattice:
+        // A12/Ms lap m' (inhomogeneous) and 4 A0/(Ms a^2) m' (homogeneous)
+        if (NSUB >= 2) {
 #pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const T mo = cur[o][c];
-            const T l = ((sxm[o][c] - mo) + (sxp[o][c] - mo)) * a.idx2 +
-                        ((sym[o][c] - mo) + (syp[o][c] - mo)) * a.idy2 +
-                        ((szm[o][c] - mo) + (szp[o][c] - mo)) * a.idz2;
-            bt[c] = C.cnn * l;
+          for (int c = 0; c < 3; ++c) bt[c] = T(0);
+#pragma unroll
+          for (int o = 0; o < NSUB; ++o) {
+            if (o == s) continue;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              const T mo = cur[o][c];
+              const T l = ((sxm[o][c] - mo) + (sxp[o][c] - mo)) * a.idx2 +
+                          ((sym[o][c] - mo) + (syp[o][c] - mo)) * a.idy2 +
+                          ((szm[o][c] - mo) + (szp[o][c] - mo)) * a.idz2;
+              bt[c] += C.cnn * l;
+            }
           }
           add(2, bt);
           if (EVAL) eacc[2] += -0.5 * C.Ms_d * dot3d(mm, bt);
 #pragma unroll
-          for (int c = 0; c < 3; ++c) bt[c] = C.ccell * cur[o][c];
+          for (int c = 0; c < 3; ++c) {
+            T so = T(0);
+#pragma unroll
+            for (int o = 0; o < NSUB; ++o)
+              if (o != s) so += cur[o][c];
+            bt[c] = C.ccell * so;
+          }
           // The homogeneous inter-sublattice field is ~1000x larger than the
           // torque it leaves when m' ~ -m, so its torque is formed from an
           // accurate m x m' (tau is linear in B) instead of from B.
@@ -372,8 +384,8 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
           }
           if (EVAL) eacc[3] += -0.5 * C.Ms_d * dot3d(mm, bt);
           // homogeneous DMI d.(m1 x m2): B = m' x dh, dh = -/+ d/Ms
-          if (a.has_dmih) {
-            cross3(cur[o], C.dh, bt);
+          if (NSUB == 2 && a.has_dmih) {
+            cross3(cur[1 - s], C.dh, bt);
             add(4, bt);
             if (EVAL) eacc[4] += -0.5 * C.Ms_d * dot3d(mm, bt);
           }
@@ -434,9 +446,15 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
         cross3(mm, mxB, mxmxB);
 #pragma unroll
         for (int c = 0; c < 3; ++c) tau[c] = -C.gl * (mxB[c] + C.alpha * mxmxB[c]);
-        if (NSUB == 2 && a0_on) {
-          T w[3], mxw[3];
-          cross3_acc(mm, cur[1 - s], w);
+        if (NSUB >= 2 && a0_on) {
+          T w[3] = {0, 0, 0}, mxw[3];
+#pragma unroll
+          for (int o = 0; o < NSUB; ++o) {
+            if (o == s) continue;
+            T wo[3];
+            cross3_acc(mm, cur[o], wo);
+            w[0] += wo[0]; w[1] += wo[1]; w[2] += wo[2];
+          }
           cross3(mm, w, mxw);
 #pragma unroll
           for (int c = 0; c < 3; ++c) tau[c] -= C.gl * C.ccell * (w[c] + C.alpha * mxw[c]);
@@ -633,9 +651,12 @@ void launch_field(const FieldArgs<T>& a, bool eval, hipStream_t st, Prof* prof) 
   } else if (a.nsub == 1) {
     if (eval) hipLaunchKernelGGL((k_field<T, 1, true>), g, b, 0, st, a);
     else hipLaunchKernelGGL((k_field<T, 1, false>), g, b, 0, st, a);
-  } else {
+  } else if (a.nsub == 2) {
     if (eval) hipLaunchKernelGGL((k_field<T, 2, true>), g, b, 0, st, a);
     else hipLaunchKernelGGL((k_field<T, 2, false>), g, b, 0, st, a);
+  } else {
+    if (eval) hipLaunchKernelGGL((k_field<T, 3, true>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((k_field<T, 3, false>), g, b, 0, st, a);
   }
 }
 
@@ -786,20 +807,20 @@ void launch_control(Ctrl* ctrl, Table<T>* tbl, const double* errpart, int nerr, 
 template <typename T>
 __global__ void k_sample_part(const Ctrl* c, const Table<T>* tbl, int nsub, long N, double* part) {
   if (!c->sample_pending) return;
-  __shared__ double red[6][256];
-  double acc[6] = {0, 0, 0, 0, 0, 0};
+  __shared__ double red[9][256];
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   const T* y = tbl->yn;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x)
     for (int s = 0; s < nsub; ++s)
       for (int q = 0; q < 3; ++q) acc[s * 3 + q] += (double)y[(s * 3 + q) * N + i];
-  for (int q = 0; q < 6; ++q) red[q][threadIdx.x] = acc[q];
+  for (int q = 0; q < 9; ++q) red[q][threadIdx.x] = acc[q];
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
     if ((int)threadIdx.x < st)
-      for (int q = 0; q < 6; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + st];
+      for (int q = 0; q < 9; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + st];
     __syncthreads();
   }
-  if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
+  if (threadIdx.x < 9) part[blockIdx.x * 9 + threadIdx.x] = red[threadIdx.x][0];
 }
 
 __global__ void k_sample_final(Ctrl* c, const double* part, int nblk, long N, int nsub,
@@ -811,7 +832,7 @@ __global__ void k_sample_final(Ctrl* c, const double* part, int nblk, long N, in
     sample_t[k] = c->t;
     for (int q = 0; q < 3 * nsub; ++q) {
       double acc = 0.0;
-      for (int b = 0; b < nblk; ++b) acc += part[b * 6 + q];
+      for (int b = 0; b < nblk; ++b) acc += part[b * 9 + q];
       sample_m[k * 3 * nsub + q] = acc / (double)N;
     }
   }

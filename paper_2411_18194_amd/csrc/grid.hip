@@ -136,7 +136,7 @@ struct Grid final : GridBase {
     rc |= epart.alloc((size_t)nb_max * kNE);
     rc |= eout.alloc(kNE);
     nsamp_blk = (int)std::min<long>(256, (N + 255) / 256);
-    rc |= spart.alloc((size_t)nsamp_blk * 6);
+    rc |= spart.alloc((size_t)nsamp_blk * 9);
     rc |= elpart.alloc((N + 255) / 256);
     rc |= dtbl.alloc(1);
     rc |= dctrl.alloc(1);
@@ -455,7 +455,7 @@ struct Grid final : GridBase {
     // a periodic axis has the one cyclic length n
     if (p.pbc[0] > 0) { cx[0] = nx; nxc = 1; }
     if (p.pbc[1] > 0) { cy[0] = ny; nyc = 1; }
-    const T ms0 = (T)p.sub[0].Ms, ms1 = (T)(p.nsub == 2 ? p.sub[1].Ms : 0.0);
+    const T ms0 = (T)p.sub[0].Ms, ms1 = ms_of(1), ms2 = ms_of(2);
     MMP_HIP_TRY(hipStreamSynchronize(stream));
     DemagPlan best{};
     double best_ms = -1.0;
@@ -484,7 +484,7 @@ struct Grid final : GridBase {
             MMP_HIP_TRY(hipMemsetAsync(kb.p, 0, c.k_elems * sizeof(T), stream));
             build_all_twiddles(tb, c);
           }
-          const double ms = demag_tune<T>(&c, tb, dtbl.p, ms0, ms1, p.nsub, stream);
+          const double ms = demag_tune<T>(&c, tb, dtbl.p, ms0, ms1, p.nsub, stream, ms2);
           const hipError_t e = hipStreamSynchronize(stream);
           s1.release(); s2.release(); kb.release(); twb.release();
           if (e != hipSuccess) {
@@ -507,9 +507,12 @@ struct Grid final : GridBase {
     return 0;
   }
 
+  // Ms of sublattice s, 0 past the grid's sublattices
+  T ms_of(int s) const { return (T)(s < p.nsub ? p.sub[s].Ms : 0.0); }
+
   int apply_params() override {
-    if (p.nsub == 2)
-      for (int s = 0; s < 2; ++s)
+    if (p.nsub >= 2)
+      for (int s = 0; s < p.nsub; ++s)
         if (p.sub[s].Dint != 0.0) {
           set_error("interfacial DMI is implemented for one sublattice");
           return MMP_E_ARG;
@@ -682,8 +685,8 @@ struct Grid final : GridBase {
       launch_strain(e, stream, &prof);
     }
     if (p.demag)
-      demag_field<T>(plan, db, dtbl.p, s, dctrl.p, (T)p.sub[0].Ms,
-                     (T)(p.nsub == 2 ? p.sub[1].Ms : 0.0), p.nsub, stream, &prof);
+      demag_field<T>(plan, db, dtbl.p, s, dctrl.p, (T)p.sub[0].Ms, ms_of(1), p.nsub, stream,
+                     &prof, ms_of(2));
     FieldArgs<T> a = fa;
     a.stage = s;
     a.fuse2 = fuse2 ? 1 : 0;
@@ -880,7 +883,7 @@ struct Grid final : GridBase {
     if (every > 0.0 && cap > samp_cap) {
       drop_graphs();
       samp_t.release(); samp_m.release();
-      if (samp_t.alloc(cap) || samp_m.alloc((size_t)cap * 6)) {
+      if (samp_t.alloc(cap) || samp_m.alloc((size_t)cap * 9)) {
         set_error("device allocation failed");
         return MMP_E_NOMEM;
       }
@@ -918,9 +921,9 @@ struct Grid final : GridBase {
     }
     if (sampling && o && c.nsamples > 0) {
       const int ns = std::min(c.nsamples, samp_cap);
-      std::vector<double> tt(ns), mm((size_t)ns * 6);
+      std::vector<double> tt(ns), mm((size_t)ns * 9);
       MMP_HIP_TRY(hipMemcpy(tt.data(), samp_t.p, ns * sizeof(double), hipMemcpyDeviceToHost));
-      MMP_HIP_TRY(hipMemcpy(mm.data(), samp_m.p, ns * 6 * sizeof(double), hipMemcpyDeviceToHost));
+      MMP_HIP_TRY(hipMemcpy(mm.data(), samp_m.p, ns * 9 * sizeof(double), hipMemcpyDeviceToHost));
       for (int i = 0; i < ns; ++i) {
         if (o->sample_t) o->sample_t[i] = tt[i];
         if (o->sample_m)
@@ -947,8 +950,8 @@ struct Grid final : GridBase {
       launch_strain(ee, stream, &prof);
     }
     if (p.demag)
-      demag_field<T>(plan, db, dtbl.p, 1, nullptr, (T)p.sub[0].Ms,
-                     (T)(p.nsub == 2 ? p.sub[1].Ms : 0.0), p.nsub, stream, &prof);
+      demag_field<T>(plan, db, dtbl.p, 1, nullptr, (T)p.sub[0].Ms, ms_of(1), p.nsub, stream,
+                     &prof, ms_of(2));
     FieldArgs<T> a = fa;
     a.ctrl = nullptr;
     a.stage = 1;
@@ -1092,8 +1095,8 @@ struct Grid final : GridBase {
     int rc = 0;
     if (e == hipSuccess && stray_kernel_build(nx, ny, nz, d[0], d[1], d[2], zt, k6, stream)) rc = -1;
     if (e == hipSuccess && !rc) {
-      launch_stray<T>(tb.yn, p.nsub, p.sub[0].Ms, p.nsub == 2 ? p.sub[1].Ms : 0.0, k6, nx, ny, nz,
-                      dout, stream);
+      launch_stray<T>(tb.yn, p.nsub, p.sub[0].Ms, p.nsub >= 2 ? p.sub[1].Ms : 0.0,
+                      p.nsub == 3 ? p.sub[2].Ms : 0.0, k6, nx, ny, nz, dout, stream);
       e = hipGetLastError();
       if (e == hipSuccess) e = hipStreamSynchronize(stream);
       if (e == hipSuccess) e = hipMemcpy(out, dout, no * sizeof(double), hipMemcpyDeviceToHost);

@@ -334,7 +334,7 @@ mmp_status mmp_submit(mmp_server s, const mmp_request* r, uint64_t* ticket) {
       return MMP_E_ARG;
     }
     if (r->nx < 1 || r->ny < 1 || r->nz < 1 || !r->m0 || !(r->t_relax > 0) ||
-        (r->params.nsub != 1 && r->params.nsub != 2)) {
+        r->params.nsub < 1 || r->params.nsub > 3) {
       set_error("bad request");
       return MMP_E_ARG;
     }

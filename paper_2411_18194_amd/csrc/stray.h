@@ -6,9 +6,9 @@
 namespace mmp {
 
 // out[c][y][x] (3*nx*ny doubles, device) = -mu0 sum over the grid's cells of
-// k6 (stray_kernel_build) times M = ms0 m0 + ms1 m1 (m: nsub*3*N, device).
+// k6 (stray_kernel_build) times M = sum_s ms_s m_s (m: nsub*3*N, device).
 template <typename T>
-void launch_stray(const T* m, int nsub, double ms0, double ms1, const double* k6, int nx, int ny,
-                  int nz, double* out, hipStream_t st);
+void launch_stray(const T* m, int nsub, double ms0, double ms1, double ms2, const double* k6,
+                  int nx, int ny, int nz, double* out, hipStream_t st);
 
 }  // namespace mmp

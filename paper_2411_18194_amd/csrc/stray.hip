@@ -4,7 +4,7 @@
 // the magnetostatic field of "Magnetostatic field").
 //
 // B_t(x, y) = -mu0 sum_z sum_{x', y'} N(x - x', y - y', z_t - z) M(x', y', z),
-// M = Ms0 m0 + Ms1 m1, with the cell-pair tensor table of stray_kernel_build.
+// M = sum_s Ms_s m_s, with the cell-pair tensor table of stray_kernel_build.
 // A direct tiled sum: a block owns 16x16 target cells and walks the source
 // tiles of every layer, staging the 3x16x16 moments and the 6x31x31 tensor
 // window of the tile pair in LDS; sums in FP64.  This is an output-time
@@ -18,8 +18,9 @@ constexpr int kSW = 2 * kST - 1;      // offsets between two tiles
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_stray(const T* __restrict__ m, int nsub, double ms0,
-                                              double ms1, const double* __restrict__ k6,
-                                              int nx, int ny, int nz, double* __restrict__ out) {
+                                              double ms1, double ms2,
+                                              const double* __restrict__ k6, int nx, int ny,
+                                              int nz, double* __restrict__ out) {
   __shared__ double sm[3][kST * kST];
   __shared__ double sk[6][kSW * kSW];
   const int tx = threadIdx.x % kST, ty = threadIdx.x / kST;
@@ -43,7 +44,8 @@ __global__ __launch_bounds__(256) void k_stray(const T* __restrict__ m, int nsub
             const long i = ((long)z * ny + ys) * nx + xs;
             for (int c = 0; c < 3; ++c) {
               v[c] = ms0 * (double)m[c * N + i];
-              if (nsub == 2) v[c] += ms1 * (double)m[3 * N + c * N + i];
+              if (nsub >= 2) v[c] += ms1 * (double)m[3 * N + c * N + i];
+              if (nsub == 3) v[c] += ms2 * (double)m[6 * N + c * N + i];
             }
           }
           for (int c = 0; c < 3; ++c) sm[c][threadIdx.x] = v[c];
@@ -77,16 +79,16 @@ __global__ __launch_bounds__(256) void k_stray(const T* __restrict__ m, int nsub
 }
 
 template <typename T>
-void launch_stray(const T* m, int nsub, double ms0, double ms1, const double* k6, int nx, int ny,
-                  int nz, double* out, hipStream_t st) {
+void launch_stray(const T* m, int nsub, double ms0, double ms1, double ms2, const double* k6,
+                  int nx, int ny, int nz, double* out, hipStream_t st) {
   const dim3 g((nx + kST - 1) / kST, (ny + kST - 1) / kST);
-  hipLaunchKernelGGL((k_stray<T>), g, dim3(kST * kST), 0, st, m, nsub, ms0, ms1, k6, nx, ny, nz,
-                     out);
+  hipLaunchKernelGGL((k_stray<T>), g, dim3(kST * kST), 0, st, m, nsub, ms0, ms1, ms2, k6, nx, ny,
+                     nz, out);
 }
 
-template void launch_stray<float>(const float*, int, double, double, const double*, int, int, int,
-                                  double*, hipStream_t);
-template void launch_stray<double>(const double*, int, double, double, const double*, int, int,
-                                   int, double*, hipStream_t);
+template void launch_stray<float>(const float*, int, double, double, double, const double*, int,
+                                  int, int, double*, hipStream_t);
+template void launch_stray<double>(const double*, int, double, double, double, const double*, int,
+                                   int, int, double*, hipStream_t);
 
 }  // namespace mmp

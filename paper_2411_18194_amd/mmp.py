@@ -48,7 +48,7 @@ class Sub(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("precision", C.c_int32), ("nsub", C.c_int32),
-                ("demag", C.c_int32), ("gamma", C.c_double), ("sub", Sub * 2),
+                ("demag", C.c_int32), ("gamma", C.c_double), ("sub", Sub * 3),
                 ("A0", C.c_double), ("A12", C.c_double), ("latcon", C.c_double),
                 ("B_ext", C.c_double * 3), ("j", C.c_double * 3), ("dmi_layer", C.c_int32),
                 ("ngrains", C.c_int32), ("grain", C.POINTER(C.c_uint16)),
@@ -90,7 +90,7 @@ class Request(C.Structure):
 
 
 class Result(C.Structure):
-    _fields_ = [("status", C.c_int32), ("nsub", C.c_int32), ("m_avg", (C.c_double * 3) * 2),
+    _fields_ = [("status", C.c_int32), ("nsub", C.c_int32), ("m_avg", (C.c_double * 3) * 3),
                 ("energy", C.c_double), ("steps", C.c_int64), ("rejects", C.c_int64),
                 ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
 
