@@ -22,6 +22,11 @@ periodic): on a periodic axis the ghost of a boundary cell is the cell at
 the opposite end, for the exchange, inter-sublattice and DMI stencils alike,
 and no DMI boundary condition applies on that axis's faces.
 
+Grain boundaries (demonstrations of polycrystalline magnets: the
+ferromagnetic and inhomogeneous antiferromagnetic exchange constants are
+reduced at grain boundaries): a link between cells of different grains
+carries scale * A in the exchange and A12 stencils; DMI is not scaled.
+
 Homogeneous DMI of a two-sublattice magnet: energy density d.(m1 x m2)
 (the pair counted once; summing both orders would cancel it), fields
 -(m2 x d)/Ms1 and -(d x m1)/Ms2.  It is reported with the DMI term.
@@ -98,6 +103,28 @@ def laplacian(g, d):
     return out
 
 
+def link_weights(grain, scale, periodic=(False, False, False)):
+    """Exchange weight of each cell's six links (x-, x+, y-, y+, z-, z+):
+    ``scale`` between cells of different grains, 1 inside a grain and
+    towards a ghost (the paper reduces the exchange constants at grain
+    boundaries).  grain: (nz, ny, nx) ids."""
+    g = ghost_pad(np.asarray(grain, dtype=np.int64)[None], periodic)[0]
+    c = g[1:-1, 1:-1, 1:-1]
+    nb = (g[1:-1, 1:-1, :-2], g[1:-1, 1:-1, 2:], g[1:-1, :-2, 1:-1], g[1:-1, 2:, 1:-1],
+          g[:-2, 1:-1, 1:-1], g[2:, 1:-1, 1:-1])
+    return [np.where(n == c, 1.0, scale) for n in nb]
+
+
+def laplacian_weighted(g, d, w):
+    """Laplacian of a ghosted array with per-link weights w (link_weights)."""
+    dx, dy, dz = d
+    c = g[:, 1:-1, 1:-1, 1:-1]
+    out = (w[0] * (g[:, 1:-1, 1:-1, :-2] - c) + w[1] * (g[:, 1:-1, 1:-1, 2:] - c)) / (dx * dx)
+    out = out + (w[2] * (g[:, 1:-1, :-2, 1:-1] - c) + w[3] * (g[:, 1:-1, 2:, 1:-1] - c)) / (dy * dy)
+    out = out + (w[4] * (g[:, :-2, 1:-1, 1:-1] - c) + w[5] * (g[:, 2:, 1:-1, 1:-1] - c)) / (dz * dz)
+    return out
+
+
 def central_dx(g, d):
     return (g[:, 1:-1, 1:-1, 2:] - g[:, 1:-1, 1:-1, :-2]) / (2.0 * d[0])
 
@@ -116,21 +143,25 @@ def dmi_layer_mask(shape_zyx, dmi_layer):
     return mask
 
 
-def exchange_field(m, Ms, A, d, D=0.0, dmi_layer=None, periodic=(False, False, False)):
-    """(2A/Ms) lap m with Neumann (or DMI, or periodic) ghosts."""
+def exchange_field(m, Ms, A, d, D=0.0, dmi_layer=None, periodic=(False, False, False),
+                   links=None):
+    """(2A/Ms) lap m with Neumann (or DMI, or periodic) ghosts; ``links``
+    (link_weights) scales the exchange at grain boundaries."""
     if Ms == 0.0:
         return np.zeros_like(m)
     g = ghosted(m, d, D, A, dmi_layer, periodic)
-    return (2.0 * A / Ms) * laplacian(g, d)
+    lap = laplacian(g, d) if links is None else laplacian_weighted(g, d, links)
+    return (2.0 * A / Ms) * lap
 
 
-def afm_nn_field(mp, Ms, A12, d, periodic=(False, False, False)):
+def afm_nn_field(mp, Ms, A12, d, periodic=(False, False, False), links=None):
     """(A12/Ms) lap m' with plain Neumann (or periodic) ghosts (second term of
-    Eq. 3)."""
+    Eq. 3), scaled at grain boundaries by ``links``."""
     if Ms == 0.0:
         return np.zeros_like(mp)
     g = ghosted(mp, d, periodic=periodic)
-    return (A12 / Ms) * laplacian(g, d)
+    lap = laplacian(g, d) if links is None else laplacian_weighted(g, d, links)
+    return (A12 / Ms) * lap
 
 
 def afm_cell_field(mp, Ms, A0, a):

@@ -7,7 +7,10 @@ or three sublattices couples them through Eq. 3 (for three, every pair with
 the same A12 and A0: B^(s) gains sum over s' != s of A12/Ms lap m^(s') +
 4 A0/(Ms a^2) m^(s'), the paper's three exchange-coupled sublattices of the
 non-collinear Mn3Sn demonstration) and shares one demagnetising field built
-from the summed moment.  With elasticity on, the displacement u
+from the summed moment.  In a polycrystalline magnet (grain ids per cell)
+the A11 and A12 stencil links between cells of different grains carry
+grain_exchange_scale times the constant (the paper's domain-wall mobility
+and Mn3Sn demonstrations reduce both at grain boundaries).  With elasticity on, the displacement u
 and velocity v join the state (Eq. 7) and the strain feeds Eq. 9 back.
 
 Energies (joules, FP64) follow one rule for every term bilinear in m:
@@ -52,6 +55,11 @@ class Problem:
         if any(self.pbc) and p["elastic"] is not None:
             raise ValueError("periodic boundaries are not combined with elasticity")
         self.periodic = tuple(v > 0 for v in self.pbc)
+        # exchange scale at grain boundaries (1 = none)
+        gscale = p.get("grain_exchange_scale", 1.0)
+        self.links = None
+        if p.get("grain") is not None and gscale != 1.0:
+            self.links = fl.link_weights(p["grain"], gscale, self.periodic)
         # boundary condition of the stencils: "open" (ghost = boundary cell,
         # or the Eq. 5 ghosts of the interfacial DMI) or "eq6" (Eq. 6 with
         # the general DMI tensors of Eq. 4)
@@ -91,11 +99,11 @@ class Problem:
             return self._eq6_term(name, m, s)
         if name == "exch":
             return fl.exchange_field(ms, Ms, p["A11"][s], d, p["Dint"][s],
-                                     p["dmi_layer"], self.periodic)
+                                     p["dmi_layer"], self.periodic, self.links)
         if name == "afm_nn":
             B = np.zeros_like(ms)
             for mo in others:
-                B = B + fl.afm_nn_field(mo, Ms, p["A12"], d, self.periodic)
+                B = B + fl.afm_nn_field(mo, Ms, p["A12"], d, self.periodic, self.links)
             return B
         if name == "afm_cell":
             B = np.zeros_like(ms)
@@ -123,6 +131,11 @@ class Problem:
                                            self.strain(u))
         raise KeyError(name)
 
+    def _lap(self, g):
+        if self.links is None:
+            return fl.laplacian(g, self.d)
+        return fl.laplacian_weighted(g, self.d, self.links)
+
     def _eq6_term(self, name, m, s):
         """Exchange, inter-sublattice exchange or DMI over the Eq. 6 ghosts."""
         p, d = self.p, self.d
@@ -132,11 +145,11 @@ class Problem:
         g = dmi.eq6_ghosts(np.asarray(m), d, p["A11"], p["A12"], self.W, self.periodic)
         o = 1 - s if self.nsub == 2 else None
         if name == "exch":
-            return (2.0 * p["A11"][s] / Ms) * fl.laplacian(g[s], d)
+            return (2.0 * p["A11"][s] / Ms) * self._lap(g[s])
         if name == "afm_nn":
             if o is None:
                 return np.zeros_like(m[s])
-            return (p["A12"] / Ms) * fl.laplacian(g[o], d)
+            return (p["A12"] / Ms) * self._lap(g[o])
         B = dmi.tensor_field(g[s], None if o is None else g[o], Ms, self.W[s], self.W12, d)
         if o is not None:
             B = B + fl.homogeneous_dmi_field(m[s], m[o], Ms, p.get("dmi_homo", (0, 0, 0)),

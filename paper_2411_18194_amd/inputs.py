@@ -85,6 +85,7 @@ def base_params(n, cell, nsub=1):
         "bc": "open",
         "dmi_W": None,
         "dmi_W12": None,
+        "grain_exchange_scale": 1.0,
     }
 
 

@@ -240,3 +240,93 @@ def test_three_sublattice_triangular_state_torque_free():
     for s in range(3):
         assert np.allclose(np.cross(m[s], B[s], axis=0), 0, atol=1e-9 * np.abs(B).max())
     assert np.abs(P.torque(m)).max() < 1e-9 * P.p["gamma"] * np.abs(B).max()
+
+
+def _grains(n, seed):
+    ids, _ = inputs.voronoi_grains(inputs.rng(seed), n, (2e-9, 2e-9, 2e-9), 5)
+    return ids
+
+
+def test_grain_boundary_exchange_gradient():
+    """Scaled links at grain boundaries: the field is still the energy
+    gradient (every cell, boundaries and periodic wrap included)."""
+    n = (7, 6, 2)
+    p = inputs.base_params(n, (2e-9, 2e-9, 2e-9), nsub=2)
+    p.update(Ms=[4e5, 3e5], A11=[1e-11, 8e-12], A12=-5e-12, grain=_grains(n, 10),
+             grain_axes=np.tile([0.0, 0.0, 1.0], (5, 1)), grain_exchange_scale=0.25,
+             pbc=(1, 0, 0))
+    m = inputs.random_unit(inputs.rng(11), 2, n)
+    _energy_gradient_check(p, m, ("exch",))
+    _energy_gradient_check(p, m, ("afm_nn",))
+
+
+def test_grain_boundary_exchange_limits():
+    """Scale 1 is the plain exchange; scale 0 decouples the grains: a state
+    uniform inside each grain then has no exchange field."""
+    n = (8, 7, 1)
+    ids = _grains(n, 12)
+    base = inputs.base_params(n, (2e-9, 2e-9, 2e-9))
+    base.update(Ms=[8e5], A11=[1.3e-11], grain=ids, grain_axes=np.tile([0.0, 0.0, 1.0], (5, 1)))
+    m = inputs.random_unit(inputs.rng(13), 1, n)
+    b1 = Problem(dict(base, grain_exchange_scale=1.0)).eval_heff(m, ("exch",))
+    b0 = Problem(dict(base)).eval_heff(m, ("exch",))
+    assert np.array_equal(b1, b0)
+    dirs = inputs.random_unit(inputs.rng(14), 1, (5, 1, 1))[0, :, 0, 0, :]
+    mg = dirs[:, ids][None]
+    bz = Problem(dict(base, grain_exchange_scale=0.0)).eval_heff(mg, ("exch",))
+    assert np.abs(bz).max() < 1e-12 * np.abs(b0).max()
+    assert np.abs(Problem(dict(base)).eval_heff(mg, ("exch",))).max() > 0
+
+
+def test_grain_boundary_exchange_link_energy():
+    """Brute force over links: for unit vectors the exchange energy is
+    V sum_links w A |m_i - m_j|^2 / d^2, w = scale across a grain boundary
+    (periodic wrap along x included)."""
+    n = (6, 5, 3)
+    d = (2e-9, 2.5e-9, 1.5e-9)
+    ids = _grains(n, 15)
+    scale, A = 0.3, 1.2e-11
+    p = inputs.base_params(n, d)
+    p.update(Ms=[7e5], A11=[A], grain=ids, grain_axes=np.tile([0.0, 0.0, 1.0], (5, 1)),
+             grain_exchange_scale=scale, pbc=(1, 0, 0))
+    m = inputs.random_unit(inputs.rng(16), 1, n)
+    P = Problem(p)
+    nx, ny, nz = n
+    E = 0.0
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                for (ddx, ddy, ddz), h in (((1, 0, 0), d[0]), ((0, 1, 0), d[1]),
+                                           ((0, 0, 1), d[2])):
+                    X, Y, Z = x + ddx, y + ddy, z + ddz
+                    if X == nx:
+                        X = 0
+                    if Y == ny or Z == nz:
+                        continue
+                    w = 1.0 if ids[z, y, x] == ids[Z, Y, X] else scale
+                    dm = m[0, :, z, y, x] - m[0, :, Z, Y, X]
+                    E += w * A * float(dm @ dm) / h ** 2
+    E *= P.V
+    assert P.energies(m)["exch"] == pytest.approx(E, rel=1e-12)
+
+
+def test_grain_boundary_exchange_with_dmi_tensors():
+    """Grain-boundary scaling over the Eq. 6 ghosts (interfacial DMI tensors
+    of a two-sublattice magnet): the bulk field is the energy gradient, and
+    the DMI field is not scaled."""
+    n = (8, 6, 1)
+    D = 1.5e-3
+    Wi = [[0.0, D, 0.0], [-D, 0.0, 0.0], [0.0, 0.0, 0.0]]
+    p = inputs.base_params(n, (2e-9, 2e-9, 2e-9), nsub=2)
+    p.update(Ms=[4e5, 4e5], A11=[1e-11, 1e-11], A0=-2e-11, A12=-4e-12, latcon=0.35e-9,
+             bc="eq6", dmi_W=[Wi, Wi], grain=_grains(n, 17),
+             grain_axes=np.tile([0.0, 0.0, 1.0], (5, 1)), grain_exchange_scale=0.25)
+    m = inputs.random_unit(inputs.rng(18), 2, n)
+    for t in ("exch", "afm_nn", "dmi"):
+        _energy_gradient_check(p, m, (t,), interior_only=True)
+    b1 = Problem(p).eval_heff(m, ("dmi",))
+    b0 = Problem(dict(p, grain_exchange_scale=1.0)).eval_heff(m, ("dmi",))
+    assert np.array_equal(b1, b0)
+    e1 = Problem(p).eval_heff(m, ("exch",))
+    e0 = Problem(dict(p, grain_exchange_scale=1.0)).eval_heff(m, ("exch",))
+    assert not np.allclose(e1, e0)
