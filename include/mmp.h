@@ -163,6 +163,13 @@ typedef struct {
                              J/m^2; needs bc_eq6; interfacial D:
                              W_x = (0, D, 0), W_y = (-D, 0, 0)             */
   double dmi_W12[3][3];   /* inter-sublattice DMI tensor, same form        */
+  double grain_exch_reduction; /* polycrystal (ngrains > 0): the exchange
+                             (A11) and inhomogeneous inter-sublattice (A12)
+                             stencil links between cells of different grains
+                             carry (1 - r) times the constant (the paper's
+                             reduced exchange at grain boundaries); DMI is
+                             not scaled; 0 = none, 1 = decoupled grains;
+                             0 <= r <= 1                                   */
 } mmp_params;
 
 typedef struct {

@@ -153,6 +153,10 @@ mmp_status mmp_set_params(mmp_grid g, const mmp_params* p) {
     set_error("bad grain description");
     return MMP_E_ARG;
   }
+  if (!(p->grain_exch_reduction >= 0.0 && p->grain_exch_reduction <= 1.0)) {
+    set_error("grain_exch_reduction must be in [0, 1]");
+    return MMP_E_ARG;
+  }
   if (p->nsub == 2 && p->A0 != 0.0 && !(p->latcon > 0)) { set_error("latcon must be > 0"); return MMP_E_ARG; }
   if (p->elastic && !(p->rho > 0)) { set_error("rho must be > 0"); return MMP_E_ARG; }
   if (!(p->rayleigh >= 0.0)) { set_error("rayleigh must be >= 0"); return MMP_E_ARG; }

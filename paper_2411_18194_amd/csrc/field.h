@@ -44,6 +44,10 @@ struct FieldArgs {
   T cW[2][3][3], cW12[2][3][3];
   const uint16_t* grain;
   const T* gaxes;
+  // grain boundaries (gbx != 0): A11 and A12 links between cells of
+  // different grains scaled by gbx_scale
+  int gbx;
+  T gbx_scale;
   const T* Bd;
   const T* eps;
   const Table<T>* tbl;

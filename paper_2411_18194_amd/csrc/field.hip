@@ -141,7 +141,8 @@ __device__ void eq6_ghost(const FieldArgs<T>& a, const T (*m)[3], int ax, T side
 // Block w (tile-major over z chunks) of one grid; stage and fuse2 come from
 // the launch so that one argument block serves every stage.
 // GDMI: general DMI tensors with the Eq. 6 ghosts on every stencil.
-template <typename T, int NSUB, bool EVAL, bool GDMI = false>
+// GBX: exchange links between different grains scaled by gbx_scale.
+template <typename T, int NSUB, bool EVAL, bool GDMI = false, bool GBX = false>
 __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, const int stage,
                                             const int fuse2) {
   const int ntile = a.nbx * a.nby;
@@ -243,6 +244,25 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
         uax[1] = a.gaxes[3 * g + 1];
         uax[2] = a.gaxes[3 * g + 2];
       }
+      // link weights x-, x+, y-, y+, z-, z+ of the A11 and A12 stencils: the
+      // scale across a grain boundary, 1 inside a grain and towards a
+      // missing neighbour (its offset is 0, the cell's own grain)
+      T wl[6];
+      if constexpr (GBX) {
+        const uint16_t* gr = a.grain + i;
+        const int g0 = gr[0];
+        const T f = a.gbx_scale;
+        wl[0] = gr[dxm] == g0 ? T(1) : f;
+        wl[1] = gr[dxp] == g0 ? T(1) : f;
+        wl[2] = gr[dym] == g0 ? T(1) : f;
+        wl[3] = gr[dyp] == g0 ? T(1) : f;
+        wl[4] = gr[z > 0 ? -plane : 0] == g0 ? T(1) : f;
+        wl[5] = gr[dzp] == g0 ? T(1) : f;
+      }
+      auto lk = [&](int k, T v) -> T {
+        if constexpr (GBX) return wl[k] * v;
+        else return v;
+      };
       const bool dmil = NSUB == 1 && a.has_dmi && (a.dmi_layer < 0 || z == a.dmi_layer);
       // neighbours seen by the exchange and DMI stencils: the loaded ones, or
       // the Eq. 6 ghosts on the faces of the open axes (z neighbours are
@@ -302,9 +322,9 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
         // exchange
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const T l = ((gxm[c] - mm[c]) + (gxp[c] - mm[c])) * a.idx2 +
-                      ((gym[c] - mm[c]) + (gyp[c] - mm[c])) * a.idy2 +
-                      ((szm[s][c] - mm[c]) + (szp[s][c] - mm[c])) * a.idz2;
+          const T l = (lk(0, gxm[c] - mm[c]) + lk(1, gxp[c] - mm[c])) * a.idx2 +
+                      (lk(2, gym[c] - mm[c]) + lk(3, gyp[c] - mm[c])) * a.idy2 +
+                      (lk(4, szm[s][c] - mm[c]) + lk(5, szp[s][c] - mm[c])) * a.idz2;
           bt[c] = C.cex * l;
         }
         add(1, bt);
@@ -357,9 +377,9 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
               const T mo = cur[o][c];
-              const T l = ((sxm[o][c] - mo) + (sxp[o][c] - mo)) * a.idx2 +
-                          ((sym[o][c] - mo) + (syp[o][c] - mo)) * a.idy2 +
-                          ((szm[o][c] - mo) + (szp[o][c] - mo)) * a.idz2;
+              const T l = (lk(0, sxm[o][c] - mo) + lk(1, sxp[o][c] - mo)) * a.idx2 +
+                          (lk(2, sym[o][c] - mo) + lk(3, syp[o][c] - mo)) * a.idy2 +
+                          (lk(4, szm[o][c] - mo) + lk(5, szp[o][c] - mo)) * a.idz2;
               bt[c] += C.cnn * l;
             }
           }
@@ -603,10 +623,10 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
   }
 }
 
-template <typename T, int NSUB, bool EVAL, bool GDMI = false>
+template <typename T, int NSUB, bool EVAL, bool GDMI = false, bool GBX = false>
 __global__ __launch_bounds__(256) void k_field(const FieldArgs<T> a) {
   if (ctrl_stopped(a.ctrl)) return;
-  field_block<T, NSUB, EVAL, GDMI>(a, xcd_remap(blockIdx.x, a.nb_pad), a.stage, a.fuse2);
+  field_block<T, NSUB, EVAL, GDMI, GBX>(a, xcd_remap(blockIdx.x, a.nb_pad), a.stage, a.fuse2);
 }
 
 // Many grids in one launch: block b runs block work[b].y of grid work[b].x
@@ -636,28 +656,35 @@ void launch_field_multi(const FieldArgs<T>* args, const int2* work, int nwork, i
                        nb_pad, stage, fuse2);
 }
 
+// The Eq. 6 ghosts (GDMI) exist for one and two sublattices only.
+template <typename T, bool EVAL, bool GDMI, bool GBX>
+void launch_field_nsub(const FieldArgs<T>& a, hipStream_t st) {
+  const dim3 g(a.nb_pad), b(256);
+  if (a.nsub == 1) {
+    hipLaunchKernelGGL((k_field<T, 1, EVAL, GDMI, GBX>), g, b, 0, st, a);
+  } else if (a.nsub == 2) {
+    hipLaunchKernelGGL((k_field<T, 2, EVAL, GDMI, GBX>), g, b, 0, st, a);
+  } else if constexpr (!GDMI) {
+    hipLaunchKernelGGL((k_field<T, 3, EVAL, GDMI, GBX>), g, b, 0, st, a);
+  }
+}
+
+template <typename T, bool EVAL>
+void launch_field_var(const FieldArgs<T>& a, hipStream_t st) {
+  if (a.gdmi) {
+    if (a.gbx) launch_field_nsub<T, EVAL, true, true>(a, st);
+    else launch_field_nsub<T, EVAL, true, false>(a, st);
+  } else {
+    if (a.gbx) launch_field_nsub<T, EVAL, false, true>(a, st);
+    else launch_field_nsub<T, EVAL, false, false>(a, st);
+  }
+}
+
 template <typename T>
 void launch_field(const FieldArgs<T>& a, bool eval, hipStream_t st, Prof* prof) {
   ProfScope ps(prof, P_FIELD, st);
-  const dim3 g(a.nb_pad), b(256);
-  if (a.gdmi) {
-    if (a.nsub == 1) {
-      if (eval) hipLaunchKernelGGL((k_field<T, 1, true, true>), g, b, 0, st, a);
-      else hipLaunchKernelGGL((k_field<T, 1, false, true>), g, b, 0, st, a);
-    } else {
-      if (eval) hipLaunchKernelGGL((k_field<T, 2, true, true>), g, b, 0, st, a);
-      else hipLaunchKernelGGL((k_field<T, 2, false, true>), g, b, 0, st, a);
-    }
-  } else if (a.nsub == 1) {
-    if (eval) hipLaunchKernelGGL((k_field<T, 1, true>), g, b, 0, st, a);
-    else hipLaunchKernelGGL((k_field<T, 1, false>), g, b, 0, st, a);
-  } else if (a.nsub == 2) {
-    if (eval) hipLaunchKernelGGL((k_field<T, 2, true>), g, b, 0, st, a);
-    else hipLaunchKernelGGL((k_field<T, 2, false>), g, b, 0, st, a);
-  } else {
-    if (eval) hipLaunchKernelGGL((k_field<T, 3, true>), g, b, 0, st, a);
-    else hipLaunchKernelGGL((k_field<T, 3, false>), g, b, 0, st, a);
-  }
+  if (eval) launch_field_var<T, true>(a, st);
+  else launch_field_var<T, false>(a, st);
 }
 
 // --------------------------------------------------------- combine2 ----

@@ -574,6 +574,8 @@ struct Grid final : GridBase {
     a.has_dmih = (p.nsub == 2 && (p.dmi_homo[0] != 0.0 || p.dmi_homo[1] != 0.0 ||
                                   p.dmi_homo[2] != 0.0)) ? 1 : 0;
     a.gdmi = p.bc_eq6 ? 1 : 0;
+    a.gbx = (p.ngrains > 0 && p.grain_exch_reduction != 0.0) ? 1 : 0;
+    a.gbx_scale = (T)(1.0 - p.grain_exch_reduction);
     a.eA12 = (T)(p.nsub == 2 ? p.A12 : 0.0);
     for (int s = 0; s < 2; ++s) {
       const bool on = s < p.nsub;
@@ -1161,7 +1163,8 @@ struct Batch final : BatchBase {
     const auto* t = dynamic_cast<const Grid<T>*>(g);
     // one stage sequence serves every member: the Dormand-Prince pair
     return t && t->params_set && !t->p.demag && !t->p.elastic && t->p.nsub == nsub &&
-           t->p.solver == RK_DP45 && !t->p.bc_eq6;
+           t->p.solver == RK_DP45 && !t->p.bc_eq6 &&
+           !(t->p.ngrains > 0 && t->p.grain_exch_reduction != 0.0);
   }
   int size() const override { return (int)mem.size(); }
   int in_flight() const override { return count; }

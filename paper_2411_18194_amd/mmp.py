@@ -59,7 +59,8 @@ class Params(C.Structure):
                 ("dt0", C.c_double), ("dt_min", C.c_double), ("solver", C.c_int32),
                 ("pbc", C.c_int32 * 3), ("rayleigh", C.c_double),
                 ("dmi_homo", C.c_double * 3), ("bc_eq6", C.c_int32), ("pad2", C.c_int32),
-                ("dmi_W", ((C.c_double * 3) * 3) * 2), ("dmi_W12", (C.c_double * 3) * 3)]
+                ("dmi_W", ((C.c_double * 3) * 3) * 2), ("dmi_W12", (C.c_double * 3) * 3),
+                ("grain_exch_reduction", C.c_double)]
 
 
 class StepInfo(C.Structure):
@@ -214,6 +215,7 @@ def make_params(p: dict, precision=FP32, tol=1e-5, dt0=1e-14, dt_min=1e-20):
         P.ngrains = ax.shape[0]
         P.grain = g.ctypes.data_as(C.POINTER(C.c_uint16))
         P.grain_axes = _dptr(ax)
+        P.grain_exch_reduction = 1.0 - float(p.get("grain_exchange_scale", 1.0))
     el = p.get("elastic")
     if el is not None:
         P.elastic = 1

@@ -38,13 +38,14 @@ def test_struct_layout_matches_header(tmp_path):
     prog = tmp_path / "sz.c"
     prog.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "mmp.h"\n'
-        'int main(){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
+        'int main(){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
         "sizeof(mmp_params), sizeof(mmp_request), sizeof(mmp_result),"
         "sizeof(mmp_run_opts), sizeof(mmp_run_info), sizeof(mmp_step_info),"
         "sizeof(mmp_server_opts), offsetof(mmp_params, grain),"
         "offsetof(mmp_params, rho), offsetof(mmp_request, m0), sizeof(mmp_plan),"
         "offsetof(mmp_plan, z_lanes), offsetof(mmp_plan, field_ms),"
-        "offsetof(mmp_params, solver));return 0;}\n")
+        "offsetof(mmp_params, solver), offsetof(mmp_params, grain_exch_reduction));"
+        "return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)],
                    check=True)
@@ -54,7 +55,8 @@ def test_struct_layout_matches_header(tmp_path):
             C.sizeof(mmp.RunOpts), C.sizeof(mmp.RunInfo), C.sizeof(mmp.StepInfo),
             C.sizeof(mmp.ServerOpts), mmp.Params.grain.offset, mmp.Params.rho.offset,
             mmp.Request.m0.offset, C.sizeof(mmp.Plan), mmp.Plan.z_lanes.offset,
-            mmp.Plan.field_ms.offset, mmp.Params.solver.offset]
+            mmp.Plan.field_ms.offset, mmp.Params.solver.offset,
+            mmp.Params.grain_exch_reduction.offset]
     assert got == want
 
 

@@ -1,0 +1,136 @@
+"""GPU parity of the exchange reduced at grain boundaries.
+
+The paper's polycrystalline demonstrations (antiferromagnetic domain-wall
+mobility: A11 and A12 reduced by 75 % between grains; the Mn3Sn film:
+coupling between grains reduced to 10 %) scale the A11 and A12 stencil
+links between cells of different grains.  Per-term fields, torque and
+energies: FP64 <= 1e-12, FP32 <= 2e-6 (norm of test_gpu_parity); fixed FP64
+steps max |dm| <= 1e-12.
+"""
+import numpy as np
+import pytest
+
+from oracle.system import Problem, TERMS
+from paper_2411_18194_amd import inputs, mmp
+
+pytestmark = pytest.mark.gpu
+
+TOL = {mmp.FP64: 1e-12, mmp.FP32: 2e-6}
+
+
+def relerr(a, b):
+    s = np.abs(b).max()
+    return np.abs(a - b).max() / (s if s > 0 else 1.0)
+
+
+def _grains(n, d, seed, ng):
+    """Voronoi grain ids and a random easy axis per grain."""
+    g = inputs.rng(seed)
+    ids, _ = inputs.voronoi_grains(g, n, d, ng)
+    axes = g.standard_normal((ng, 3))
+    return ids, axes / np.linalg.norm(axes, axis=1, keepdims=True)
+
+
+def _fm():
+    n = (20, 12, 3)
+    d = (2e-9, 2e-9, 2e-9)
+    ids, axes = _grains(n, d, 90, 9)
+    p = inputs.base_params(n, d)
+    p.update(Ms=[8e5], A11=[1.3e-11], alpha=[0.1], Ku1=[2e5], demag=True, Dint=[1e-3],
+             dmi_layer=None, B_ext=(0.0, 0.01, 0.02), grain=ids, grain_axes=axes,
+             grain_exchange_scale=0.25, pbc=(2, 0, 0), zl_P=[0.5], zl_xi=[0.05],
+             j=(2e11, 0.0, 0.0))
+    return p, inputs.smoothed_random_unit(inputs.rng(91), 1, n, sigma=1.5)
+
+
+def _afm_strip():
+    n = (24, 10, 1)
+    d = (2e-9, 2e-9, 10e-9)
+    ids, axes = _grains(n, d, 92, 8)
+    D = 1.5e-3
+    Wi = [[0.0, D, 0.0], [-D, 0.0, 0.0], [0.0, 0.0, 0.0]]
+    p = inputs.base_params(n, d, nsub=2)
+    p.update(Ms=[4e5, 4e5], A11=[1e-11, 1e-11], alpha=[0.05, 0.05], A0=-2e-11, A12=-1e-11,
+             latcon=0.35e-9, Ku1=[6e4, 6e4], anis_u=[(0, 0, 1), (0, 0, 1)], demag=True,
+             bc="eq6", dmi_W=[Wi, Wi], grain=ids, grain_axes=np.tile([0.0, 0.0, 1.0], (8, 1)),
+             grain_exchange_scale=0.25)
+    mm = inputs.smoothed_random_unit(inputs.rng(93), 1, n, sigma=1.5)
+    return p, np.concatenate([mm, -mm]) + 0.05 * inputs.random_unit(inputs.rng(94), 2, n)
+
+
+def _three():
+    n = (16, 16, 1)
+    d = (1e-9, 1e-9, 30e-9)
+    ids, axes = _grains(n, d, 95, 6)
+    p = inputs.base_params(n, d, nsub=3)
+    p.update(Ms=[3e5, 3e5, 3e5], A11=[6e-12] * 3, alpha=[0.01] * 3, A0=-2e-11, A12=-1e-12,
+             latcon=0.5e-9, Ku1=[1e4] * 3, demag=True, grain=ids, grain_axes=axes,
+             grain_exchange_scale=0.1)
+    return p, inputs.random_unit(inputs.rng(96), 3, n)
+
+
+CASES = {"fm_pbc": _fm, "afm_strip_eq6": _afm_strip, "three": _three}
+_oracles = {}
+
+
+def _case(name):
+    if name not in _oracles:
+        p, m = CASES[name]()
+        m = m / np.linalg.norm(m, axis=1, keepdims=True)
+        _oracles[name] = (p, m, Problem(p))
+    return _oracles[name]
+
+
+def test_cases_cross_grain_boundaries():
+    for name in CASES:
+        p, _, P = _case(name)
+        assert P.links is not None
+        assert any(np.any(w != 1.0) for w in P.links), name
+
+
+@pytest.mark.parametrize("prec", [mmp.FP64, mmp.FP32])
+@pytest.mark.parametrize("name", list(CASES))
+def test_eval_heff_per_term(name, prec):
+    p, m, P = _case(name)
+    if prec == mmp.FP32:
+        m = np.asarray(m, np.float32).astype(np.float64)
+    g = mmp.Grid(p, prec)
+    g.set_state(m)
+    worst = {}
+    for term in TERMS:
+        b, _ = g.eval_heff(mmp.TERM_BITS[term])
+        ref = P.eval_heff(m, (term,))
+        if np.abs(ref).max() == 0:
+            assert np.abs(b).max() == 0, term
+            continue
+        worst[term] = relerr(b, ref)
+    b, e = g.eval_heff(mmp.T_ALL)
+    worst["total"] = relerr(b, P.eval_heff(m))
+    t, _ = g.eval_heff(mmp.T_ALL | mmp.T_ZL | mmp.OUT_TORQUE)
+    worst["torque"] = relerr(t, P.torque(m))
+    bad = {k: v for k, v in worst.items() if not v <= TOL[prec]}
+    assert not bad, (name, prec, worst)
+    Eref = P.energies(m)
+    scale = sum(abs(v) for v in Eref.values())
+    for k in mmp.ENERGY_NAMES:
+        assert abs(e[k] - Eref[k]) <= TOL[prec] * scale, (k, e[k], Eref[k])
+    g.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fixed_steps_fp64(name):
+    p, m, P = _case(name)
+    dt = 5e-14 if p["nsub"] == 1 else 1e-15
+    g = mmp.Grid(p, mmp.FP64)
+    g.set_state(m)
+    g.run_fixed(dt, 3)
+    mg = g.get_state()[0]
+    g.close()
+    y, _ = P.run_fixed(P.initial_state(m), 0.0, dt, 3)
+    assert np.abs(mg - y[0]).max() < 1e-12
+
+
+def test_reduction_out_of_range():
+    p, _, _ = _case("fm_pbc")
+    with pytest.raises(mmp.MMPError):
+        mmp.Grid(dict(p, grain_exchange_scale=-0.5), mmp.FP32).close()
