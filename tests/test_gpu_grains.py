@@ -134,3 +134,50 @@ def test_reduction_out_of_range():
     p, _, _ = _case("fm_pbc")
     with pytest.raises(mmp.MMPError):
         mmp.Grid(dict(p, grain_exchange_scale=-0.5), mmp.FP32).close()
+
+
+def _afm_small(seed):
+    n = (12, 8, 1)
+    d = (1e-9, 1e-9, 1e-9)
+    ids, axes = _grains(n, d, seed, 5)
+    p = inputs.base_params(n, d, nsub=2)
+    p.update(Ms=[4e5, 4e5], A11=[1e-11, 1e-11], alpha=[0.1, 0.1], A0=-2.5e-11, A12=-5e-12,
+             latcon=0.35e-9, Ku1=[6e4, 6e4], grain=ids, grain_axes=axes,
+             grain_exchange_scale=0.25, zl_P=[0.5, 0.5], zl_xi=[0.1, 0.1], j=(1e12, 0.0, 0.0))
+    mm = inputs.smoothed_random_unit(inputs.rng(seed + 1), 1, n, sigma=1.5)
+    m = np.concatenate([mm, -mm]) + 0.05 * inputs.random_unit(inputs.rng(seed + 2), 2, n)
+    return p, m / np.linalg.norm(m, axis=1, keepdims=True)
+
+
+def test_adaptive_run_fp64():
+    """Adaptive Dormand-Prince run from a too-large first step: the same
+    accept/reject sequence and trajectory as the oracle."""
+    p, m = _afm_small(97)
+    P = Problem(p)
+    g = mmp.Grid(p, mmp.FP64, tol=1e-5, dt0=2e-13)
+    g.set_state(m)
+    info, _, _ = g.run(0.2e-12)
+    mg = g.get_state()[0]
+    g.close()
+    y, _, oinfo, _ = P.run([m.copy()], 0.0, 0.2e-12, tol=1e-5, dt0=2e-13)
+    assert oinfo["rejects"] > 0
+    assert (info.steps, info.rejects) == (oinfo["steps"], oinfo["rejects"])
+    assert np.abs(mg - y[0]).max() < 1e-10
+
+
+def test_served_request_matches_alone():
+    """A request with reduced grain-boundary exchange is served on its own
+    stream (not batched) and gives the result of a plain grid."""
+    p, m = _afm_small(98)
+    srv = mmp.Server(hbm_budget=8 << 30, max_active=2, precision=mmp.FP32, batch=True)
+    out = srv.wait(srv.submit(p, m, 0.2e-12))
+    srv.close()
+    assert out.status == 0
+    g = mmp.Grid(p, mmp.FP32)
+    g.set_state(m)
+    info, _, _ = g.run(0.2e-12)
+    ref = g.get_state()[0].reshape(2, 3, -1).mean(axis=2)
+    g.close()
+    assert (out.steps, out.rejects) == (info.steps, info.rejects)
+    got = np.array([[out.m_avg[s][c] for c in range(3)] for s in range(2)])
+    assert np.allclose(got, ref, rtol=0, atol=1e-12)
