@@ -17,8 +17,10 @@ gives each kernel's average duration, and its step time is reported too.
 Also reported: the dominant kernel's algorithmic bytes per launch over its
 average HIP-event duration in the profiled region (roofline vs 8 TB/s), the
 HBM traffic the rocprofv3 counters measured for that kernel (when the
-committed counter summary matches the current kernel source), and the FP64
-CPU oracle timed on a bounded sample of the same workload.
+committed counter summary matches the current kernel source), the rate of a
+plain device copy moving the same number of bytes (the stream rate reachable
+at that working set; frac_of_copy), and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
 
 Before the warm-up the demag plan is autotuned (candidate pads and launch
 shapes timed on the device, the fastest installed), as a caller would do
@@ -165,6 +167,26 @@ def roofline(res, rb):
             "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
             "algorithmic_bytes_per_launch": ab[dom], "avg_launch_ms": round(avg_s * 1e3, 4),
             "time_share": share}
+
+
+def copy_rate(nbytes, reps=10):
+    """GB/s of a plain device copy moving nbytes in total (half read, half
+    written): the stream rate reachable at the dominant kernel's working set."""
+    import torch
+    n = max(1, nbytes // 8)
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    return 2 * n * 4 / sec / 1e9
 
 
 def cpu_baseline():
@@ -432,6 +454,9 @@ def main():
     if not args.no_prof:
         out["roofline"] = roofline(r32, 4)
         out["roofline"]["profiled_ms_per_step"] = round(r32["prof_ms_per_step"], 4)
+        cr = copy_rate(out["roofline"]["algorithmic_bytes_per_launch"])
+        out["roofline"]["copy_same_bytes_GBps"] = round(cr, 1)
+        out["roofline"]["frac_of_copy"] = round(out["roofline"]["achieved"] / cr, 4)
     if not args.no_fp64:
         r64 = run_gpu(mmp.FP64, max(3, args.steps // 3), args.warmup, prof=False, tune=tune)
         _progress("FP64 film done")
