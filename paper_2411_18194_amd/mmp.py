@@ -134,7 +134,7 @@ def load(path: str = LIB_PATH):
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise MMPError(-3, f"{path} not built; run __graft_entry__.build()")
+        raise MMPError(-3, f"{path} not built; run python -m paper_2411_18194_amd.build")
     lib = C.CDLL(path)
     dp = C.POINTER(C.c_double)
     vp = C.c_void_p
