@@ -1,7 +1,10 @@
 """Full-size checks on the 512x512x16 film (the benchmark workload).
 
-The oracle cannot evaluate the 4.2M-cell convolution in a test, so at full
-size the GPU path is checked against what holds at any size:
+The FP64 oracle evaluates the whole film (its tensor takes seconds to tens
+of seconds on the host cores): every cell's demag and total field and the
+energies with the autotuned plan (FP64 <= 1e-12, FP32 <= 2e-6), and one
+benchmark step in FP64 (max |dm| <= 1e-12).  Beside that, what holds at
+any size:
 * the FP64 tensor at sampled offsets of every regime equals the oracle's;
 * a uniformly magnetised prism along x, y, z has demag energy
   1/2 mu0 Ms^2 V_prism N_prism, N_prism the analytic self-term of the whole
@@ -105,3 +108,51 @@ def test_fp32_trajectory_fullsize(c2):
         g.close()
     assert np.abs(out[0] - out[1]).max() <= 1e-4
     assert np.abs(np.linalg.norm(out[1], axis=1) - 1).max() < 1e-6
+
+
+@pytest.fixture(scope="module")
+def c2_oracle(c2):
+    """The FP64 oracle of the whole film (tensor ~25 s on 8 cores)."""
+    import os
+
+    from oracle.system import Problem
+    p, m0 = c2
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    return Problem(p, demag_workers=workers)
+
+
+@pytest.mark.parametrize("prec,tol", [(mmp.FP64, 1e-12), (mmp.FP32, 2e-6)])
+def test_field_parity_fullsize(c2, c2_oracle, prec, tol):
+    """Every cell of the 512x512x16 film, autotuned plan (the benchmark's
+    launch configuration): demag and total field against the FP64 oracle."""
+    p, m0 = c2
+    m = m0 if prec == mmp.FP64 else np.asarray(m0, np.float32).astype(np.float64)
+    g = mmp.Grid(p, prec)
+    g.set_state(m)
+    g.autotune()
+    bd, _ = g.eval_heff(mmp.T_DEMAG)
+    b, e = g.eval_heff(mmp.T_ALL)
+    g.close()
+    P = c2_oracle
+    assert relerr(bd, P.eval_heff(m, ("demag",))) <= tol
+    assert relerr(b, P.eval_heff(m)) <= tol
+    Eref = P.energies(m)
+    scale = sum(abs(v) for v in Eref.values())
+    for k in mmp.ENERGY_NAMES:
+        assert abs(e[k] - Eref[k]) <= tol * scale, (k, e[k], Eref[k])
+
+
+def test_fixed_step_fullsize_fp64(c2, c2_oracle):
+    """One benchmark step (Dormand-Prince, dt = 0.1 ns/1667) of the whole
+    film in FP64 with the autotuned plan: max |dm| <= 1e-12."""
+    p, m0 = c2
+    dt = inputs.c2_fixed_dt()
+    g = mmp.Grid(p, mmp.FP64)
+    g.set_state(m0)
+    g.autotune()
+    g.run_fixed(dt, 1)
+    mg = g.get_state()[0]
+    g.close()
+    P = c2_oracle
+    y, _ = P.run_fixed(P.initial_state(m0), 0.0, dt, 1)
+    assert np.abs(mg - y[0]).max() < 1e-12
