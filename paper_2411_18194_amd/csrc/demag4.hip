@@ -356,11 +356,13 @@ __global__ __launch_bounds__(256) void k4_ffty_mul2d(M4Args<T> a) {
 }
 
 // ------------------------------------------ 3-D z columns + multiply ----
-// The value that lane (lane ^ X) of the same quad holds, X = 1 or 2 (DPP
-// quad permutations [1,0,3,2] and [2,3,0,1]; no LDS traffic).
+// The value that lane (lane ^ X) of the same quad holds, X = 1, 2 or 3 (DPP
+// quad permutations [1,0,3,2], [2,3,0,1] and [3,2,1,0]; no LDS traffic).
 template <int X>
 __device__ __forceinline__ int quad_xor_i(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, X == 1 ? 0xB1 : 0x4E, 0xF, 0xF, false);
+  static_assert(X >= 1 && X <= 3, "quad lane mask");
+  return __builtin_amdgcn_update_dpp(0, v, X == 1 ? 0xB1 : (X == 2 ? 0x4E : 0x1B), 0xF, 0xF,
+                                     false);
 }
 template <int X>
 __device__ __forceinline__ float quad_xor(float v) {
@@ -395,6 +397,87 @@ __device__ __forceinline__ cpx<T> lane_root(int q) {
     if (q == 3) w = root<T, 3 * N, P, INV>();
   }
   return w;
+}
+
+// exp(-2 pi i n t / P) with n = N0 + q and t = q ^ D, for the lane index q < Q
+template <typename T, int P, int Q, int D, int N0>
+__device__ __forceinline__ cpx<T> split_root(int q) {
+  cpx<T> w = root<T, (N0 * D) % P, P, false>();
+  if constexpr (Q >= 2)
+    if (q == 1) w = root<T, ((N0 + 1) * (1 ^ D)) % P, P, false>();
+  if constexpr (Q >= 4) {
+    if (q == 2) w = root<T, ((N0 + 2) * (2 ^ D)) % P, P, false>();
+    if (q == 3) w = root<T, ((N0 + 3) * (3 ^ D)) % P, P, false>();
+  }
+  return w;
+}
+
+// Forward input of the Q lanes of a column with the loads shared: lane t
+// needs its twisted, folded column y_t(r) = sum over n = r (mod R) of
+// x(n) w^(n t), R = PZ/Q.  When Q divides R every plane n of a residue r
+// lies in lane r mod Q, so lane q loads only the planes n = Q i + q, forms
+// for each lane t = q ^ D of the quad the terms of t's residues r = q + Q j
+// that its planes carry, and the terms reach t by the quad permutation ^D.
+// The sums and twiddles are those of loading every plane in every lane, at
+// 1/Q of the loads and of the registers they occupy.
+template <typename T, int PZ, int Q>
+__device__ __forceinline__ void zcol_load_split(const cpx<T>* col, long zs, long cs, int nz,
+                                                int q, cpx<T>* vx, cpx<T>* vy, cpx<T>* vz) {
+  using V = cpx<T>;
+  constexpr int R = PZ / Q, NH = PZ / 2, NL = NH / Q, J = R / Q, K = NH / R;
+  static_assert(Q > 1 && R % Q == 0 && NL >= 1 && K >= 1, "shared column loads");
+  V l[3][NL];
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    const int n = Q * i + q;
+    const long off = (long)(n < nz ? n : 0) * zs;
+    l[0][i] = ntload(col + off);
+    l[1][i] = ntload(col + cs + off);
+    l[2][i] = ntload(col + 2 * cs + off);
+  }
+#pragma unroll
+  for (int i = 0; i < NL; ++i)
+    if (Q * i + q >= nz) l[0][i] = l[1][i] = l[2][i] = cmk<T>(0, 0);
+  V in[3][Q][J];
+  static_for<0, Q>([&](auto dc) {
+    constexpr int D = decltype(dc)::value;
+    static_for<0, J>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      V acc[3] = {cmk<T>(0, 0), cmk<T>(0, 0), cmk<T>(0, 0)};
+      static_for<0, K>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        const V w = split_root<T, PZ, Q, D, Q * j + R * k>(q);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c] = cadd(acc[c], cmul(l[c][j + J * k], w));
+      });
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if constexpr (D == 0) in[c][D][j] = acc[c];
+        else in[c][D][j] = quad_xor_c<D, T>(acc[c]);
+      }
+    });
+  });
+  // residue r = p + Q j came from lane p through the permutation ^(p ^ q)
+#pragma unroll
+  for (int p = 0; p < Q; ++p) {
+    const int D = p ^ q;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      V o[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        o[c] = in[c][0][j];
+        if (D == 1) o[c] = in[c][1][j];
+        if constexpr (Q >= 4) {
+          if (D == 2) o[c] = in[c][2][j];
+          if (D == 3) o[c] = in[c][3][j];
+        }
+      }
+      vx[p + Q * j] = o[0];
+      vy[p + Q * j] = o[1];
+      vz[p + Q * j] = o[2];
+    }
+  }
 }
 
 // Inverse transform of one component held by the Q lanes of a column and
@@ -476,32 +559,36 @@ __device__ __forceinline__ void fftz_mul_body(const Z4Args<T>& a) {
   V* col = a.S2 + (long)kx * a.Py + ky;
   V vx[R], vy[R], vz[R];
   // nz <= PZ/2 for every power-of-two pad, so the upper half is zero
-  // all planes are loaded first (a plain unrolled loop keeps the loads
-  // back to back), then lane q twists them by w^(n q) and folds mod R
-  V lx[NH], ly[NH], lz[NH];
+  if constexpr (Q > 1 && (PZ / Q) % Q == 0) {
+    zcol_load_split<T, PZ, Q>(col, zs, cs, a.nz, q, vx, vy, vz);
+  } else {
+    // all planes are loaded first (a plain unrolled loop keeps the loads
+    // back to back), then lane q twists them by w^(n q) and folds mod R
+    V lx[NH], ly[NH], lz[NH];
 #pragma unroll
-  for (int n = 0; n < NH; ++n) {
-    const bool in = n < a.nz;
-    lx[n] = in ? ntload(col + n * zs) : cmk<T>(0, 0);
-    ly[n] = in ? ntload(col + cs + n * zs) : cmk<T>(0, 0);
-    lz[n] = in ? ntload(col + 2 * cs + n * zs) : cmk<T>(0, 0);
+    for (int n = 0; n < NH; ++n) {
+      const bool in = n < a.nz;
+      lx[n] = in ? ntload(col + n * zs) : cmk<T>(0, 0);
+      ly[n] = in ? ntload(col + cs + n * zs) : cmk<T>(0, 0);
+      lz[n] = in ? ntload(col + 2 * cs + n * zs) : cmk<T>(0, 0);
+    }
+    static_for<0, NH>([&](auto nc) {
+      constexpr int n = decltype(nc)::value;
+      V x = lx[n], y = ly[n], z = lz[n];
+      if constexpr (Q > 1 && n > 0) {
+        const V wq = lane_root<T, n, PZ, Q, false>(q);
+        x = cmul(x, wq);
+        y = cmul(y, wq);
+        z = cmul(z, wq);
+      }
+      if constexpr (n < R) {
+        vx[n] = x; vy[n] = y; vz[n] = z;
+      } else {
+        vx[n % R] = cadd(vx[n % R], x); vy[n % R] = cadd(vy[n % R], y);
+        vz[n % R] = cadd(vz[n % R], z);
+      }
+    });
   }
-  static_for<0, NH>([&](auto nc) {
-    constexpr int n = decltype(nc)::value;
-    V x = lx[n], y = ly[n], z = lz[n];
-    if constexpr (Q > 1 && n > 0) {
-      const V wq = lane_root<T, n, PZ, Q, false>(q);
-      x = cmul(x, wq);
-      y = cmul(y, wq);
-      z = cmul(z, wq);
-    }
-    if constexpr (n < R) {
-      vx[n] = x; vy[n] = y; vz[n] = z;
-    } else {
-      vx[n % R] = cadd(vx[n % R], x); vy[n % R] = cadd(vy[n % R], y);
-      vz[n % R] = cadd(vz[n % R], z);
-    }
-  });
   if constexpr (Q == 1) {
     reg_fft_hz<T, PZ, false>(vx);
     reg_fft_hz<T, PZ, false>(vy);
