@@ -6,10 +6,11 @@ Zhang-Li (Methods, "Micromagnetism": implemented as in mumax3, whose text is
 not reproduced in the paper):
   tau_ZL = -1/(1+alpha^2) [(1 + xi alpha) m x (m x (u.grad) m)
                            + (xi - alpha) m x (u.grad) m]
-with the drift velocity u = P mu_B j / (e Ms) (g = 2).  This prefactor is a
-reading of this build; only its structure is pinned (a uniform state feels
-no torque), so the Zhang-Li term is "parity unpinned" beyond GPU/oracle
-agreement.  (u.grad) m uses central differences with clamped neighbours
+with the drift velocity u = P mu_B j / (e Ms) (g = 2).  The torque's
+structure is pinned (a uniform state feels no torque; a periodic helix
+gives the closed form of both terms, tests/test_oracle_pbc.py), but the
+drift-velocity prefactor is a reading of this build: it is "parity
+unpinned" beyond GPU/oracle agreement.  (u.grad) m uses central differences with clamped neighbours
 (the boundary cell stands in for the missing one) over 2*d.
 """
 from __future__ import annotations

@@ -2,7 +2,8 @@
 
 * Exchange, DMI and the Zhang-Li derivative of spirals whose period divides
   the periodic length match their discrete closed forms at every cell,
-  boundary cells included (with Neumann ghosts they do not).
+  boundary cells included (with Neumann ghosts they do not); so does the
+  whole Zhang-Li torque of a helix (both of its terms, any alpha and xi).
 * The periodic demag field by FFT equals the plain double sum over cell
   pairs and images (tiny grids, odd and even lengths, so the half-period
   offset is covered).
@@ -71,6 +72,24 @@ def test_zhang_li_derivative_periodic():
     s = math.sin(k * d[0]) / d[0]
     ref = 3.0 * s * np.stack([-np.sin(k * x), np.cos(k * x), 0 * x])[:, None, None, :]
     assert np.abs(dm - np.broadcast_to(ref, dm.shape)).max() < 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("alpha,xi", [(0.02, 0.1), (0.3, 0.05), (0.1, 0.1)])
+def test_zhang_li_torque_helix_closed_form(alpha, xi):
+    """Periodic in-plane helix phi = k x, drift u along x: with a = (u.grad) m,
+    m x a = u s z and m x (m x a) = -a (s = sin(k dx)/dx), so the torque is
+    [(1 + xi alpha) a - (xi - alpha) u s z] / (1 + alpha^2) at every cell;
+    for xi = alpha it is the pure advection a."""
+    n, d = (24, 2, 1), (1.5e-9, 1e-9, 1e-9)
+    k, x, m = _spiral(n, d, 8)
+    ux = -40.0
+    tau = tq.zhang_li_torque(m, (ux, 0.0, 0.0), alpha, xi, d, periodic=PX)
+    s = math.sin(k * d[0]) / d[0]
+    a = ux * s * np.stack([-np.sin(k * x), np.cos(k * x), 0 * x])
+    zhat = np.stack([0 * x, 0 * x, 1 + 0 * x])
+    ref = ((1 + xi * alpha) * a - (xi - alpha) * ux * s * zhat) / (1 + alpha * alpha)
+    ref = np.broadcast_to(ref[:, None, None, :], tau.shape)
+    assert np.abs(tau - ref).max() < 1e-12 * np.abs(ref).max()
 
 
 @pytest.mark.parametrize("n,pbc", [((4, 3, 2), (2, 0, 0)), ((3, 4, 1), (1, 2, 0))])
