@@ -3,7 +3,10 @@
 The paper's polycrystalline demonstrations (antiferromagnetic domain-wall
 mobility: A11 and A12 reduced by 75 % between grains; the Mn3Sn film:
 coupling between grains reduced to 10 %) scale the A11 and A12 stencil
-links between cells of different grains.  Per-term fields, torque and
+links between cells of different grains.  Cases: a periodic ferromagnet,
+the two-sublattice strip with Eq. 6 tensors, three sublattices, and a
+periodic two-sublattice grid with demag over several 64x4 field tiles with
+ragged tails.  Per-term fields, torque and
 energies: FP64 <= 1e-12, FP32 <= 2e-6 (norm of test_gpu_parity); fixed FP64
 steps max |dm| <= 1e-12.
 """
@@ -69,7 +72,20 @@ def _three():
     return p, inputs.random_unit(inputs.rng(96), 3, n)
 
 
-CASES = {"fm_pbc": _fm, "afm_strip_eq6": _afm_strip, "three": _three}
+def _afm_tiles():
+    # several 64x4 field tiles with ragged tails in x and y, periodic x
+    n = (150, 11, 2)
+    d = (1e-9, 1e-9, 1e-9)
+    ids, axes = _grains(n, d, 99, 12)
+    p = inputs.base_params(n, d, nsub=2)
+    p.update(Ms=[4e5, 3.5e5], A11=[1e-11, 9e-12], alpha=[0.01, 0.02], A0=-2.5e-11, A12=-5e-12,
+             latcon=0.35e-9, Ku1=[6e4, 5e4], demag=True, grain=ids, grain_axes=axes,
+             grain_exchange_scale=0.4, pbc=(3, 0, 0), zl_P=[0.5, 0.4], zl_xi=[0.1, 0.2],
+             j=(5e11, 0.0, 0.0))
+    return p, inputs.random_unit(inputs.rng(100), 2, n)
+
+
+CASES = {"fm_pbc": _fm, "afm_strip_eq6": _afm_strip, "three": _three, "afm_tiles": _afm_tiles}
 _oracles = {}
 
 
