@@ -170,6 +170,13 @@ typedef struct {
                              reduced exchange at grain boundaries); DMI is
                              not scaled; 0 = none, 1 = decoupled grains;
                              0 <= r <= 1                                   */
+  /* Adaptive step control (0 = default): after every attempt the proposal
+     is h * clip(safety (tol/err)^(1/(q+1)), fac_min, fac_max) (fac_max when
+     err = 0), then at most dt_max; the first step is at most dt_max too.  */
+  double dt_max;          /* largest step, s (0 = unbounded)               */
+  double safety;          /* in (0, 1] (default 0.8)                       */
+  double fac_min;         /* in (0, 1] (default 0.1)                       */
+  double fac_max;         /* >= 1, >= fac_min (default 2)                  */
 } mmp_params;
 
 typedef struct {

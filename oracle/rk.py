@@ -120,11 +120,15 @@ FAC_MIN = 0.1
 FAC_MAX = 2.0
 
 
-def new_dt(dt, err, tol, q=4):
+def new_dt(dt, err, tol, q=4, safety=SAFETY, fac_min=FAC_MIN, fac_max=FAC_MAX, dt_max=None):
+    """Next step size: dt * clip(safety (tol/err)^(1/(q+1)), fac_min, fac_max)
+    (fac_max when err == 0), then at most dt_max."""
     if err == 0.0:
-        return dt * FAC_MAX
-    fac = SAFETY * (tol / err) ** (1.0 / (q + 1))
-    return dt * min(FAC_MAX, max(FAC_MIN, fac))
+        out = dt * fac_max
+    else:
+        fac = safety * (tol / err) ** (1.0 / (q + 1))
+        out = dt * min(fac_max, max(fac_min, fac))
+    return out if not dt_max else min(out, dt_max)
 
 
 class Stepper:

@@ -29,7 +29,7 @@ from . import fields as fl
 from . import dmi
 from . import torque as tq
 from .demag import Demag
-from .rk import TABLEAUS, Stepper, new_dt
+from .rk import FAC_MAX, FAC_MIN, SAFETY, TABLEAUS, Stepper, new_dt
 
 TERMS = ("demag", "exch", "afm_nn", "afm_cell", "dmi", "anis_u", "anis_c",
          "zeeman", "mel")
@@ -287,7 +287,10 @@ class Problem:
         step of ~1e-26 s that the step-size floor rejects.
         """
         t = t0
-        dt = dt0
+        p = self.p
+        ctl = dict(safety=p.get("safety") or SAFETY, fac_min=p.get("fac_min") or FAC_MIN,
+                   fac_max=p.get("fac_max") or FAC_MAX, dt_max=p.get("dt_max") or None)
+        dt = dt0 if not ctl["dt_max"] else min(dt0, ctl["dt_max"])
         samples = [] if sample is None else [(t, sample(y))]
         k = 1
 
@@ -315,7 +318,7 @@ class Problem:
                     next_out = out_time(k)
             else:
                 rejects += 1
-            dt = new_dt(h, err, tol, self.tableau.q)
+            dt = new_dt(h, err, tol, self.tableau.q, **ctl)
             if dt < dt_min:
                 raise RuntimeError("time step underflow")
         return y, t, dict(steps=steps, rejects=rejects, dt=dt), samples

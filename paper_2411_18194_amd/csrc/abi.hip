@@ -153,6 +153,15 @@ mmp_status mmp_set_params(mmp_grid g, const mmp_params* p) {
     set_error("bad grain description");
     return MMP_E_ARG;
   }
+  {
+    const double fmn = p->fac_min > 0 ? p->fac_min : 0.1, fmx = p->fac_max > 0 ? p->fac_max : 2.0;
+    if (!(p->dt_max >= 0.0) || !(p->safety >= 0.0 && p->safety <= 1.0) ||
+        !(p->fac_min >= 0.0 && p->fac_min <= 1.0) || !(p->fac_max == 0.0 || p->fac_max >= 1.0) ||
+        !(fmn <= fmx)) {
+      set_error("step control: dt_max >= 0, safety and fac_min in (0, 1], fac_max >= 1");
+      return MMP_E_ARG;
+    }
+  }
   if (!(p->grain_exch_reduction >= 0.0 && p->grain_exch_reduction <= 1.0)) {
     set_error("grain_exch_reduction must be in [0, 1]");
     return MMP_E_ARG;

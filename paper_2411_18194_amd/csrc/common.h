@@ -161,6 +161,9 @@ struct Ctrl {
   int32_t accepted;  // last attempt accepted
   int32_t nonfinite; // set by kernels on NaN/Inf
   int32_t pad;
+  // step-size rule: clip(safety (tol/err)^(1/(q+1)), fac_min, fac_max),
+  // then at most dt_max (0: unbounded)
+  double safety, fac_min, fac_max, dt_max;
 };
 
 // Pointer table of one grid's integrator buffers (device resident so the

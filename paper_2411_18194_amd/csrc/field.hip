@@ -779,10 +779,11 @@ __device__ __forceinline__ void control_block(Ctrl* c, Table<T>* tbl, const doub
     c->rejects += 1;
   }
   if (!c->fixed) {
-    double fac = 2.0;
-    if (err > 0.0) fac = 0.8 * pow(c->tol / err, 1.0 / (RK::t[tbl->rk].q + 1));
-    fac = fmin(2.0, fmax(0.1, fac));
+    double fac = c->fac_max;
+    if (err > 0.0) fac = c->safety * pow(c->tol / err, 1.0 / (RK::t[tbl->rk].q + 1));
+    fac = fmin(c->fac_max, fmax(c->fac_min, fac));
     c->dt = h * fac;
+    if (c->dt_max > 0.0) c->dt = fmin(c->dt, c->dt_max);
     if (c->dt < c->dt_min) {
       c->status = MMP_E_DT_UNDERFLOW;
       c->done = 1;

@@ -798,6 +798,10 @@ struct Grid final : GridBase {
     c.t_end = init.t_end; c.t_next = init.t_next; c.sample_every = init.sample_every;
     c.t0 = c.t; c.tol = init.tol; c.dt_min = init.dt_min; c.fixed = init.fixed;
     c.max_attempts = init.max_attempts;
+    c.safety = p.safety > 0 ? p.safety : 0.8;
+    c.fac_min = p.fac_min > 0 ? p.fac_min : 0.1;
+    c.fac_max = p.fac_max > 0 ? p.fac_max : 2.0;
+    c.dt_max = p.dt_max > 0 ? p.dt_max : 0.0;
     c.done = 0; c.status = 0; c.sample_k = init.fixed ? 0 : 1; c.nsamples = 0;
     c.sample_pending = 0; c.nonfinite = 0;
     if (init.fixed) {
@@ -805,6 +809,7 @@ struct Grid final : GridBase {
       c.land = 0;
     } else {
       if (c.dt <= 0) c.dt = p.dt0 > 0 ? p.dt0 : 1e-14;
+      if (c.dt_max > 0.0) c.dt = std::min(c.dt, c.dt_max);
       const double target = std::min(c.t_next, c.t_end);
       const double rem = target - c.t;
       c.land = c.dt >= rem ? 1 : 0;

@@ -60,7 +60,8 @@ class Params(C.Structure):
                 ("pbc", C.c_int32 * 3), ("rayleigh", C.c_double),
                 ("dmi_homo", C.c_double * 3), ("bc_eq6", C.c_int32), ("pad2", C.c_int32),
                 ("dmi_W", ((C.c_double * 3) * 3) * 2), ("dmi_W12", (C.c_double * 3) * 3),
-                ("grain_exch_reduction", C.c_double)]
+                ("grain_exch_reduction", C.c_double), ("dt_max", C.c_double),
+                ("safety", C.c_double), ("fac_min", C.c_double), ("fac_max", C.c_double)]
 
 
 class StepInfo(C.Structure):
@@ -223,6 +224,10 @@ def make_params(p: dict, precision=FP32, tol=1e-5, dt0=1e-14, dt_min=1e-20):
         P.eta = el["eta"]; P.trac_amp = el["trac_amp"]; P.trac_freq = el["trac_freq"]
         P.rayleigh = el.get("rayleigh", 0.0)
     P.tol, P.dt0, P.dt_min = tol, dt0, dt_min
+    P.dt_max = float(p.get("dt_max") or 0.0)
+    P.safety = float(p.get("safety") or 0.0)
+    P.fac_min = float(p.get("fac_min") or 0.0)
+    P.fac_max = float(p.get("fac_max") or 0.0)
     P.solver = SOLVERS[p.get("solver", "dp45")]
     P.pbc[:] = [int(v) for v in p.get("pbc", (0, 0, 0))]
     P.dmi_homo[:] = [float(v) for v in p.get("dmi_homo", (0.0, 0.0, 0.0))]

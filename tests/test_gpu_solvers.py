@@ -161,3 +161,28 @@ def test_unknown_solver_rejected():
         mmp._check(g.lib.mmp_set_params(g.h, mmp.C.byref(P)))
     assert e.value.code == -1
     g.close()
+
+
+@pytest.mark.parametrize("ctl", [dict(safety=0.9, fac_min=0.2, fac_max=5.0),
+                                 dict(dt_max=2.5e-13, safety=0.7)])
+def test_step_control_parameters(ctl):
+    """Device-side control with the caller's safety, clamps and dt_max: the
+    oracle's accept/reject sequence and trajectory (FP64)."""
+    p, m0 = inputs.config_c1()
+    p = dict(p, **ctl)
+    g = mmp.Grid(p, mmp.FP64, tol=1e-6, dt0=1e-11)
+    g.set_state(m0)
+    info, _, _ = g.run(10e-12)
+    mg = g.get_state()[0]
+    g.close()
+    y, _, oinfo, _ = Problem(p).run([m0.copy()], 0.0, 10e-12, tol=1e-6, dt0=1e-11)
+    assert oinfo["rejects"] > 0 or "dt_max" in ctl
+    assert (info.steps, info.rejects) == (oinfo["steps"], oinfo["rejects"])
+    assert np.abs(mg - y[0]).max() < 1e-10
+
+
+def test_step_control_rejections():
+    p, _ = inputs.config_c1()
+    for bad in (dict(safety=1.5), dict(fac_min=2.0), dict(fac_max=0.5), dict(dt_max=-1.0)):
+        with pytest.raises(mmp.MMPError):
+            mmp.Grid(dict(p, **bad), mmp.FP32).close()

@@ -254,3 +254,42 @@ def test_output_times_merge_with_the_end():
     ts = [s[0] for s in samples]
     assert len(ts) == 6 and ts[-1] == t_end
     assert np.allclose(ts, np.arange(6) * every, rtol=1e-12, atol=0)
+
+
+def test_step_size_rule_parameters():
+    """The step-size rule with explicit safety, clamps and dt_max: an error
+    equal to tol scales the step by the safety factor alone; a tiny error
+    (or zero) hits fac_max, a huge one fac_min; dt_max caps the result."""
+    dt, tol = 1e-13, 1e-5
+    kw = dict(safety=0.9, fac_min=0.2, fac_max=5.0)
+    assert rk.new_dt(dt, tol, tol, 4, **kw) == pytest.approx(0.9 * dt, rel=1e-15)
+    assert rk.new_dt(dt, tol * 2 ** 5, tol, 4, **kw) == pytest.approx(0.45 * dt, rel=1e-14)
+    assert rk.new_dt(dt, 1e-30, tol, 4, **kw) == 5.0 * dt
+    assert rk.new_dt(dt, 0.0, tol, 4, **kw) == 5.0 * dt
+    assert rk.new_dt(dt, 1.0, tol, 4, **kw) == 0.2 * dt
+    assert rk.new_dt(dt, 0.0, tol, 4, dt_max=3e-13, **kw) == 3e-13
+    assert rk.new_dt(dt, tol, tol, 4) == pytest.approx(0.8 * dt, rel=1e-15)
+
+
+def test_dt_max_bounds_every_step():
+    """An adaptive run with dt_max takes no step longer than dt_max: the
+    times it lands on are spaced by at most dt_max, and it needs at least
+    T/dt_max steps."""
+    p, m0 = inputs.config_c1()
+    T, dmax = 20e-12, 2.5e-13
+    q = dict(p, dt_max=dmax)
+    P = Problem(q)
+    times = []
+    P.stepper.step = _record(P.stepper.step, times)
+    _, t, info, _ = P.run([m0.copy()], 0.0, T, tol=1e-5, dt0=1e-12)
+    assert t == T and info["steps"] >= math.ceil(T / dmax)
+    assert max(times) <= dmax
+    free = Problem(p).run([m0.copy()], 0.0, T, tol=1e-5, dt0=1e-12)[2]
+    assert free["steps"] < info["steps"]
+
+
+def _record(step, out):
+    def wrapped(t, y, h):
+        out.append(h)
+        return step(t, y, h)
+    return wrapped
