@@ -486,6 +486,8 @@ __device__ __forceinline__ void zcol_load_split(const cpx<T>* col, long zs, long
 //   b(n) = sum_q w^(-n q) IFFT_R(B(Q j + q))(n mod R),
 // so each lane forms its term for n < PZ/2 and the Q lanes sum them with a
 // recursive-halving exchange that leaves lane q owning PZ/(2Q) planes.
+// Plain stores: the y inverse pass reads these planes next, and part of
+// them is still in the Infinity Cache when it does.
 template <typename T, int PZ, int Q>
 __device__ __forceinline__ void zcol_inverse_store(cpx<T>* v, cpx<T>* col, long zs, int nz,
                                                    int q) {
@@ -498,7 +500,7 @@ __device__ __forceinline__ void zcol_inverse_store(cpx<T>* v, cpx<T>* col, long 
   if constexpr (Q == 1) {
 #pragma unroll
     for (int z = 0; z < NH; ++z)
-      if (z < nz) ntstore(col + z * zs, t[bitrev<PZ>(z)]);
+      if (z < nz) col[z * zs] = t[bitrev<PZ>(z)];
   } else {
     V c[NH];
     static_for<0, NH>([&](auto nc) {
@@ -529,7 +531,7 @@ __device__ __forceinline__ void zcol_inverse_store(cpx<T>* v, cpx<T>* col, long 
     base += hi ? S / 2 : 0;
 #pragma unroll
     for (int i = 0; i < S / 2; ++i)
-      if (base + i < nz) ntstore(col + (base + i) * zs, c[i]);
+      if (base + i < nz) col[(base + i) * zs] = c[i];
   }
 }
 
