@@ -1,7 +1,9 @@
 """Build libmmp.so (HIP, gfx950) in-tree.
 
 Each translation unit under csrc/ is compiled by hipcc in parallel and the
-objects are linked into paper_2411_18194_amd/libmmp.so.  Always rebuilds.
+objects are linked into paper_2411_18194_amd/libmmp.so.  Always rebuilds,
+unless `--changed` asks to recompile only the units whose source, or any
+header under csrc/ or include/, is newer than their object.
 """
 from __future__ import annotations
 
@@ -46,11 +48,33 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
+def _headers_mtime() -> float:
+    t = 0.0
+    for d in (CSRC, os.path.join(ROOT, "include")):
+        for f in os.listdir(d):
+            if f.endswith(".h"):
+                t = max(t, os.path.getmtime(os.path.join(d, f)))
+    return t
+
+
+def _stale(src: str, hdr: float) -> bool:
+    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return os.path.getmtime(os.path.join(CSRC, src)) > t or hdr > t
+
+
+def build(jobs: int | None = None, verbose: bool = False, changed_only: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(len(SOURCES), max(1, min(8, os.cpu_count() or 1)))
+    todo = SOURCES
+    if changed_only:
+        hdr = _headers_mtime()
+        todo = [s for s in SOURCES if _stale(s, hdr)]
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        list(ex.map(_compile, todo))
+    objs = [os.path.join(BUILD, os.path.splitext(s)[0] + ".o") for s in SOURCES]
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-o", tmp, *objs, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -63,5 +87,5 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, changed_only="--changed" in sys.argv[1:])
     sys.exit(0)
