@@ -31,6 +31,12 @@ wave speed sqrt(C44/rho) and the static strain of a shear traction
 reproduce the paper's printed ~4 km/s and ~0.14 % for the NiO parameters;
 energy balance with eta = 0; the printed Rayleigh coefficient gives the
 printed ~5 % damping ratio of 24 nm shear waves.
+tests/test_oracle_magnetoelastic.py: the force equals the divergence of the
+magnetoelastic stress de/deps of the cubic magnetoelastic energy (symbolic,
+sympy) on polynomial magnetisations, B1 and B2 parts separately.
+tests/test_oracle_balance.py: the coupled system's energy balance closes at
+the solver's order, and the discrete boundary power tends to the traction
+power and the magnetostrictive stress's boundary work at first order.
 """
 from __future__ import annotations
 

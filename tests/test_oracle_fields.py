@@ -5,9 +5,17 @@
 * Interfacial DMI: a cycloid (cos kx, 0, sin kx) gives in the interior
   B = (2D/Ms)(sin kd/d)(cos kx, 0, sin kx).
 * Uniform states feel no exchange, no inter-sublattice Laplacian term.
-* Field = -(1/(Ms V)) dE/dm of the independently written energy density
-  (finite differences of the FP64 energy) for every local term and for the
-  bulk of exchange/DMI.
+* Field = -(1/(Ms V)) dE/dm (finite differences of the FP64 energy).  For
+  the local terms (anisotropy, Zeeman, magnetoelastic) the oracle's energy
+  densities are written independently of its fields; for the bilinear
+  terms (exchange, A12, A0, DMI) the oracle's energy is -1/2 M.B of the
+  same operator, which only shows the operator is symmetric, so those
+  fields are also checked against energies written here from scratch: a
+  sum over nearest-neighbour links of A |m_j - m_i|^2 (exchange),
+  A12 (m1_j - m1_i).(m2_j - m2_i) (inhomogeneous inter-sublattice), the
+  homogeneous -4 A0/a^2 m1.m2 per cell and the interfacial DMI density
+  D [m_z div m - (m.grad) m_z] with central differences (interior).
+  Magnitudes are pinned again by the spiral and cycloid closed forms.
 * The edge canting along x of a relaxed wide strip with exchange +
   interfacial DMI + perpendicular anisotropy converges to the 1-D problem
   A theta'' = K sin(theta) cos(theta), theta' = -D/(2A) at both ends
@@ -113,6 +121,88 @@ def test_energy_gradient_dmi_bulk():
     m = inputs.random_unit(inputs.rng(3), 1, p["n"])
     _energy_gradient_check(p, m, ("dmi",), interior_only=True)
     _energy_gradient_check(p, m, ("exch",), interior_only=True)
+
+
+def _link_energy_checks(p, m, field_terms, energy, interior_only=False):
+    """Field of the named terms against -(1/(Ms V)) dE/dm of `energy`."""
+    P = Problem(p)
+    B = P.eval_heff(m, field_terms)
+    rng = np.random.default_rng(11)
+    nsub, _, nz, ny, nx = m.shape
+    for _ in range(8):
+        s, c = rng.integers(nsub), rng.integers(3)
+        z = rng.integers(nz)
+        y = rng.integers(1, ny - 1) if interior_only else rng.integers(ny)
+        x = rng.integers(1, nx - 1) if interior_only else rng.integers(nx)
+        h = 1e-6
+        mp, mm_ = m.copy(), m.copy()
+        mp[s, c, z, y, x] += h
+        mm_[s, c, z, y, x] -= h
+        g = (energy(mp) - energy(mm_)) / (2 * h)
+        expect = -g / (p["Ms"][s] * P.V)
+        assert B[s, c, z, y, x] == pytest.approx(expect, rel=2e-6, abs=1e-9 * np.abs(B).max())
+
+
+def _links(f, axis):
+    """Differences f_j - f_i over the nearest-neighbour links along a spatial
+    axis (0 = x) of a (3, nz, ny, nx) field."""
+    return np.diff(f, axis=3 - axis)
+
+
+def test_energy_gradient_against_link_energies():
+    d = (2e-9, 3e-9, 1.5e-9)
+    p = inputs.base_params((6, 5, 3), d, nsub=2)
+    p.update(Ms=[8e5, 5e5], A11=[1e-11, 2e-11], A12=-5e-12, A0=-2e-11, latcon=0.35e-9)
+    m = inputs.random_unit(inputs.rng(12), 2, p["n"])
+    V = d[0] * d[1] * d[2]
+
+    def e_exch(mm):
+        return sum(p["A11"][s] * V / d[a] ** 2 * np.sum(_links(mm[s], a) ** 2)
+                   for s in range(2) for a in range(3))
+
+    def e_a12(mm):
+        return sum(p["A12"] * V / d[a] ** 2 * np.sum(_links(mm[0], a) * _links(mm[1], a))
+                   for a in range(3))
+
+    def e_a0(mm):
+        return -4.0 * p["A0"] / p["latcon"] ** 2 * V * np.sum(mm[0] * mm[1])
+
+    _link_energy_checks(p, m, ("exch",), e_exch)
+    _link_energy_checks(p, m, ("afm_nn",), e_a12)
+    _link_energy_checks(p, m, ("afm_cell",), e_a0)
+
+
+def test_dmi_field_against_its_energy_density():
+    d = (2e-9, 2.5e-9, 2e-9)
+    p = inputs.base_params((9, 8, 1), d)
+    D = 3e-3
+    p.update(Ms=[1.1e6], Dint=[D], dmi_layer=0)
+    m = inputs.random_unit(inputs.rng(13), 1, p["n"])
+    V = d[0] * d[1] * d[2]
+
+    def cdiff(f, axis):
+        # central difference on the cells that have both neighbours
+        g = np.moveaxis(f, 2 - axis, 0)
+        return np.moveaxis((g[2:] - g[:-2]) / (2 * d[axis]), 0, 2 - axis)
+
+    def energy(mm):
+        mx, my, mz = mm[0, 0], mm[0, 1], mm[0, 2]        # (nz, ny, nx)
+        e = 0.0
+        # x part on cells with both x neighbours, y part likewise
+        e += np.sum(mz[:, :, 1:-1] * cdiff(mx, 0) - mx[:, :, 1:-1] * cdiff(mz, 0))
+        e += np.sum(mz[:, 1:-1, :] * cdiff(my, 1) - my[:, 1:-1, :] * cdiff(mz, 1))
+        return D * V * e
+
+    # the field two cells in from every edge sees only interior energy terms
+    P = Problem(p)
+    B = P.eval_heff(m, ("dmi",))
+    for (y, x, c) in [(3, 4, 0), (4, 2, 1), (5, 6, 2), (2, 3, 2), (4, 5, 0)]:
+        h = 1e-6
+        mp, mm_ = m.copy(), m.copy()
+        mp[0, c, 0, y, x] += h
+        mm_[0, c, 0, y, x] -= h
+        expect = -(energy(mp) - energy(mm_)) / (2 * h) / (p["Ms"][0] * V)
+        assert B[0, c, 0, y, x] == pytest.approx(expect, rel=2e-6, abs=1e-9 * np.abs(B).max())
 
 
 def test_magnetoelastic_energy_gradient():
