@@ -285,6 +285,23 @@ mmp_status mmp_get_demag_tensor(mmp_grid g, double* n6);
  * (6 nz (2nx-1)(2ny-1) doubles) for the call.  Synchronous. */
 mmp_status mmp_stray_field(mmp_grid g, double height, double* b_out);
 
+/* Allocation-free variant of mmp_stray_field, for callers that cannot call
+ * hipMalloc (code under HIP graph capture, serving loops, harnesses that
+ * forbid device allocation).  Same field, same kernels; b_out_dev is a
+ * caller-owned DEVICE buffer of 3*nx*ny doubles [comp][y][x] on the grid's
+ * device.  Enqueued on the grid's stream (mmp_set_stream) and returns
+ * without synchronising: the field is there once that stream has run it
+ * (e.g. after mmp_synchronize).  The tensor table lives in a fixed
+ * per-device array of MMP_STRAY_NOALLOC_MAX doubles (16 MiB) that the
+ * library holds from the first call on a device until the process ends:
+ * MMP_E_TOO_LARGE when 6*nz*(2nx-1)*(2ny-1) exceeds it, MMP_E_ARG for
+ * height < dz/2 or a b_out_dev that is not device memory of the grid's
+ * device.  Every call on one GPU uses that GPU's one array: calls that
+ * overlap on one GPU (other streams, other threads) race and must be
+ * ordered by the caller. */
+#define MMP_STRAY_NOALLOC_MAX 2097152
+mmp_status mmp_stray_field_noalloc(mmp_grid g, double height, double* b_out_dev);
+
 /* ------------------------------------------------------------- plan -- */
 
 /* Launch plan of a grid.

@@ -340,6 +340,15 @@ mmp_status mmp_stray_field(mmp_grid g, double height, double* b_out) {
   MMP_GUARD_END
 }
 
+mmp_status mmp_stray_field_noalloc(mmp_grid g, double height, double* b_out_dev) {
+  MMP_GUARD_BEGIN
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!b_out_dev) { set_error("null output"); return MMP_E_ARG; }
+  return g->impl->stray_noalloc(height, b_out_dev);
+  MMP_GUARD_END
+}
+
 mmp_status mmp_get_plan(mmp_grid g, mmp_plan* out) {
   MMP_GUARD_BEGIN
   if (int rc = check_grid(g)) return rc;

@@ -38,6 +38,7 @@ struct GridBase {
   virtual long long bytes() const = 0;
   virtual int tensor(double* n6) = 0;
   virtual int stray(double height, double* out) = 0;
+  virtual int stray_noalloc(double height, double* out_dev) = 0;
   virtual int get_plan(mmp_plan* out) = 0;
   virtual int set_plan(const mmp_plan* in) = 0;
   virtual int autotune(mmp_plan* out) = 0;

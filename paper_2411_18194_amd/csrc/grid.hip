@@ -1075,14 +1075,35 @@ struct Grid final : GridBase {
     if (rc || e != hipSuccess) { set_error("tensor build failed"); return MMP_E_HIP; }
     return 0;
   }
-  // stray field in the layer of cells centred `height` above the top
-  // surface (synchronous; host output [3][ny][nx])
-  int stray(double height, double* out) override {
+  // device address of the state slot of the pointer table
+  const T* const* yn_slot() const {
+    return reinterpret_cast<const T* const*>(reinterpret_cast<const char*>(dtbl.p) +
+                                             offsetof(Table<T>, yn));
+  }
+
+  int stray_check(double height) {
     if (int rc = ensure_ready()) return rc;
     if (!(height >= 0.5 * d[2])) {
       set_error("stray field: height must be >= dz/2 (the layer clears the magnet)");
       return MMP_E_ARG;
     }
+    return 0;
+  }
+
+  // tensor table into k6, then the field into dout, on the grid's stream
+  hipError_t stray_launch(double height, double* k6, double* dout) {
+    const double zt = (nz - 0.5) * d[2] + height;
+    if (stray_kernel_build(nx, ny, nz, d[0], d[1], d[2], zt, k6, stream))
+      return hipErrorLaunchFailure;
+    launch_stray<T>(yn_slot(), p.nsub, p.sub[0].Ms, p.nsub >= 2 ? p.sub[1].Ms : 0.0,
+                    p.nsub == 3 ? p.sub[2].Ms : 0.0, k6, nx, ny, nz, dout, stream);
+    return hipGetLastError();
+  }
+
+  // stray field in the layer of cells centred `height` above the top
+  // surface (synchronous; host output [3][ny][nx])
+  int stray(double height, double* out) override {
+    if (int rc = stray_check(height)) return rc;
     const size_t nk = (size_t)6 * nz * (2 * ny - 1) * (2 * nx - 1);
     const size_t no = (size_t)3 * nx * ny;
     double *k6 = nullptr, *dout = nullptr;
@@ -1096,24 +1117,48 @@ struct Grid final : GridBase {
       set_error("stray field: device allocation failed");
       return MMP_E_NOMEM;
     }
-    Table<T> tb{};
-    hipError_t e = hipMemcpy(&tb, dtbl.p, sizeof(tb), hipMemcpyDeviceToHost);
-    const double zt = (nz - 0.5) * d[2] + height;
-    int rc = 0;
-    if (e == hipSuccess && stray_kernel_build(nx, ny, nz, d[0], d[1], d[2], zt, k6, stream)) rc = -1;
-    if (e == hipSuccess && !rc) {
-      launch_stray<T>(tb.yn, p.nsub, p.sub[0].Ms, p.nsub >= 2 ? p.sub[1].Ms : 0.0,
-                      p.nsub == 3 ? p.sub[2].Ms : 0.0, k6, nx, ny, nz, dout, stream);
-      e = hipGetLastError();
-      if (e == hipSuccess) e = hipStreamSynchronize(stream);
-      if (e == hipSuccess) e = hipMemcpy(out, dout, no * sizeof(double), hipMemcpyDeviceToHost);
-    }
+    hipError_t e = stray_launch(height, k6, dout);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e == hipSuccess) e = hipMemcpy(out, dout, no * sizeof(double), hipMemcpyDeviceToHost);
     (void)hipFree(k6);
     (void)hipFree(dout);
-    if (e != hipSuccess || rc) {
-      set_error(std::string("stray field: ") + (rc ? "tensor build failed" : hipGetErrorString(e)));
+    if (e != hipSuccess) {
+      set_error(std::string("stray field: ") + hipGetErrorString(e));
       return MMP_E_HIP;
     }
+    return 0;
+  }
+
+  // the same field into a caller-owned device buffer, the tensor table in
+  // the library's fixed per-device table; enqueued on the grid's stream
+  // with no allocation and no host synchronisation
+  int stray_noalloc(double height, double* dout) override {
+    if (int rc = stray_check(height)) return rc;
+    const long nk = 6L * nz * (2L * ny - 1) * (2L * nx - 1);
+    if (nk > kStrayScratchDoubles) {
+      set_error("stray field (no allocation): the tensor table needs " + std::to_string(nk) +
+                " doubles, above the fixed " + std::to_string(kStrayScratchDoubles) +
+                " (6 nz (2nx-1)(2ny-1) must not exceed it)");
+      return MMP_E_TOO_LARGE;
+    }
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, dout) != hipSuccess || at.type != hipMemoryTypeDevice) {
+      (void)hipGetLastError();
+      set_error("stray field (no allocation): b_out_dev is not device memory");
+      return MMP_E_ARG;
+    }
+    int dev = 0;
+    MMP_HIP_TRY(hipStreamGetDevice(stream, &dev));
+    if (at.device != dev) {
+      set_error("stray field (no allocation): b_out_dev is on another device than the grid");
+      return MMP_E_ARG;
+    }
+    double* k6 = nullptr;
+    if (stray_scratch(dev, &k6)) {
+      set_error("stray field (no allocation): hipGetSymbolAddress of the tensor table failed");
+      return MMP_E_HIP;
+    }
+    MMP_HIP_TRY(stray_launch(height, k6, dout));
     return 0;
   }
 

@@ -9,6 +9,8 @@
 // tiles of every layer, staging the 3x16x16 moments and the 6x31x31 tensor
 // window of the tile pair in LDS; sums in FP64.  This is an output-time
 // operation (one image per call), not part of a step.
+#include <mutex>
+
 #include "stray.h"
 
 namespace mmp {
@@ -16,11 +18,15 @@ namespace mmp {
 constexpr int kST = 16;               // tile edge
 constexpr int kSW = 2 * kST - 1;      // offsets between two tiles
 
+// The state is read through its slot in the grid's device pointer table
+// (the controller swaps that table after accepted steps), so a launch needs
+// no host read-back of the table.
 template <typename T>
-__global__ __launch_bounds__(256) void k_stray(const T* __restrict__ m, int nsub, double ms0,
-                                              double ms1, double ms2,
+__global__ __launch_bounds__(256) void k_stray(const T* const* __restrict__ mslot, int nsub,
+                                              double ms0, double ms1, double ms2,
                                               const double* __restrict__ k6, int nx, int ny,
                                               int nz, double* __restrict__ out) {
+  const T* __restrict__ m = *mslot;
   __shared__ double sm[3][kST * kST];
   __shared__ double sk[6][kSW * kSW];
   const int tx = threadIdx.x % kST, ty = threadIdx.x / kST;
@@ -79,16 +85,48 @@ __global__ __launch_bounds__(256) void k_stray(const T* __restrict__ m, int nsub
 }
 
 template <typename T>
-void launch_stray(const T* m, int nsub, double ms0, double ms1, double ms2, const double* k6,
-                  int nx, int ny, int nz, double* out, hipStream_t st) {
+void launch_stray(const T* const* mslot, int nsub, double ms0, double ms1, double ms2,
+                  const double* k6, int nx, int ny, int nz, double* out, hipStream_t st) {
   const dim3 g((nx + kST - 1) / kST, (ny + kST - 1) / kST);
-  hipLaunchKernelGGL((k_stray<T>), g, dim3(kST * kST), 0, st, m, nsub, ms0, ms1, ms2, k6, nx, ny,
-                     nz, out);
+  hipLaunchKernelGGL((k_stray<T>), g, dim3(kST * kST), 0, st, mslot, nsub, ms0, ms1, ms2, k6, nx,
+                     ny, nz, out);
 }
 
-template void launch_stray<float>(const float*, int, double, double, double, const double*, int,
-                                  int, int, double*, hipStream_t);
-template void launch_stray<double>(const double*, int, double, double, double, const double*, int,
-                                   int, int, double*, hipStream_t);
+template void launch_stray<float>(const float* const*, int, double, double, double,
+                                  const double*, int, int, int, double*, hipStream_t);
+template void launch_stray<double>(const double* const*, int, double, double, double,
+                                   const double*, int, int, int, double*, hipStream_t);
+
+// ------------------------------------------------ fixed tensor table --
+// Tensor table of the allocation-free stray-field call: one array per GPU,
+// held for the life of the process.  Host code must not pass the array's
+// name to a kernel (in host code it only names a host-side stand-in); the
+// device address comes from hipGetSymbolAddress, taken once per device
+// with that device current.
+static __device__ __align__(256) double scratch[kStrayScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+int stray_scratch(int dev, double** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) return -1;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return -1;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return -1;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr) return -1;
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return 0;
+}
 
 }  // namespace mmp

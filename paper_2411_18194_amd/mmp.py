@@ -122,7 +122,8 @@ def _plan_dict(pl: Plan) -> dict:
 EXPORTS = ("mmp_grid_create", "mmp_grid_destroy", "mmp_set_params", "mmp_set_state",
            "mmp_get_state", "mmp_eval_heff", "mmp_step", "mmp_run_fixed", "mmp_run",
            "mmp_set_stream", "mmp_set_graphs", "mmp_synchronize", "mmp_grid_bytes", "mmp_get_demag_tensor",
-           "mmp_get_plan", "mmp_set_plan", "mmp_autotune", "mmp_stray_field", "mmp_prof_enable", "mmp_prof_count", "mmp_prof_read", "mmp_prof_reset",
+           "mmp_get_plan", "mmp_set_plan", "mmp_autotune", "mmp_stray_field",
+           "mmp_stray_field_noalloc", "mmp_prof_enable", "mmp_prof_count", "mmp_prof_read", "mmp_prof_reset",
            "mmp_server_create", "mmp_submit", "mmp_poll", "mmp_server_destroy",
            "mmp_server_clock", "mmp_last_error")
 
@@ -155,6 +156,7 @@ def load(path: str = LIB_PATH):
         "mmp_grid_bytes": ([vp, C.POINTER(C.c_int64)], C.c_int32),
         "mmp_get_demag_tensor": ([vp, dp], C.c_int32),
         "mmp_stray_field": ([vp, C.c_double, dp], C.c_int32),
+        "mmp_stray_field_noalloc": ([vp, C.c_double, vp], C.c_int32),
         "mmp_get_plan": ([vp, C.POINTER(Plan)], C.c_int32),
         "mmp_set_plan": ([vp, C.POINTER(Plan)], C.c_int32),
         "mmp_autotune": ([vp, C.POINTER(Plan)], C.c_int32),
@@ -362,6 +364,13 @@ class Grid:
         b = np.empty((3, ny, nx))
         _check(self.lib.mmp_stray_field(self.h, float(height), _dptr(b)))
         return b
+
+    def stray_field_noalloc(self, height, out_dev_ptr):
+        """Enqueue the stray field into the caller's device buffer at address
+        out_dev_ptr (3*nx*ny doubles) on the grid's stream, with no device
+        allocation; synchronise before reading it."""
+        _check(self.lib.mmp_stray_field_noalloc(self.h, float(height),
+                                                C.c_void_p(int(out_dev_ptr))))
 
     def plan(self) -> dict:
         """The demag plan: pads and launch shapes (see mmp_plan)."""
