@@ -175,7 +175,8 @@ typedef struct {
      err = 0), then at most dt_max; the first step is at most dt_max too.  */
   double dt_max;          /* largest step, s (0 = unbounded)               */
   double safety;          /* in (0, 1] (default 0.8)                       */
-  double fac_min;         /* in (0, 1] (default 0.1)                       */
+  double fac_min;         /* in (0, 1) (default 0.1): below 1, so that a
+                             rejected attempt always shrinks the step     */
   double fac_max;         /* >= 1, >= fac_min (default 2)                  */
 } mmp_params;
 
@@ -236,9 +237,11 @@ mmp_status mmp_get_state(mmp_grid g, double* m, double* u, double* v,
 mmp_status mmp_eval_heff(mmp_grid g, uint32_t term_mask, double* b_out,
                          double* energy_out);
 
-/* One Dormand-Prince step.  dt_fixed > 0: fixed step, enqueued without a
- * host synchronisation when info is NULL.  dt_fixed == 0: adaptive, retried
- * until accepted (synchronous). */
+/* One step of the grid's Runge-Kutta pair (mmp_params.solver).
+ * dt_fixed > 0: fixed step, enqueued without a host synchronisation when
+ * info is NULL.  dt_fixed == 0: adaptive, retried until accepted
+ * (synchronous); MMP_E_DT_UNDERFLOW if the step falls below dt_min first,
+ * MMP_E_STATE if 1000 attempts in a row are rejected. */
 mmp_status mmp_step(mmp_grid g, double dt_fixed, mmp_step_info* info);
 
 /* nsteps fixed steps of dt, all enqueued on the grid's stream with no host
@@ -405,6 +408,10 @@ typedef struct {
 
 mmp_status mmp_server_create(const mmp_server_opts* o, mmp_server* out);
 mmp_status mmp_submit(mmp_server s, const mmp_request* r, uint64_t* ticket);
+/* MMP_PENDING while the request is queued or running; MMP_OK with its
+ * result once it has finished (out->status holds the request's own status).
+ * A result is returned once: afterwards the ticket is unknown
+ * (MMP_E_TICKET). */
 mmp_status mmp_poll(mmp_server s, uint64_t ticket, mmp_result* out);
 mmp_status mmp_server_destroy(mmp_server s);
 double mmp_server_clock(mmp_server s);

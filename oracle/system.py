@@ -290,6 +290,10 @@ class Problem:
         p = self.p
         ctl = dict(safety=p.get("safety") or SAFETY, fac_min=p.get("fac_min") or FAC_MIN,
                    fac_max=p.get("fac_max") or FAC_MAX, dt_max=p.get("dt_max") or None)
+        if not (0.0 < ctl["fac_min"] < 1.0 and 0.0 < ctl["safety"] <= 1.0
+                and ctl["fac_max"] >= 1.0):
+            # a rejected attempt must shrink the step, or the loop never ends
+            raise ValueError("step control: fac_min in (0, 1), safety in (0, 1], fac_max >= 1")
         dt = dt0 if not ctl["dt_max"] else min(dt0, ctl["dt_max"])
         samples = [] if sample is None else [(t, sample(y))]
         k = 1

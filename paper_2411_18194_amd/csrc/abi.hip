@@ -155,10 +155,12 @@ mmp_status mmp_set_params(mmp_grid g, const mmp_params* p) {
   }
   {
     const double fmn = p->fac_min > 0 ? p->fac_min : 0.1, fmx = p->fac_max > 0 ? p->fac_max : 2.0;
+    // fac_min < 1: a rejected attempt must shrink the step, or an adaptive
+    // run retries the same step forever
     if (!(p->dt_max >= 0.0) || !(p->safety >= 0.0 && p->safety <= 1.0) ||
-        !(p->fac_min >= 0.0 && p->fac_min <= 1.0) || !(p->fac_max == 0.0 || p->fac_max >= 1.0) ||
+        !(p->fac_min >= 0.0 && p->fac_min < 1.0) || !(p->fac_max == 0.0 || p->fac_max >= 1.0) ||
         !(fmn <= fmx)) {
-      set_error("step control: dt_max >= 0, safety and fac_min in (0, 1], fac_max >= 1");
+      set_error("step control: dt_max >= 0, safety in (0, 1], fac_min in (0, 1), fac_max >= 1");
       return MMP_E_ARG;
     }
   }

@@ -80,6 +80,9 @@ struct BatchBase {
   // handed to the members (their run_poll reports them)
   virtual int poll() = 0;
   virtual long long cells() const = 0;
+  // after a failed chunk or poll: wait for the batch's stream, drop every
+  // member and every chunk in flight; the batch is then empty and idle
+  virtual void abandon() = 0;
 };
 
 BatchBase* make_batch(int precision, int nsub);

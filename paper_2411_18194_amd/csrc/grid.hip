@@ -1,6 +1,7 @@
 // Grid driver: device buffers, parameter coefficients, and the enqueueing
 // of Dormand-Prince steps whose control lives on the device.
 #include <algorithm>
+#include <atomic>
 #include <cstddef>
 #include <cstring>
 #include <map>
@@ -623,6 +624,10 @@ struct Grid final : GridBase {
   }
 
   int set_state(const double* m, const double* uu, const double* vv, double t) override {
+    // work enqueued without a host synchronisation (mmp_step with a fixed
+    // dt, mmp_run_fixed) may still swap the pointer table or write the
+    // state and controller: let it finish before they are replaced
+    MMP_HIP_TRY(hipStreamSynchronize(stream));
     const size_t nm = (size_t)p.nsub * 3 * N;
     // the pointer table may have been swapped by earlier steps: reset it
     Table<T> tb{};
@@ -864,11 +869,16 @@ struct Grid final : GridBase {
     if ((rc = begin_segment(init))) return rc;
     Ctrl c{};
     const int64_t s0 = hctrl->steps;
-    for (int it = 0; it < 1000; ++it) {
+    constexpr int kMaxAttempts = 1000;
+    for (int it = 0; it < kMaxAttempts; ++it) {
       attempt(false, false);
       if ((rc = read_ctrl(&c))) return rc;
       if (c.status) { set_error(c.status == MMP_E_DT_UNDERFLOW ? "time step underflow" : "non-finite state"); return c.status; }
       if (c.steps > s0) break;
+    }
+    if (c.steps == s0) {
+      set_error("adaptive step: no attempt accepted in 1000 tries");
+      return MMP_E_STATE;
     }
     if (info) {
       info->t = c.t; info->dt = c.dt; info->err = c.err; info->steps = c.steps; info->rejects = c.rejects;
@@ -1175,6 +1185,16 @@ __global__ void k_gather_ctrl(Ctrl* const* __restrict__ src, Ctrl* __restrict__ 
   if (i < n) dst[i] = *src[i];
 }
 
+// Failure injection for host-side tests of the server's error handling:
+// the next n batch rebuilds fail with MMP_E_NOMEM (no device work is done).
+static std::atomic<int> g_batch_fail{0};
+static bool batch_fail_injected() {
+  int v = g_batch_fail.load();
+  while (v > 0)
+    if (g_batch_fail.compare_exchange_weak(v, v - 1)) return true;
+  return false;
+}
+
 template <typename T>
 struct Batch final : BatchBase {
   int nsub;
@@ -1259,6 +1279,10 @@ struct Batch final : BatchBase {
   }
 
   int rebuild() {
+    if (batch_fail_injected()) {
+      set_error("batch rebuild failed (injected)");
+      return MMP_E_NOMEM;
+    }
     if (gexec) {
       (void)hipGraphExecDestroy(gexec);
       gexec = nullptr;
@@ -1358,6 +1382,20 @@ struct Batch final : BatchBase {
     return 0;
   }
 
+  void abandon() override {
+    if (st) (void)hipStreamSynchronize(st);
+    (void)hipGetLastError();
+    count = 0;
+    head = 0;
+    for (auto& v : slot_mem) v.clear();
+    mem.clear();
+    dirty = true;
+    if (gexec) {
+      (void)hipGraphExecDestroy(gexec);
+      gexec = nullptr;
+    }
+  }
+
   int poll() override {
     if (count == 0) return 0;
     const hipError_t q = hipEventQuery(ev[head]);
@@ -1370,6 +1408,8 @@ struct Batch final : BatchBase {
     return 0;
   }
 };
+
+extern "C" void mmp_test_fail_batch_rebuilds(int n) { g_batch_fail.store(n < 0 ? 0 : n); }
 
 BatchBase* make_batch(int precision, int nsub) {
   if (precision == MMP_FP64) return new Batch<double>(nsub);

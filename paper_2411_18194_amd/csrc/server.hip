@@ -41,11 +41,18 @@ struct Req {
   bool batched = false;
 };
 
+// Device footprint of a request: the buffers Grid<T>::alloc_layout makes
+// for its parameters (state pair, stage pair, 7 slopes; with elasticity u
+// and v pairs, their stage pairs, 14 slopes and the strain, strain-rate and
+// stress tensors; grain ids and axes; the demag spectra, kernel and field),
+// the transient FP64 tensor of the demag build, and 1 MiB of small buffers.
 int64_t estimate_bytes(const mmp_request& r, int precision) {
   const int64_t N = (int64_t)r.nx * r.ny * r.nz;
   const int64_t rb = precision == MMP_FP64 ? 8 : 4;
   const int ns = r.params.nsub;
   int64_t b = (4 + 7) * (int64_t)ns * 3 * N * rb;  // state, stages, k
+  if (r.params.elastic) b += (8 * 3 + 14 * 3 + 3 * 6) * N * rb;
+  if (r.params.ngrains > 0) b += N * 2 + (int64_t)r.params.ngrains * 3 * rb;
   if (r.params.demag) {
     DemagPlan p;
     if (demag_plan(r.nx, r.ny, r.nz, (int)rb, nullptr, &p, r.params.pbc) == 0)
@@ -176,6 +183,21 @@ struct mmp_server_s {
     return rc != 0 || fin;
   }
 
+  // a failed chunk or poll: the batch drops its members and chunks (after
+  // its stream has drained, so no kernel still reads their grids), every
+  // member and every request waiting to join is finished with the error,
+  // and the next batched request starts a fresh batch
+  void fail_batch(BatchState& B, int rc) {
+    B.b->abandon();
+    for (Req* q : B.members) finish(q, rc);
+    for (Req* q : B.joining) finish(q, rc);
+    B.members.clear();
+    B.joining.clear();
+    B.draining = false;
+    delete B.b;
+    B.b = nullptr;
+  }
+
   // one round of a batch: collect finished chunks; when it is idle and a
   // member has finished or requests wait to join, change the membership;
   // keep two chunks in flight otherwise.  Returns whether anything moved.
@@ -187,8 +209,7 @@ struct mmp_server_s {
       if (rc == MMP_PENDING) break;
       any = true;
       if (rc != 0) {
-        for (Req* q : B.members) finish(q, rc);
-        B.members.clear();
+        fail_batch(B, rc);
         return true;
       }
       int st = 0;
@@ -224,9 +245,8 @@ struct mmp_server_s {
       while (B.b->in_flight() < 2) {
         const int rc = B.b->run_chunk(chunk);
         if (rc) {
-          for (Req* q : B.members) finish(q, rc);
-          B.members.clear();
-          break;
+          fail_batch(B, rc);
+          return true;
         }
         any = true;
       }
@@ -372,7 +392,11 @@ mmp_status mmp_poll(mmp_server s, uint64_t ticket, mmp_result* out) {
   std::lock_guard<std::mutex> lk(s->mu);
   auto it = s->done.find(ticket);
   if (it != s->done.end()) {
+    // a result is handed out once; the server keeps nothing of a request
+    // after that, so a long stream does not grow its tables
     *out = it->second;
+    s->done.erase(it);
+    s->known.erase(ticket);
     return MMP_OK;
   }
   if (s->known.count(ticket)) return MMP_PENDING;

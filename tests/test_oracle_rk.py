@@ -293,3 +293,14 @@ def _record(step, out):
         out.append(h)
         return step(t, y, h)
     return wrapped
+
+
+@pytest.mark.parametrize("bad", [dict(fac_min=1.0), dict(fac_min=1.5), dict(safety=1.2),
+                                 dict(fac_max=0.5)])
+def test_step_control_that_cannot_shrink_is_rejected(bad):
+    """With fac_min >= 1 a rejected attempt would retry the same step
+    forever; such settings are refused before the first step."""
+    p, m0 = inputs.config_c1()
+    P = Problem(dict(p, **bad))
+    with pytest.raises(ValueError):
+        P.run([m0.copy()], 0.0, 1e-12, tol=1e-5, dt0=1e-13)
