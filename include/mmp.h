@@ -25,7 +25,10 @@
  *   of the last error on the calling thread is mmp_last_error().  No call
  *   throws across the ABI.  Inputs are copied; outputs go to caller-owned
  *   buffers of the documented size.  A grid handle is used by one thread
- *   at a time; a server handle is thread-safe.
+ *   at a time; a server handle is thread-safe.  Grids on different threads
+ *   may run concurrently: the library serialises its HIP graph captures
+ *   with its synchronous copies and device allocations, which would
+ *   otherwise invalidate a capture in flight on another thread.
  *
  * Precision: the state, FFTs and stencils run in FP32 or FP64 (per grid);
  * the demagnetising tensor is built in FP64, the RK error norm, the time
@@ -339,7 +342,11 @@ typedef struct {
   int32_t field_zplanes;  /* z cells per thread of the field kernel        */
   uint32_t kinds;         /* out: bits 0/1/2 set when the x/y/z passes use
                              the power-of-two register kernels             */
-  int32_t reserved;       /* 0                                             */
+  int32_t lds_axes;       /* bits 0/1/2: run the x/y/z passes through the
+                             mixed-radix LDS kernels even where the pad is
+                             a power of two (0 = the register kernels
+                             there); such a grid computes its field bitwise
+                             as the server's batched demag does            */
   double demag_ms;        /* out: time of one demag evaluation measured by
                              mmp_autotune for this plan, 0 if not tuned    */
   double field_ms;        /* out: time of one field-kernel stage measured
@@ -382,10 +389,15 @@ typedef struct {
   int64_t hbm_budget;     /* bytes of device memory for requests           */
   int32_t max_active;     /* concurrent requests on the device             */
   int32_t precision;      /* MMP_FP32 or MMP_FP64 for every request        */
-  int32_t batch;          /* 1: requests without demag and elasticity step
-                             together, one launch per stage for all of
-                             them (same results as alone); 0: each request
-                             on its own stream                             */
+  int32_t batch;          /* 1: requests without elasticity that use the
+                             Dormand-Prince pair step together, one batch
+                             per sublattice count: every stage is one
+                             launch per demag pass and one field launch for
+                             all members (demag through the mixed-radix LDS
+                             kernels on every axis, the request's own
+                             kernels set to match: mmp_plan.lds_axes = 7),
+                             so a result is the same alone and in the mix;
+                             0: each request on its own stream             */
 } mmp_server_opts;
 
 typedef struct {

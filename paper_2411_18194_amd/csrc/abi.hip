@@ -9,6 +9,10 @@
 namespace mmp {
 
 static thread_local std::string g_last_error;
+std::recursive_mutex& device_mutex() {
+  static std::recursive_mutex mu;
+  return mu;
+}
 void set_error(const std::string& msg) { g_last_error = msg; }
 const char* get_error() { return g_last_error.c_str(); }
 
@@ -122,7 +126,10 @@ mmp_status mmp_grid_destroy(mmp_grid g) {
     (void)hipStreamSynchronize(g->impl->stream);
     hipStream_t own = g->impl->own_stream;
     g->impl.reset();
-    if (own) (void)hipStreamDestroy(own);
+    if (own) {
+      DeviceLock lk(device_mutex());
+      (void)hipStreamDestroy(own);
+    }
   }
   delete g;
   return MMP_OK;
@@ -131,6 +138,7 @@ mmp_status mmp_grid_destroy(mmp_grid g) {
 
 mmp_status mmp_set_params(mmp_grid g, const mmp_params* p) {
   MMP_GUARD_BEGIN
+  DeviceLock lk(device_mutex());  // synchronous copies: not during a capture
   if (!g || !p) { set_error("null argument"); return MMP_E_ARG; }
   if (p->struct_size != sizeof(mmp_params)) { set_error("mmp_params struct_size mismatch"); return MMP_E_ARG; }
   if (p->precision != MMP_FP32 && p->precision != MMP_FP64) { set_error("bad precision"); return MMP_E_ARG; }
@@ -197,14 +205,22 @@ mmp_status mmp_set_params(mmp_grid g, const mmp_params* p) {
       (void)hipStreamSynchronize(g->impl->stream);
       hipStream_t own = g->impl->own_stream;
       g->impl.reset();
-      if (own) (void)hipStreamDestroy(own);
+      if (own) {
+        DeviceLock lk(device_mutex());
+        (void)hipStreamDestroy(own);
+      }
     }
     GridBase* b = make_grid(p->precision);
     b->nx = g->nx; b->ny = g->ny; b->nz = g->nz;
     for (int i = 0; i < 3; ++i) b->d[i] = g->d[i];
     b->N = N;
     b->precision = p->precision;
-    if (hipStreamCreateWithFlags(&b->own_stream, hipStreamNonBlocking) != hipSuccess) {
+    hipError_t se;
+    {
+      DeviceLock lk(device_mutex());
+      se = hipStreamCreateWithFlags(&b->own_stream, hipStreamNonBlocking);
+    }
+    if (se != hipSuccess) {
       delete b;
       set_error("stream creation failed");
       return MMP_E_HIP;
@@ -233,6 +249,7 @@ mmp_status mmp_set_params(mmp_grid g, const mmp_params* p) {
 
 mmp_status mmp_set_state(mmp_grid g, const double* m, const double* u, const double* v, double t) {
   MMP_GUARD_BEGIN
+  DeviceLock lk(device_mutex());  // synchronous copies: not during a capture
   int rc = check_grid(g);
   if (rc) return rc;
   if (!m) { set_error("null magnetisation"); return MMP_E_ARG; }
@@ -242,6 +259,7 @@ mmp_status mmp_set_state(mmp_grid g, const double* m, const double* u, const dou
 
 mmp_status mmp_get_state(mmp_grid g, double* m, double* u, double* v, double* t, double* dt) {
   MMP_GUARD_BEGIN
+  DeviceLock lk(device_mutex());  // synchronous copies: not during a capture
   int rc = check_grid(g);
   if (rc) return rc;
   if (!g->impl->state_set) { set_error("mmp_set_state has not been called"); return MMP_E_STATE; }
@@ -251,6 +269,7 @@ mmp_status mmp_get_state(mmp_grid g, double* m, double* u, double* v, double* t,
 
 mmp_status mmp_eval_heff(mmp_grid g, uint32_t mask, double* b, double* e) {
   MMP_GUARD_BEGIN
+  DeviceLock lk(device_mutex());  // synchronous copies: not during a capture
   int rc = check_grid(g);
   if (rc) return rc;
   return g->impl->eval(mask, b, e);
@@ -326,6 +345,7 @@ mmp_status mmp_grid_bytes(mmp_grid g, int64_t* bytes) {
 
 mmp_status mmp_get_demag_tensor(mmp_grid g, double* n6) {
   MMP_GUARD_BEGIN
+  DeviceLock lk(device_mutex());  // synchronous copies: not during a capture
   int rc = check_grid(g);
   if (rc) return rc;
   if (!n6) { set_error("null output"); return MMP_E_ARG; }
@@ -335,6 +355,7 @@ mmp_status mmp_get_demag_tensor(mmp_grid g, double* n6) {
 
 mmp_status mmp_stray_field(mmp_grid g, double height, double* b_out) {
   MMP_GUARD_BEGIN
+  DeviceLock lk(device_mutex());  // synchronous copies: not during a capture
   int rc = check_grid(g);
   if (rc) return rc;
   if (!b_out) { set_error("null output"); return MMP_E_ARG; }
@@ -364,6 +385,7 @@ mmp_status mmp_get_plan(mmp_grid g, mmp_plan* out) {
 
 mmp_status mmp_set_plan(mmp_grid g, const mmp_plan* p) {
   MMP_GUARD_BEGIN
+  DeviceLock lk(device_mutex());  // synchronous copies: not during a capture
   if (int rc = check_grid(g)) return rc;
   if (!p || p->struct_size != sizeof(mmp_plan)) {
     set_error("mmp_plan: null or struct_size mismatch");
@@ -375,6 +397,7 @@ mmp_status mmp_set_plan(mmp_grid g, const mmp_plan* p) {
 
 mmp_status mmp_autotune(mmp_grid g, mmp_plan* out) {
   MMP_GUARD_BEGIN
+  DeviceLock lk(device_mutex());  // synchronous copies: not during a capture
   if (int rc = check_grid(g)) return rc;
   if (out && out->struct_size != sizeof(mmp_plan)) {
     set_error("mmp_plan: struct_size mismatch");

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "mmp.h"
@@ -212,6 +213,15 @@ inline int fft_radices(int L, int* out) {
 }
 
 void set_error(const std::string& msg);
+
+// A HIP graph capture on one thread must not overlap a call that
+// synchronises the device (hipMalloc, hipFree, pinned host memory, stream
+// creation and destruction) on another thread: such a call waits on the
+// capturing stream and invalidates the capture.  The library takes this
+// lock around every capture and every such call (the server's builder
+// thread sets grids up while its worker thread captures and replays).
+std::recursive_mutex& device_mutex();
+using DeviceLock = std::lock_guard<std::recursive_mutex>;
 const char* get_error();
 
 #define MMP_HIP_TRY(expr)                                                   \

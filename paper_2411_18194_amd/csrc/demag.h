@@ -1,6 +1,8 @@
 // Demagnetising-field convolution on the GPU: plan, buffers, launchers.
 #pragma once
 
+#include <vector>
+
 #include "common.h"
 #include "fft_engine.h"
 #include "prof.h"
@@ -33,6 +35,9 @@ struct DemagPlan {
   // image repetitions per axis; > 0 makes the axis periodic (x and y only):
   // P = n, no zero padding, the kernel summed over the images
   int rep[3] = {0, 0, 0};
+  // axes (bits 0/1/2 = x/y/z) forced onto the mixed-radix LDS kernels
+  // although their pads are powers of two
+  int force_lds = 0;
   size_t s1_elems = 0, s2_elems = 0, k_elems = 0;
 };
 
@@ -94,6 +99,48 @@ int stray_kernel_build(int nx, int ny, int nz, double dx, double dy, double dz, 
                        double* k6, hipStream_t st);
 int demag_tensor_only(int nx, int ny, int nz, double dx, double dy, double dz, double* n6,
                       hipStream_t st);
+
+// One grid of a batched demag evaluation: its plan (pads; its launch
+// shapes are not used), buffers, state table, controller and moments.
+template <typename T>
+struct DemagMember {
+  const DemagPlan* plan;
+  DemagBufs<T> bufs;
+  const Table<T>* tbl;
+  const Ctrl* ctrl;
+  T ms0, ms1, ms2;
+  int nsub;
+};
+
+// The demag passes of many grids of any pads, each pass one launch for all
+// of them over a device work table of (grid, block) entries, through the
+// mixed-radix LDS kernels with 256-thread blocks.  A grid's field is bitwise
+// the one its own plan gives with every axis on those kernels (force_lds =
+// 7): the per-line arithmetic of the LDS kernels does not depend on how
+// lines are grouped into blocks.
+// Whether a grid with plan p can join a batched demag evaluation (its lines
+// fit one 256-thread block of the LDS kernels).
+bool demag_multi_fits(const DemagPlan& p);
+
+template <typename T>
+class DemagMulti {
+ public:
+  DemagMulti() = default;
+  DemagMulti(const DemagMulti&) = delete;
+  DemagMulti& operator=(const DemagMulti&) = delete;
+  ~DemagMulti() { release(); }
+  // device tables for the members (synchronous); 0, or MMP_E_NOMEM /
+  // MMP_E_HIP
+  int build(const std::vector<DemagMember<T>>& members, hipStream_t st);
+  // B_d of every member for the stage input of `stage`
+  void launch(int stage, hipStream_t st) const;
+  bool empty() const { return impl == nullptr; }
+  void release();
+
+ private:
+  struct Impl;
+  Impl* impl = nullptr;
+};
 
 template <typename T>
 void build_twiddles(cpx<T>* tw, int L, hipStream_t st);

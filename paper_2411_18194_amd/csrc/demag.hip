@@ -50,17 +50,21 @@ struct XArgs {
   Rad rad;
 };
 
+// The pass bodies take the block's coordinates (and the stage) as
+// arguments: the single-grid kernels pass blockIdx, the batched kernels
+// the entry of their work table.
 template <typename T, bool P2>
-__global__ void k_fftx_fwd(XArgs<T> a) {
+__device__ __forceinline__ void fftx_fwd_body(const XArgs<T>& a, int stage, int bx, int by,
+                                              int bz) {
   using V = cpx<T>;
   if (ctrl_stopped(a.ctrl)) return;
   extern __shared__ char smem_raw[];
   V* buf = reinterpret_cast<V*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int c = blockIdx.z, z = blockIdx.y, y0 = blockIdx.x * a.ty;
+  const int c = bz, z = by, y0 = bx * a.ty;
   const int nl = a.ty >> 1;
   const long N = (long)a.nx * a.ny * a.nz;
-  const T* m = stage_in(a.tbl, a.stage);
+  const T* m = stage_in(a.tbl, stage);
   const T* m0 = m + (long)c * N + (long)z * a.ny * a.nx;
   const T* m1 = m0 + 3 * N;
   for (int idx = tid; idx < nl * a.Px; idx += nthr) {
@@ -100,13 +104,18 @@ __global__ void k_fftx_fwd(XArgs<T> a) {
 }
 
 template <typename T, bool P2>
-__global__ void k_fftx_inv(XArgs<T> a) {
+__global__ void k_fftx_fwd(XArgs<T> a) {
+  fftx_fwd_body<T, P2>(a, a.stage, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+template <typename T, bool P2>
+__device__ __forceinline__ void fftx_inv_body(const XArgs<T>& a, int bx, int by, int bz) {
   using V = cpx<T>;
   if (ctrl_stopped(a.ctrl)) return;
   extern __shared__ char smem_raw[];
   V* buf = reinterpret_cast<V*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int c = blockIdx.z, z = blockIdx.y, y0 = blockIdx.x * a.ty;
+  const int c = bz, z = by, y0 = bx * a.ty;
   const int nl = a.ty >> 1;
   const V* in = a.S1 + ((long)(c * a.nz + z) * a.Hx) * a.ldy + y0;
   for (int idx = tid; idx < nl * a.Hx; idx += nthr) {
@@ -130,6 +139,11 @@ __global__ void k_fftx_inv(XArgs<T> a) {
   }
 }
 
+template <typename T, bool P2>
+__global__ void k_fftx_inv(XArgs<T> a) {
+  fftx_inv_body<T, P2>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
 // --------------------------------------------------------------- y pass --
 template <typename T>
 struct YArgs {
@@ -142,13 +156,13 @@ struct YArgs {
 };
 
 template <typename T, bool INV, bool P2>
-__global__ void k_ffty(YArgs<T> a) {
+__device__ __forceinline__ void ffty_body(const YArgs<T>& a, int bx) {
   using V = cpx<T>;
   if (ctrl_stopped(a.ctrl)) return;
   extern __shared__ char smem_raw[];
   V* buf = reinterpret_cast<V*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int l0 = blockIdx.x * a.nl;
+  const int l0 = bx * a.nl;
   for (int idx = tid; idx < a.nl * a.L; idx += nthr) {
     const int q = idx / a.L, e = idx - q * a.L;
     const int gl = l0 + q;
@@ -163,6 +177,11 @@ __global__ void k_ffty(YArgs<T> a) {
     const int gl = l0 + q;
     if (gl < a.nlines) a.out[(long)gl * a.ld_out + e] = buf[q * a.L + e];
   }
+}
+
+template <typename T, bool INV, bool P2>
+__global__ void k_ffty(YArgs<T> a) {
+  ffty_body<T, INV, P2>(a, blockIdx.x);
 }
 
 // Symmetric 3x3 multiply with the octant kernel; sy/sz flip the odd parts.
@@ -196,13 +215,13 @@ struct M2Args {
 };
 
 template <typename T, bool P2>
-__global__ void k_ffty_mul2d(M2Args<T> a) {
+__device__ __forceinline__ void ffty_mul2d_body(const M2Args<T>& a, int bx) {
   using V = cpx<T>;
   if (ctrl_stopped(a.ctrl)) return;
   extern __shared__ char smem_raw[];
   V* buf = reinterpret_cast<V*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int kx0 = blockIdx.x * a.nk;
+  const int kx0 = bx * a.nk;
   const int L = a.Py;
   const int nl = 3 * a.nk;
   for (int idx = tid; idx < nl * L; idx += nthr) {
@@ -240,6 +259,11 @@ __global__ void k_ffty_mul2d(M2Args<T> a) {
   }
 }
 
+template <typename T, bool P2>
+__global__ void k_ffty_mul2d(M2Args<T> a) {
+  ffty_mul2d_body<T, P2>(a, blockIdx.x);
+}
+
 // 3-D grids: z forward, multiply, z inverse for tk ky values of one kx.
 template <typename T>
 struct ZArgs {
@@ -252,13 +276,13 @@ struct ZArgs {
 };
 
 template <typename T, bool P2>
-__global__ void k_fftz_mul(ZArgs<T> a) {
+__device__ __forceinline__ void fftz_mul_body(const ZArgs<T>& a, int bx, int by) {
   using V = cpx<T>;
   if (ctrl_stopped(a.ctrl)) return;
   extern __shared__ char smem_raw[];
   V* buf = reinterpret_cast<V*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int kx = blockIdx.y, ky0 = blockIdx.x * a.tk;
+  const int kx = by, ky0 = bx * a.tk;
   const int L = a.Pz;
   const int nl = 3 * a.tk;
   const long zstride = (long)a.Hx * a.Py;
@@ -300,6 +324,53 @@ __global__ void k_fftz_mul(ZArgs<T> a) {
     const int z = r % a.nz, c = r / a.nz;
     if (ky0 + j < a.Py) obase[c * cstride + z * zstride + j] = buf[(c * a.tk + j) * a.ls + z];
   }
+}
+
+template <typename T, bool P2>
+__global__ void k_fftz_mul(ZArgs<T> a) {
+  fftz_mul_body<T, P2>(a, blockIdx.x, blockIdx.y);
+}
+
+// --------------------------------------------------------- batched passes --
+// One launch of a pass for many grids: block b runs the pass body of grid
+// work[b].x at block coordinates (work[b].y, .z, .w) with that grid's
+// arguments.  256 threads per block; the dynamic LDS is the largest any
+// grid's block needs.
+constexpr int kMultiThreads = 256;
+
+template <typename T>
+__global__ __launch_bounds__(kMultiThreads) void k_fftx_fwd_multi(
+    const XArgs<T>* __restrict__ args, const int4* __restrict__ work, int stage) {
+  const int4 w = work[blockIdx.x];
+  fftx_fwd_body<T, false>(args[w.x], stage, w.y, w.z, w.w);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kMultiThreads) void k_fftx_inv_multi(
+    const XArgs<T>* __restrict__ args, const int4* __restrict__ work) {
+  const int4 w = work[blockIdx.x];
+  fftx_inv_body<T, false>(args[w.x], w.y, w.z, w.w);
+}
+
+template <typename T, bool INV>
+__global__ __launch_bounds__(kMultiThreads) void k_ffty_multi(const YArgs<T>* __restrict__ args,
+                                                              const int4* __restrict__ work) {
+  const int4 w = work[blockIdx.x];
+  ffty_body<T, INV, false>(args[w.x], w.y);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kMultiThreads) void k_fftz_mul_multi(
+    const ZArgs<T>* __restrict__ args, const int4* __restrict__ work) {
+  const int4 w = work[blockIdx.x];
+  fftz_mul_body<T, false>(args[w.x], w.y, w.z);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kMultiThreads) void k_ffty_mul2d_multi(
+    const M2Args<T>* __restrict__ args, const int4* __restrict__ work) {
+  const int4 w = work[blockIdx.x];
+  ffty_mul2d_body<T, false>(args[w.x], w.y);
 }
 
 // ------------------------------------------------------------------ plan --
@@ -546,6 +617,220 @@ void demag_pass(int pass, const DemagPlan& p, const DemagBufs<T>& b, const Table
     }
   }
 }
+
+// ------------------------------------------------------ batched driver --
+template <typename T>
+struct DemagMulti<T>::Impl {
+  // host copies (kept until the next build) and one device allocation
+  std::vector<XArgs<T>> xf;
+  std::vector<YArgs<T>> yf, yi;
+  std::vector<ZArgs<T>> z;
+  std::vector<M2Args<T>> m2;
+  std::vector<int4> wxf, wxi, wyf, wyi, wz, wm2;
+  char* dev = nullptr;
+  const XArgs<T>* d_xf = nullptr;
+  const XArgs<T>* d_xi = nullptr;
+  const YArgs<T>* d_yf = nullptr;
+  const YArgs<T>* d_yi = nullptr;
+  const ZArgs<T>* d_z = nullptr;
+  const M2Args<T>* d_m2 = nullptr;
+  const int4 *d_wxf = nullptr, *d_wxi = nullptr, *d_wyf = nullptr, *d_wyi = nullptr,
+             *d_wz = nullptr, *d_wm2 = nullptr;
+  size_t lds_x = 0, lds_y = 0, lds_z = 0, lds_m2 = 0;
+};
+
+template <typename T>
+void DemagMulti<T>::release() {
+  if (!impl) return;
+  if (impl->dev) {
+    DeviceLock lk(device_mutex());
+    (void)hipFree(impl->dev);
+  }
+  delete impl;
+  impl = nullptr;
+}
+
+// largest power of two <= cap (>= 1), at most hi
+static int pow2_floor(long cap, int hi) {
+  int v = 1;
+  while (v < hi && 2L * v <= cap) v *= 2;
+  return v;
+}
+
+bool demag_multi_fits(const DemagPlan& p) {
+  const long cap = (long)kMaxE * kMultiThreads;
+  if (p.Px > cap || p.Py > cap) return false;
+  if (p.nz == 1) return 3L * p.Py <= cap;
+  return 3L * (p.Pz + 1) <= cap;
+}
+
+template <typename T>
+int DemagMulti<T>::build(const std::vector<DemagMember<T>>& members, hipStream_t st) {
+  using V = cpx<T>;
+  release();
+  if (members.empty()) return 0;
+  for (const auto& mb : members)
+    if (!demag_multi_fits(*mb.plan)) {
+      set_error("batched demag: a pad is too long for one block's lines");
+      return MMP_E_ARG;
+    }
+  impl = new Impl();
+  Impl& I = *impl;
+  const long cap = (long)kMaxE * kMultiThreads;   // complex elements per block
+  for (size_t g = 0; g < members.size(); ++g) {
+    const DemagMember<T>& mb = members[g];
+    const DemagPlan& p = *mb.plan;
+    const int gi = (int)g;
+    // x passes: the most rows per block (<= 16) that fit
+    int ty = 2;
+    while (ty < 16 && (long)ty * p.Px <= cap && ty < p.ny + (p.ny & 1)) ty *= 2;
+    XArgs<T> xa{};
+    xa.tbl = mb.tbl; xa.ctrl = mb.ctrl; xa.stage = 0;
+    xa.ms0 = mb.ms0; xa.ms1 = mb.ms1; xa.ms2 = mb.ms2; xa.nsub = mb.nsub;
+    xa.S1 = mb.bufs.S1; xa.Bd = mb.bufs.Bd; xa.tw = mb.bufs.twx;
+    xa.nx = p.nx; xa.ny = p.ny; xa.nz = p.nz; xa.Px = p.Px; xa.Hx = p.Hx; xa.ldy = p.ldy;
+    xa.ty = ty; xa.rad = p.rx;
+    I.xf.push_back(xa);
+    const int xf_idx = (int)I.xf.size() - 1;
+    for (int c = 0; c < 3; ++c)
+      for (int z = 0; z < p.nz; ++z)
+        for (int b = 0; b < (p.ny + ty - 1) / ty; ++b) {
+          I.wxf.push_back(make_int4(xf_idx, b, z, c));
+          I.wxi.push_back(make_int4(xf_idx, b, z, c));
+        }
+    I.lds_x = std::max(I.lds_x, (size_t)(ty / 2) * p.Px * sizeof(V));
+    if (p.nz == 1) {
+      const int nk = pow2_floor(cap / (3L * p.Py), 64);
+      M2Args<T> a{};
+      a.ctrl = mb.ctrl; a.S1 = mb.bufs.S1; a.K = mb.bufs.K; a.tw = mb.bufs.twy;
+      a.ny = p.ny; a.Py = p.Py; a.Hx = p.Hx; a.Hy = p.Hy; a.ldy = p.ldy; a.nk = nk;
+      a.rad = p.ry;
+      I.m2.push_back(a);
+      const int idx = (int)I.m2.size() - 1;
+      for (int b = 0; b < (p.Hx + nk - 1) / nk; ++b) I.wm2.push_back(make_int4(idx, b, 0, 0));
+      I.lds_m2 = std::max(I.lds_m2, (size_t)3 * nk * p.Py * sizeof(V));
+    } else {
+      const int nl = pow2_floor(cap / p.Py, 64);
+      const int nlines = 3 * p.nz * p.Hx;
+      YArgs<T> a{};
+      a.ctrl = mb.ctrl; a.tw = mb.bufs.twy; a.nlines = nlines; a.L = p.Py; a.nl = nl;
+      a.rad = p.ry;
+      YArgs<T> f = a, i = a;
+      f.in = mb.bufs.S1; f.out = mb.bufs.S2;
+      f.nvalid_in = p.ny; f.ld_in = p.ldy; f.nvalid_out = p.Py; f.ld_out = p.Py;
+      i.in = mb.bufs.S2; i.out = mb.bufs.S1;
+      i.nvalid_in = p.Py; i.ld_in = p.Py; i.nvalid_out = p.ny; i.ld_out = p.ldy;
+      I.yf.push_back(f);
+      I.yi.push_back(i);
+      const int idx = (int)I.yf.size() - 1;
+      for (int b = 0; b < (nlines + nl - 1) / nl; ++b) {
+        I.wyf.push_back(make_int4(idx, b, 0, 0));
+        I.wyi.push_back(make_int4(idx, b, 0, 0));
+      }
+      I.lds_y = std::max(I.lds_y, (size_t)nl * p.Py * sizeof(V));
+      const int tk = pow2_floor(cap / (3L * (p.Pz + 1)), 64);
+      ZArgs<T> za{};
+      za.ctrl = mb.ctrl; za.S2 = mb.bufs.S2; za.K = mb.bufs.K; za.tw = mb.bufs.twz;
+      za.nz = p.nz; za.Pz = p.Pz; za.Hx = p.Hx; za.Py = p.Py; za.Hy = p.Hy; za.Hz = p.Hz;
+      za.tk = tk; za.ls = p.Pz + 1; za.rad = p.rz;
+      I.z.push_back(za);
+      const int zi = (int)I.z.size() - 1;
+      for (int kx = 0; kx < p.Hx; ++kx)
+        for (int b = 0; b < (p.Py + tk - 1) / tk; ++b) I.wz.push_back(make_int4(zi, b, kx, 0));
+      I.lds_z = std::max(I.lds_z, (size_t)3 * tk * (p.Pz + 1) * sizeof(V));
+    }
+  }
+  // one device allocation, 256-byte aligned segments
+  size_t off = 0;
+  auto seg = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  const size_t o_xf = seg(I.xf.size() * sizeof(XArgs<T>));
+  const size_t o_yf = seg(I.yf.size() * sizeof(YArgs<T>));
+  const size_t o_yi = seg(I.yi.size() * sizeof(YArgs<T>));
+  const size_t o_z = seg(I.z.size() * sizeof(ZArgs<T>));
+  const size_t o_m2 = seg(I.m2.size() * sizeof(M2Args<T>));
+  const size_t o_wxf = seg(I.wxf.size() * sizeof(int4));
+  const size_t o_wxi = seg(I.wxi.size() * sizeof(int4));
+  const size_t o_wyf = seg(I.wyf.size() * sizeof(int4));
+  const size_t o_wyi = seg(I.wyi.size() * sizeof(int4));
+  const size_t o_wz = seg(I.wz.size() * sizeof(int4));
+  const size_t o_wm2 = seg(I.wm2.size() * sizeof(int4));
+  hipError_t ae;
+  {
+    DeviceLock lk(device_mutex());
+    ae = hipMalloc(&I.dev, off);
+  }
+  if (ae != hipSuccess) {
+    I.dev = nullptr;
+    release();
+    set_error("device allocation failed (batched demag tables)");
+    return MMP_E_NOMEM;
+  }
+  auto put = [&](size_t o, const void* src, size_t bytes) {
+    return bytes ? hipMemcpyAsync(I.dev + o, src, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
+  };
+  hipError_t e = hipSuccess;
+  for (auto r : {put(o_xf, I.xf.data(), I.xf.size() * sizeof(XArgs<T>)),
+                 put(o_yf, I.yf.data(), I.yf.size() * sizeof(YArgs<T>)),
+                 put(o_yi, I.yi.data(), I.yi.size() * sizeof(YArgs<T>)),
+                 put(o_z, I.z.data(), I.z.size() * sizeof(ZArgs<T>)),
+                 put(o_m2, I.m2.data(), I.m2.size() * sizeof(M2Args<T>)),
+                 put(o_wxf, I.wxf.data(), I.wxf.size() * sizeof(int4)),
+                 put(o_wxi, I.wxi.data(), I.wxi.size() * sizeof(int4)),
+                 put(o_wyf, I.wyf.data(), I.wyf.size() * sizeof(int4)),
+                 put(o_wyi, I.wyi.data(), I.wyi.size() * sizeof(int4)),
+                 put(o_wz, I.wz.data(), I.wz.size() * sizeof(int4)),
+                 put(o_wm2, I.wm2.data(), I.wm2.size() * sizeof(int4))})
+    if (r != hipSuccess) e = r;
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    release();
+    set_error(std::string("batched demag tables: ") + hipGetErrorString(e));
+    return MMP_E_HIP;
+  }
+  // the x inverse pass reads the same arguments as the forward one
+  I.d_xf = reinterpret_cast<const XArgs<T>*>(I.dev + o_xf);
+  I.d_xi = I.d_xf;
+  I.d_yf = reinterpret_cast<const YArgs<T>*>(I.dev + o_yf);
+  I.d_yi = reinterpret_cast<const YArgs<T>*>(I.dev + o_yi);
+  I.d_z = reinterpret_cast<const ZArgs<T>*>(I.dev + o_z);
+  I.d_m2 = reinterpret_cast<const M2Args<T>*>(I.dev + o_m2);
+  I.d_wxf = reinterpret_cast<const int4*>(I.dev + o_wxf);
+  I.d_wxi = reinterpret_cast<const int4*>(I.dev + o_wxi);
+  I.d_wyf = reinterpret_cast<const int4*>(I.dev + o_wyf);
+  I.d_wyi = reinterpret_cast<const int4*>(I.dev + o_wyi);
+  I.d_wz = reinterpret_cast<const int4*>(I.dev + o_wz);
+  I.d_wm2 = reinterpret_cast<const int4*>(I.dev + o_wm2);
+  return 0;
+}
+
+template <typename T>
+void DemagMulti<T>::launch(int stage, hipStream_t st) const {
+  if (!impl) return;
+  const Impl& I = *impl;
+  const dim3 b(kMultiThreads);
+  hipLaunchKernelGGL((k_fftx_fwd_multi<T>), dim3((unsigned)I.wxf.size()), b, I.lds_x, st, I.d_xf,
+                     I.d_wxf, stage);
+  if (!I.wm2.empty())
+    hipLaunchKernelGGL((k_ffty_mul2d_multi<T>), dim3((unsigned)I.wm2.size()), b, I.lds_m2, st,
+                       I.d_m2, I.d_wm2);
+  if (!I.wyf.empty()) {
+    hipLaunchKernelGGL((k_ffty_multi<T, false>), dim3((unsigned)I.wyf.size()), b, I.lds_y, st,
+                       I.d_yf, I.d_wyf);
+    hipLaunchKernelGGL((k_fftz_mul_multi<T>), dim3((unsigned)I.wz.size()), b, I.lds_z, st, I.d_z,
+                       I.d_wz);
+    hipLaunchKernelGGL((k_ffty_multi<T, true>), dim3((unsigned)I.wyi.size()), b, I.lds_y, st,
+                       I.d_yi, I.d_wyi);
+  }
+  hipLaunchKernelGGL((k_fftx_inv_multi<T>), dim3((unsigned)I.wxi.size()), b, I.lds_x, st, I.d_xi,
+                     I.d_wxi);
+}
+
+template class DemagMulti<float>;
+template class DemagMulti<double>;
 
 static const int kPassProf[DP_COUNT] = {P_FFTX_FWD, P_FFTY_FWD, P_FFTZ_MUL,
                                         P_FFTY_INV, P_FFTX_INV, P_FFTY_MUL2D};

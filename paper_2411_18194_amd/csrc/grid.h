@@ -39,6 +39,10 @@ struct GridBase {
   virtual int tensor(double* n6) = 0;
   virtual int stray(double height, double* out) = 0;
   virtual int stray_noalloc(double height, double* out_dev) = 0;
+  // averages of m per sublattice (m_avg[3 nsub], reduced on the device in
+  // FP64) and the per-term energies (e[MMP_NENERGY]) of the current state;
+  // synchronous
+  virtual int summary(double* m_avg, double* e) = 0;
   virtual int get_plan(mmp_plan* out) = 0;
   virtual int set_plan(const mmp_plan* in) = 0;
   virtual int autotune(mmp_plan* out) = 0;

@@ -42,10 +42,14 @@ struct Buf {
   int alloc(size_t count) {
     n = count;
     if (count == 0) return 0;
+    DeviceLock lk(device_mutex());
     return hipMalloc(&p, count * sizeof(T)) == hipSuccess ? 0 : -1;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      DeviceLock lk(device_mutex());
+      (void)hipFree(p);
+    }
     p = nullptr;
     n = 0;
   }
@@ -61,6 +65,8 @@ struct Grid final : GridBase {
   Buf<double> errpart, epart, eout, spart, samp_t, samp_m, elpart;
   Buf<Table<T>> dtbl;
   Buf<Ctrl> dctrl;
+  Buf<Ctrl> sctrl;        // controller of an on-demand average (summary)
+  Buf<double> sres;       // its time and averages
   Ctrl* hctrl = nullptr;  // pinned mirror
   // demag
   DemagPlan plan{};
@@ -81,6 +87,7 @@ struct Grid final : GridBase {
   ~Grid() override {
     if (stream) (void)hipStreamSynchronize(stream);
     free_all();
+    DeviceLock lk(device_mutex());
     if (hctrl) (void)hipHostFree(hctrl);
     for (int i = 0; i < 2; ++i) {
       if (chunk_ev[i]) (void)hipEventDestroy(chunk_ev[i]);
@@ -98,6 +105,8 @@ struct Grid final : GridBase {
     for (auto* b : {&errpart, &epart, &eout, &spart, &samp_t, &samp_m, &elpart}) b->release();
     dtbl.release();
     dctrl.release();
+    sctrl.release();
+    sres.release();
     S1.release(); S2.release(); tw.release();
     plan = DemagPlan{};
     allocated = false;
@@ -170,7 +179,10 @@ struct Grid final : GridBase {
       free_all();
       return MMP_E_NOMEM;
     }
-    if (!hctrl) MMP_HIP_TRY(hipHostMalloc((void**)&hctrl, sizeof(Ctrl), 0));
+    if (!hctrl) {
+      DeviceLock lk(device_mutex());
+      MMP_HIP_TRY(hipHostMalloc((void**)&hctrl, sizeof(Ctrl), 0));
+    }
     // pointer table
     Table<T> t{};
     t.yn = y[0].p; t.ynew = y[1].p; t.sa = sa.p; t.sb = sb.p;
@@ -277,6 +289,7 @@ struct Grid final : GridBase {
 
   // twiddles and the transformed kernel for the current pads
   int build_demag() {
+    DeviceLock lk(device_mutex());
     double* n6 = nullptr;
     MMP_HIP_TRY(hipMalloc(&n6, 6 * (size_t)N * sizeof(double)));
     build_all_twiddles(db, plan);
@@ -334,6 +347,7 @@ struct Grid final : GridBase {
       o->z_cols = plan.tk;
       o->z_lanes = plan.zq; o->z_waves = plan.zw; o->z_threads = plan.zt;
       o->kinds = (plan.p2x ? 1u : 0u) | (plan.p2y ? 2u : 0u) | (plan.p2z ? 4u : 0u);
+      o->lds_axes = plan.force_lds;
       o->demag_ms = tuned_ms;
     }
     o->field_zplanes = field_zc;
@@ -357,6 +371,14 @@ struct Grid final : GridBase {
                   ">= 2n-1 and <= 4096");
         return MMP_E_ARG;
       }
+      if (in->lds_axes < 0 || in->lds_axes > 7) {
+        set_error("lds_axes: bits 0..2 only");
+        return MMP_E_ARG;
+      }
+      np.force_lds = in->lds_axes;
+      if (np.force_lds & 1) np.p2x = false;
+      if (np.force_lds & 2) np.p2y = false;
+      if (np.force_lds & 4) np.p2z = false;
       np.tyf = in->x_rows[0]; np.tyi = in->x_rows[1];
       np.nlyf = in->y_lines[0]; np.nlyi = in->y_lines[1];
       np.nk = in->xy_cols;
@@ -744,6 +766,7 @@ struct Grid final : GridBase {
 
   int graph_for(int kind, hipGraphExec_t* out) {
     if (!gexec[kind]) {
+      DeviceLock lk(device_mutex());
       hipGraph_t g = nullptr;
       MMP_HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
       for (int i = 0; i < kGraphAttempts; ++i) attempt(kind == 0, kind == 2);
@@ -937,6 +960,7 @@ struct Grid final : GridBase {
       info->nsamples = c.nsamples; info->status = c.status;
     }
     if (sampling && o && c.nsamples > 0) {
+      DeviceLock lk(device_mutex());
       const int ns = std::min(c.nsamples, samp_cap);
       std::vector<double> tt(ns), mm((size_t)ns * 9);
       MMP_HIP_TRY(hipMemcpy(tt.data(), samp_t.p, ns * sizeof(double), hipMemcpyDeviceToHost));
@@ -951,6 +975,26 @@ struct Grid final : GridBase {
       set_error(c.status == MMP_E_DT_UNDERFLOW ? "time step underflow" : "non-finite state");
       return c.status;
     }
+    return 0;
+  }
+
+  int summary(double* m_avg, double* e) override {
+    if (int rc = ensure_ready()) return rc;
+    DeviceLock lk(device_mutex());
+    if (!sctrl.p && (sctrl.alloc(1) || sres.alloc(10))) {
+      set_error("device allocation failed");
+      return MMP_E_NOMEM;
+    }
+    MMP_HIP_TRY(hipStreamSynchronize(stream));
+    Ctrl c{};
+    c.sample_pending = 1;
+    MMP_HIP_TRY(hipMemcpy(sctrl.p, &c, sizeof(c), hipMemcpyHostToDevice));
+    launch_sample<T>(sctrl.p, dtbl.p, p.nsub, N, spart.p, nsamp_blk, sres.p, sres.p + 1, 1,
+                     stream, nullptr);
+    MMP_HIP_TRY(hipGetLastError());
+    if (int rc = eval(0, nullptr, e)) return rc;   // synchronises the stream
+    MMP_HIP_TRY(hipMemcpy(m_avg, sres.p + 1, 3 * (size_t)p.nsub * sizeof(double),
+                          hipMemcpyDeviceToHost));
     return 0;
   }
 
@@ -1029,7 +1073,10 @@ struct Grid final : GridBase {
     if ((rc = begin_segment(init))) return rc;
     for (int i = 0; i < 2; ++i) {
       if (!chunk_ev[i]) MMP_HIP_TRY(hipEventCreateWithFlags(&chunk_ev[i], hipEventDisableTiming));
-      if (!chunk_ctrl[i]) MMP_HIP_TRY(hipHostMalloc((void**)&chunk_ctrl[i], sizeof(Ctrl), 0));
+      if (!chunk_ctrl[i]) {
+        DeviceLock lk(device_mutex());
+        MMP_HIP_TRY(hipHostMalloc((void**)&chunk_ctrl[i], sizeof(Ctrl), 0));
+      }
     }
     chunk_head = 0;
     chunk_count = 0;
@@ -1076,6 +1123,7 @@ struct Grid final : GridBase {
 
   int tensor(double* n6) override {
     double* d6 = nullptr;
+    DeviceLock lk(device_mutex());
     MMP_HIP_TRY(hipMalloc(&d6, 6 * (size_t)N * sizeof(double)));
     const int rc = demag_tensor_only(nx, ny, nz, d[0], d[1], d[2], d6, stream);
     hipError_t e = hipStreamSynchronize(stream);
@@ -1117,6 +1165,7 @@ struct Grid final : GridBase {
     const size_t nk = (size_t)6 * nz * (2 * ny - 1) * (2 * nx - 1);
     const size_t no = (size_t)3 * nx * ny;
     double *k6 = nullptr, *dout = nullptr;
+    DeviceLock lk(device_mutex());
     MMP_HIP_TRY(hipStreamSynchronize(stream));
     if (hipMalloc(&k6, nk * sizeof(double)) != hipSuccess) {
       set_error("stray field: device allocation failed");
@@ -1203,6 +1252,7 @@ struct Batch final : BatchBase {
   // device tables (rebuilt when membership changes)
   Buf<FieldArgs<T>> d_args;
   Buf<int2> d_work;
+  DemagMulti<T> dm;  // demag passes of the members with demag
   Buf<StepWork<T>> d_step;
   Buf<Ctrl*> d_cptr;
   Buf<Ctrl> d_cgather;
@@ -1221,6 +1271,7 @@ struct Batch final : BatchBase {
   explicit Batch(int ns) : nsub(ns) {}
   ~Batch() override {
     if (st) (void)hipStreamSynchronize(st);
+    DeviceLock lk(device_mutex());
     if (gexec) (void)hipGraphExecDestroy(gexec);
     for (int i = 0; i < 2; ++i) {
       if (h_c[i]) (void)hipHostFree(h_c[i]);
@@ -1231,10 +1282,15 @@ struct Batch final : BatchBase {
 
   bool accepts(const GridBase* g) const override {
     const auto* t = dynamic_cast<const Grid<T>*>(g);
-    // one stage sequence serves every member: the Dormand-Prince pair
-    return t && t->params_set && !t->p.demag && !t->p.elastic && t->p.nsub == nsub &&
-           t->p.solver == RK_DP45 && !t->p.bc_eq6 &&
-           !(t->p.ngrains > 0 && t->p.grain_exch_reduction != 0.0);
+    // one stage sequence serves every member: the Dormand-Prince pair; a
+    // member with demag joins the batched demag passes (open boundaries,
+    // lines that fit one block of the LDS kernels)
+    if (!t || !t->params_set || t->p.elastic || t->p.nsub != nsub || t->p.solver != RK_DP45 ||
+        t->p.bc_eq6 || (t->p.ngrains > 0 && t->p.grain_exch_reduction != 0.0))
+      return false;
+    if (t->p.demag)
+      return t->demag_built && t->p.pbc[0] == 0 && t->p.pbc[1] == 0 && demag_multi_fits(t->plan);
+    return true;
   }
   int size() const override { return (int)mem.size(); }
   int in_flight() const override { return count; }
@@ -1245,7 +1301,10 @@ struct Batch final : BatchBase {
   }
 
   int ensure_stream() {
-    if (!st) MMP_HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    if (!st) {
+      DeviceLock lk(device_mutex());
+      MMP_HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    }
     for (int i = 0; i < 2; ++i)
       if (!ev[i]) MMP_HIP_TRY(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
     return 0;
@@ -1307,6 +1366,14 @@ struct Batch final : BatchBase {
       max_cells = std::max(max_cells, (long)g->N * g->p.nsub);
     }
     nwork = (int)work.size();
+    {
+      std::vector<DemagMember<T>> dms;
+      for (Grid<T>* g : mem)
+        if (g->p.demag)
+          dms.push_back({&g->plan, g->db, g->dtbl.p, g->dctrl.p, (T)g->p.sub[0].Ms, g->ms_of(1),
+                         g->ms_of(2), g->p.nsub});
+      if (int rc = dm.build(dms, st)) return rc;
+    }
     d_args.release(); d_work.release(); d_step.release(); d_cptr.release(); d_cgather.release();
     if (d_args.alloc(n) || d_work.alloc(work.size()) || d_step.alloc(n) || d_cptr.alloc(n) ||
         d_cgather.alloc(n)) {
@@ -1323,6 +1390,7 @@ struct Batch final : BatchBase {
                                st));
     MMP_HIP_TRY(hipStreamSynchronize(st));  // host vectors go out of scope
     if (n > h_cap) {
+      DeviceLock lk(device_mutex());
       for (int i = 0; i < 2; ++i) {
         if (h_c[i]) (void)hipHostFree(h_c[i]);
         h_c[i] = nullptr;
@@ -1336,8 +1404,10 @@ struct Batch final : BatchBase {
 
   void attempt() {
     constexpr int ns = RK::t[RK_DP45].ns;
-    for (int s = 2; s <= ns; ++s)
+    for (int s = 2; s <= ns; ++s) {
+      dm.launch(s, st);
       launch_field_multi<T>(d_args.p, d_work.p, nwork, nsub, s, 0, st);
+    }
     launch_step_multi<T>(d_step.p, (int)mem.size(), max_cells, st);
   }
 
@@ -1350,6 +1420,7 @@ struct Batch final : BatchBase {
     int left = attempts;
     if (left >= kGA) {
       if (!gexec) {
+        DeviceLock lk(device_mutex());
         hipGraph_t g = nullptr;
         MMP_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         for (int i = 0; i < kGA; ++i) attempt();

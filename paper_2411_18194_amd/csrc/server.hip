@@ -2,16 +2,24 @@
 //
 // Requests arrive on any thread (mmp_submit) and wait in a FIFO queue.  A
 // worker thread admits the queue head whenever a slot is free and its
-// device footprint fits the remaining HBM budget, builds its grid (own
-// stream, own demag kernel), and then round-robins over the active
-// requests: each gets a chunk of Dormand-Prince attempts enqueued on its
-// stream, so the kernels of different requests overlap on the device while
-// every request keeps its own device-side step control.  A request that
-// finishes is reduced (average m, total energy), its memory returned, and
-// the next queued request is admitted at once.  Results are read with
-// mmp_poll.  Each request runs exactly the kernels it would run alone, so
-// its result does not depend on what else is in flight.
+// device footprint fits the remaining HBM budget; a builder thread then
+// sets its grid up (own stream, own FP64 demag tensor and spectrum, first
+// stage) while the worker keeps the running requests going.  Requests that
+// can share one stage sequence (Dormand-Prince, no elasticity; with or
+// without demag) join a batch per sublattice count: every stage of all
+// members is one launch per demag pass and one field launch over device
+// work tables, 8 attempts per captured graph.  The others get chunks of
+// attempts on their own streams, round robin, so the kernels of different
+// requests overlap on the device.  Every request keeps its own device-side
+// step control and runs the arithmetic it would run alone, so its result
+// does not depend on what else is in flight.  A request that finishes is
+// reduced on the device (average m per sublattice, total energy), its
+// memory returned, and the next queued request admitted.  Results are read
+// with mmp_poll.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <string>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -38,7 +46,10 @@ struct Req {
   int64_t footprint = 0;
   mmp_grid g = nullptr;
   int chunk = 8;
+  bool try_batch = false;
   bool batched = false;
+  int setup_rc = 0;
+  std::string err;   // message of the call that failed the request
 };
 
 // Device footprint of a request: the buffers Grid<T>::alloc_layout makes
@@ -69,7 +80,12 @@ struct mmp_server_s {
   mmp_server_opts o{};
   std::mutex mu;
   std::condition_variable cv;
-  std::deque<Req*> queue;
+  std::deque<Req*> queue;       // submitted, waiting for admission
+  std::deque<Req*> to_build;    // admitted, grid not yet set up
+  std::deque<Req*> built;       // set up, not yet placed by the worker
+  int building = 0;             // admitted and not yet placed
+  std::condition_variable bcv;  // wakes the builder
+  std::thread builder;
   std::vector<Req*> active;
   std::map<uint64_t, mmp_result> done;
   std::map<uint64_t, int> known;
@@ -95,35 +111,30 @@ struct mmp_server_s {
   }
 
   void finish(Req* q, int status) {
+    if (status < 0 && q->err.empty()) q->err = mmp_last_error();
+    if (status < 0 && std::getenv("MMP_SERVER_LOG"))
+      std::fprintf(stderr, "mmp server: request %llu failed (%d): %s\n",
+                   (unsigned long long)q->ticket, status, q->err.c_str());
     mmp_result res{};
     res.status = status;
     res.nsub = q->r.params.nsub;
     res.t_submit = q->t_submit;
     res.t_admit = q->t_admit;
-    if (q->g && status == MMP_OK) {
-      mmp_step_info info{};
-      (void)info;
-      const int64_t N = (int64_t)q->r.nx * q->r.ny * q->r.nz;
-      std::vector<double> m((size_t)res.nsub * 3 * N);
-      double t = 0, dt = 0;
-      int rc = mmp_get_state(q->g, m.data(), nullptr, nullptr, &t, &dt);
-      double e[MMP_NENERGY] = {};
-      if (rc == MMP_OK) rc = mmp_eval_heff(q->g, 0, nullptr, e);
+    if (q->g && q->g->impl && status == MMP_OK) {
+      // averages and energies reduced on the device: 19 doubles come back,
+      // not the state
+      double avg[9] = {}, e[MMP_NENERGY] = {};
+      const int rc = q->g->impl->summary(avg, e);
       if (rc == MMP_OK) {
         for (int s = 0; s < res.nsub; ++s)
-          for (int c = 0; c < 3; ++c) {
-            double acc = 0;
-            const double* p = m.data() + ((size_t)s * 3 + c) * N;
-            for (int64_t i = 0; i < N; ++i) acc += p[i];
-            res.m_avg[s][c] = acc / (double)N;
-          }
+          for (int c = 0; c < 3; ++c) res.m_avg[s][c] = avg[s * 3 + c];
         double et = 0;
         for (int k = 0; k < MMP_NENERGY; ++k) et += e[k];
         res.energy = et;
       } else {
         res.status = rc;
       }
-      // the stream is idle after mmp_get_state: drain the chunks in flight
+      // the stream is idle after the summary: drain the chunks in flight
       long long steps = 0, rejects = 0;
       bool fin = false;
       int st = 0;
@@ -143,7 +154,13 @@ struct mmp_server_s {
     delete q;
   }
 
-  int start_request(Req* q) {
+  // Builder thread: creates an admitted request's grid (parameters, demag
+  // tensor and spectrum, state, first stage) on the grid's own stream while
+  // the worker keeps the running requests' chunks flowing.
+  int setup_request(Req* q) {
+    // the set-up allocates and copies synchronously: it must not overlap a
+    // graph capture on the worker thread
+    DeviceLock lk(device_mutex());
     mmp_grid g = nullptr;
     int rc = mmp_grid_create(q->r.nx, q->r.ny, q->r.nz, q->r.cellsize, &g);
     if (rc) return rc;
@@ -154,12 +171,49 @@ struct mmp_server_s {
     p.grain = q->grain.empty() ? nullptr : q->grain.data();
     p.grain_axes = q->gaxes.empty() ? nullptr : q->gaxes.data();
     if ((rc = mmp_set_params(g, &p))) return rc;
+    q->try_batch = o.batch && !p.elastic && (p.nsub == 1 || p.nsub == 2);
+    if (q->try_batch && p.demag) {
+      // the batch runs every demag pass through the LDS kernels: the
+      // request's own first stage (and its final energy) uses them too, so
+      // its result does not depend on whether it was batched
+      mmp_plan pl{};
+      pl.struct_size = sizeof(pl);
+      if (mmp_get_plan(g, &pl) == MMP_OK) {
+        pl.lds_axes = 7;
+        (void)mmp_set_plan(g, &pl);
+      }
+    }
     if ((rc = mmp_set_state(g, q->m0.data(), nullptr, nullptr, 0.0))) return rc;
-    if ((rc = g->impl->run_begin(q->r.t_relax))) return rc;
-    if (o.batch && !p.demag && !p.elastic && (p.nsub == 1 || p.nsub == 2)) {
-      BatchState& B = batches[p.nsub - 1];
-      if (!B.b) B.b = make_batch(o.precision, p.nsub);
-      if (B.b->accepts(g->impl.get())) {
+    return g->impl->run_begin(q->r.t_relax);
+  }
+
+  void builder_loop() {
+    while (true) {
+      Req* q = nullptr;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        bcv.wait(lk, [&] { return stop.load() || !to_build.empty(); });
+        if (stop.load()) return;   // the rest is finished at shutdown
+        q = to_build.front();
+        to_build.pop_front();
+      }
+      q->setup_rc = setup_request(q);
+      if (q->setup_rc) q->err = std::string("set-up: ") + mmp_last_error();
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        built.push_back(q);
+      }
+      cv.notify_all();
+    }
+  }
+
+  // Worker: a set-up request joins its batch or starts its own chunks.
+  int place_request(Req* q) {
+    if (q->try_batch) {
+      const int ns = q->r.params.nsub;
+      BatchState& B = batches[ns - 1];
+      if (!B.b) B.b = make_batch(o.precision, ns);
+      if (B.b->accepts(q->g->impl.get())) {
         q->batched = true;
         B.joining.push_back(q);
         B.draining = true;
@@ -170,8 +224,8 @@ struct mmp_server_s {
     // chunks stay in flight so the device never waits for the host
     const int64_t N = (int64_t)q->r.nx * q->r.ny * q->r.nz * q->r.params.nsub;
     q->chunk = (int)std::max<int64_t>(8, std::min<int64_t>(64, (int64_t(1) << 21) / N));
-    if ((rc = g->impl->run_chunk(q->chunk))) return rc;
-    return g->impl->run_chunk(q->chunk);
+    if (int rc = q->g->impl->run_chunk(q->chunk)) return rc;
+    return q->g->impl->run_chunk(q->chunk);
   }
 
   static bool member_done(Req* q, int* status) {
@@ -254,6 +308,20 @@ struct mmp_server_s {
     return any;
   }
 
+  // requests admitted but not yet placed, at shutdown
+  void finish_unplaced() {
+    std::vector<Req*> left;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      left.assign(to_build.begin(), to_build.end());
+      left.insert(left.end(), built.begin(), built.end());
+      to_build.clear();
+      built.clear();
+      building = 0;
+    }
+    for (Req* q : left) finish(q, MMP_E_STATE);
+  }
+
   int batched_count() const {
     return (int)(batches[0].members.size() + batches[0].joining.size() +
                  batches[1].members.size() + batches[1].joining.size());
@@ -261,26 +329,44 @@ struct mmp_server_s {
 
   void loop() {
     while (!stop.load()) {
-      // admission
-      while (true) {
-        Req* q = nullptr;
-        {
-          std::lock_guard<std::mutex> lk(mu);
-          const int busy = (int)active.size() + batched_count();
-          if (queue.empty() || busy >= o.max_active) break;
+      // admission: the queue head goes to the builder once a slot is free
+      // and its footprint fits the budget (or nothing else runs)
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        while (!queue.empty()) {
+          const int busy = (int)active.size() + batched_count() + building;
+          if (busy >= o.max_active) break;
           Req* h = queue.front();
           if (used + h->footprint > o.hbm_budget && busy > 0) break;
           queue.pop_front();
           used += h->footprint;
-          q = h;
+          h->t_admit = now();
+          to_build.push_back(h);
+          ++building;
         }
-        q->t_admit = now();
-        const int rc = start_request(q);
-        if (rc) finish(q, rc);
-        else if (!q->batched) active.push_back(q);
+      }
+      bcv.notify_one();
+      // requests the builder has set up join their batch or start chunks
+      bool any = false;
+      {
+        std::vector<Req*> ready;
+        {
+          std::lock_guard<std::mutex> lk(mu);
+          ready.assign(built.begin(), built.end());
+          built.clear();
+        }
+        for (Req* q : ready) {
+          any = true;
+          const int rc = q->setup_rc ? q->setup_rc : place_request(q);
+          {
+            std::lock_guard<std::mutex> lk(mu);
+            --building;
+          }
+          if (rc) finish(q, rc);
+          else if (!q->batched) active.push_back(q);
+        }
       }
       // progress
-      bool any = false;
       for (auto& B : batches) any |= step_batch(B);
       for (size_t i = 0; i < active.size();) {
         Req* q = active[i];
@@ -339,6 +425,7 @@ mmp_status mmp_server_create(const mmp_server_opts* o, mmp_server* out) {
     mmp_server s = new mmp_server_s();
     s->o = *o;
     s->worker = std::thread([s] { s->loop(); });
+    s->builder = std::thread([s] { s->builder_loop(); });
     *out = s;
     return MMP_OK;
   } catch (...) {
@@ -408,7 +495,10 @@ mmp_status mmp_server_destroy(mmp_server s) {
   if (!s) return MMP_OK;
   s->stop.store(true);
   s->cv.notify_all();
+  s->bcv.notify_all();
   if (s->worker.joinable()) s->worker.join();
+  if (s->builder.joinable()) s->builder.join();
+  s->finish_unplaced();
   for (Req* q : s->queue) delete q;
   delete s;
   return MMP_OK;

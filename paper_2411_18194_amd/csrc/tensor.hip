@@ -502,6 +502,7 @@ int demag_kernel_build(const DemagPlan& p, double dx, double dy, double dz, doub
   } else if (fill_tensor(p.nx, p.ny, p.nz, dx, dy, dz, n6, st)) {
     return -1;
   }
+  DeviceLock lk(device_mutex());
   double *f1 = nullptr, *f2 = nullptr, *tabs = nullptr;
   const size_t n1 = (size_t)6 * p.nz * p.ny * p.Hx;
   const size_t n2 = (size_t)6 * p.nz * p.Hy * p.Hx;

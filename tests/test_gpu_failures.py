@@ -190,11 +190,14 @@ def test_server_recovers_from_a_failed_batch():
     inject.restype = None
     srv = mmp.Server(hbm_budget=8 << 30, max_active=8, precision=mmp.FP32, batch=True)
     try:
-        inject(1)
+        # one injected failure per batch the three requests can form (they
+        # may be placed together or one by one)
+        inject(3)
         reqs = [_afm(seed=50 + i) for i in range(3)]
         tk = [srv.submit(p, m, 2e-12) for p, m in reqs]
         res = [srv.wait(t, timeout=120.0) for t in tk]
         assert all(r.status == -2 for r in res)
+        inject(0)
         # later requests run on a fresh batch, as they would alone
         tk = [srv.submit(p, m, 2e-12) for p, m in reqs]
         res = [srv.wait(t, timeout=120.0) for t in tk]
