@@ -26,8 +26,13 @@ Before the warm-up the demag plan is autotuned (candidate pads and launch
 shapes timed on the device, the fastest installed), as a caller would do
 once per shape; --no-autotune keeps the default plan.
 
+Serving: a prefix of the seeded request stream through the library's
+server (FP32, continuous batching), time-boxed, then at 0.8x the measured
+capacity, beside plain sequential FP64 on a subsample.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-fp64]
-       [--no-cpu-baseline] [--no-prof] [--no-autotune]
+       [--no-cpu-baseline] [--no-prof] [--no-autotune] [--serve N]
+       [--serve-seconds S] [--serve-active A] [--serve-baseline K]
 """
 from __future__ import annotations
 
@@ -189,68 +194,177 @@ def copy_rate(nbytes, reps=10):
     return 2 * n * 4 / sec / 1e9
 
 
-def cpu_baseline():
-    """FP64 oracle on a 256x256x16 block of the same film (1/4 of the cells)."""
+def gpu_first_torque():
+    """dm/dt of every term at the film's initial state, FP32 and FP64 grids
+    (the FP32 grid holds the state rounded to float32)."""
+    from paper_2411_18194_amd import inputs, mmp
+
+    p, m0 = inputs.config_c2()
+    out = {}
+    for prec, name in ((mmp.FP32, "f32"), (mmp.FP64, "f64")):
+        g = mmp.Grid(p, prec)
+        g.set_state(m0)
+        out[name] = g.eval_heff(mmp.T_ALL | mmp.T_ZL | mmp.OUT_TORQUE)[0].astype(np.float64)
+        g.close()
+    return out
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(gpu_torque=None):
+    """FP64 oracle on the full 512x512x16 film: three single-stage
+    evaluations (field + torque of every cell, then one Runge-Kutta stage
+    combination), FFTs on every host core, then one on a single core.  The
+    first two evaluations are of the initial state in FP64 and rounded to
+    float32: the GPU's first-stage torques of the same states are checked
+    against them (max |d tau| / max |tau|)."""
+    import numpy
+    import scipy
+
     from oracle.system import Problem
     from paper_2411_18194_amd import inputs
 
     cores = len(os.sched_getaffinity(0))
-    n = (256, 256, 16)
-    p = inputs.base_params(n, (2e-9,) * 3)
-    full, _ = inputs.config_c2(n=(8, 8, 16))
-    for k in ("Ms", "A11", "alpha", "Ku1", "anis_u", "Dint", "dmi_layer", "B_ext", "demag"):
-        p[k] = full[k]
-    m = inputs.smoothed_random_unit(inputs.rng(2), 1, n)
+    p, m64 = inputs.config_c2()
+    m32 = m64.astype(np.float32).astype(np.float64)
+    N = p["n"][0] * p["n"][1] * p["n"][2]
+    t_setup = time.perf_counter()
     P = Problem(p, demag_workers=cores)
+    t_setup = time.perf_counter() - t_setup
     dt = inputs.c2_fixed_dt()
-    y = P.initial_state(m)
-    y, _ = P.run_fixed(y, 0.0, dt, 1)          # warm-up (also fills the FSAL stage)
-    t0 = time.perf_counter()
-    nsteps = 6   # ~10 s of host work
-    y, _ = P.run_fixed(y, 0.0, dt, nsteps)
-    sec = time.perf_counter() - t0
-    N = n[0] * n[1] * n[2]
-    return {"value": N * 6 * nsteps / sec, "unit": "cell-field-evals/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{n[0]}x{n[1]}x{n[2]} block of the 512x512x16 film (same material, "
-                      f"own open-boundary demag), {nsteps} fixed DP45 steps = {6 * nsteps} "
-                      f"field evaluations, FP64 numpy/scipy (FFT on {cores} threads, "
-                      f"element-wise work on 1)", "seconds": round(sec, 2)}
+
+    def stage(m):
+        t0 = time.perf_counter()
+        k = P.rhs(0.0, [m])
+        y2 = P.stepper._combine([m], [k], [0.2], dt)
+        return time.perf_counter() - t0, k[0], y2
+
+    secs, acc = [], {}
+    for name, m in (("f64", m64), ("f32", m32), ("f64", m64)):
+        sec, tau, _ = stage(m)
+        secs.append(sec)
+        if gpu_torque is not None and name not in acc:
+            ref = tau
+            acc[name] = float(np.abs(gpu_torque[name] - ref).max() / np.abs(ref).max())
+        _progress(f"cpu baseline: evaluation {len(secs)} took {sec:.1f} s")
+    P.demag.workers = 1
+    sec1, _, _ = stage(m64)
+    _progress(f"cpu baseline: single-core evaluation took {sec1:.1f} s")
+    med = float(np.median(secs))
+    out = {"value": N / med, "unit": "cell-field-evals/s", "cores": cores, "kind": "oracle",
+           "sample": "the full 512x512x16 film, 3 single-stage evaluations (field + torque of "
+                     "every cell + one DP45 stage combination), median; FP64 numpy/scipy "
+                     f"(FFT on {cores} threads, element-wise work on 1)",
+           "seconds": [round(x, 2) for x in secs], "setup_s": round(t_setup, 1),
+           "value_1core": N / sec1, "seconds_1core": round(sec1, 2),
+           "cpu_model": _cpu_model(), "numpy": numpy.__version__, "scipy": scipy.__version__}
+    if acc:
+        out["gpu_first_stage_torque_rel_err"] = acc
+    return out
+
+
+def accuracy_c2crop():
+    """The 64x64x4 crop of the film (its own open-boundary system) run for
+    0.1 ns of fixed DP45 steps in FP32 and FP64, against the FP64 oracle's
+    stored run of the same steps (tests/golden/traj_c2crop.*): max over cells
+    of |m_gpu - m_ref| and |E_gpu - E_ref| / sum |E_ref,term| at the end."""
+    from paper_2411_18194_amd import inputs, mmp
+
+    path = os.path.join(ROOT, "tests", "golden", "traj_c2crop")
+    if not os.path.exists(path + ".npz"):
+        return None
+    gold = np.load(path + ".npz")
+    with open(path + ".json") as fh:
+        meta = json.load(fh)
+    p, m0 = inputs.config_c2_crop()
+    out = {"workload": f"64x64x4 crop of the film, {meta['steps']} fixed DP45 steps of "
+                       f"{meta['dt']:.4g} s (0.1 ns), vs the FP64 oracle"}
+    for prec, name in ((mmp.FP32, "f32"), (mmp.FP64, "f64")):
+        g = mmp.Grid(p, prec)
+        g.set_state(m0)
+        g.run_fixed(meta["dt"], meta["steps"])
+        m = g.get_state()[0]
+        _, e = g.eval_heff(mmp.T_ALL, want_b=False)
+        g.close()
+        r = {"max_dm": float(np.linalg.norm(m - gold["m"].astype(np.float64), axis=1).max())}
+        if "energy" in gold:
+            ref = dict(zip([str(x) for x in gold["energy_names"]], gold["energy"]))
+            scale = sum(abs(v) for v in ref.values())
+            r["rel_energy_err"] = abs(sum(e.values()) - sum(ref.values())) / scale
+        out[name] = r
+    return out
 
 
 def _percentiles(lat):
+    if len(lat) == 0:
+        return (None, None)
     lat = np.sort(np.asarray(lat))
     return (float(np.percentile(lat, 50)), float(np.percentile(lat, 99)))
 
 
-def _serve_pass(reqs, states, precision, rate_scale, max_active, batch=True):
-    """Open-loop replay of the request stream through the server.
+def _stats(prefix, vals):
+    p50, p99 = _percentiles(vals)
+    return {prefix + "_p50_s": None if p50 is None else round(p50, 4),
+            prefix + "_p99_s": None if p99 is None else round(p99, 4)}
 
-    Request i is submitted at t_arrive[i] * rate_scale after the start (a
-    scale above 1 slows the arrivals down).  Latency = t_done - t_submit on
-    the server's clock."""
+
+def _serve_pass(reqs, states, precision, arrivals, box_s, max_active, batch=True):
+    """Open-loop replay through the library's server: request i is submitted
+    at arrivals[i] seconds after the start; results are collected until all
+    are done or box_s seconds have passed (the rest are counted as
+    unfinished).  Latency = t_done - t_submit, queue wait = t_admit -
+    t_submit, service = t_done - t_admit, on the server's clock."""
     from paper_2411_18194_amd import mmp
 
     srv = mmp.Server(hbm_budget=64 << 30, max_active=max_active, precision=precision,
                      batch=batch)
     t0 = srv.clock()
-    tickets = []
-    for r, m in zip(reqs, states):
-        while srv.clock() - t0 < r["t_arrive"] * rate_scale:
-            time.sleep(2e-4)
-        tickets.append(srv.submit(r["params"], m, r["t_relax"], tol=r["tol"]))
-    res = [srv.wait(t, timeout=900.0) for t in tickets]
+    tickets, res = [], {}
+    i = 0
+    while True:
+        now = srv.clock() - t0
+        while i < len(reqs) and arrivals[i] <= now:
+            tickets.append(srv.submit(reqs[i]["params"], states[i], reqs[i]["t_relax"],
+                                      tol=reqs[i]["tol"]))
+            i += 1
+        for k, t in enumerate(tickets):
+            if k not in res:
+                r = srv.poll(t)
+                if r is not None:
+                    res[k] = r
+        if len(res) == len(reqs) or now > box_s:
+            break
+        time.sleep(2e-3)
+    end = srv.clock() - t0
     srv.close()
-    bad = [x.status for x in res if x.status != 0]
+    done = [res[k] for k in sorted(res)]
+    bad = [x.status for x in done if x.status != 0]
     if bad:
         raise RuntimeError(f"serving: {len(bad)} requests failed: {bad[:5]}")
-    lat = [x.t_done - x.t_submit for x in res]
-    span = max(x.t_done for x in res) - min(x.t_submit for x in res)
-    p50, p99 = _percentiles(lat)
-    cells = sum(r["params"]["n"][0] * r["params"]["n"][1] * r["params"]["n"][2] for r in reqs)
-    steps = sum(x.steps + x.rejects for x in res)
-    return {"solves_per_s": len(res) / span, "p50_s": p50, "p99_s": p99, "makespan_s": span,
-            "requests": len(res), "attempts": int(steps), "cells": int(cells)}
+    lat = [x.t_done - x.t_submit for x in done]
+    span = (max(x.t_done for x in done) - t0) if done else end
+    out = {"submitted": i, "completed": len(done), "unfinished": len(reqs) - len(done),
+           "time_box_s": box_s, "elapsed_s": round(end, 3),
+           "solves_per_s": round(len(done) / (span if len(done) == len(reqs) else end), 4),
+           "attempts": int(sum(x.steps + x.rejects for x in done)),
+           "cells_done": int(sum(reqs[k]["params"]["n"][0] * reqs[k]["params"]["n"][1] *
+                                 reqs[k]["params"]["n"][2] for k in res))}
+    out.update(_stats("latency", lat))
+    out.update(_stats("queue", [x.t_admit - x.t_submit for x in done]))
+    out.update(_stats("service", [x.t_done - x.t_admit for x in done]))
+    if len(done) < len(reqs):
+        out["note"] = ("percentiles over the completed requests only; the unfinished ones "
+                       "had waited at least time_box_s - t_arrive when the box closed")
+    return out
 
 
 def _sequential_fp64(reqs, states):
@@ -275,48 +389,54 @@ def _sequential_fp64(reqs, states):
         start = max(t_free, r["t_arrive"])
         t_free = start + sv
         lat.append(t_free - r["t_arrive"])
-    p50, p99 = _percentiles(lat)
-    return {"solves_per_s": len(reqs) / sum(service), "p50_s": p50, "p99_s": p99,
-            "requests": len(reqs), "service_s": [round(x, 3) for x in service]}
+    out = {"solves_per_s": round(len(reqs) / sum(service), 4), "requests": len(reqs),
+           "service_s": [round(x, 3) for x in service]}
+    out.update(_stats("latency", lat))
+    return out
 
 
 def _progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_serve(count, max_active=8, baseline=0):
-    """Relaxation requests (a seeded prefix of the 4000-request stream at
-    200/s: 70 % FM with demag, 30 % two-sublattice AFM, 0.5 ns each) served
-    by the library's server in FP32; then the same requests re-timed with
-    arrivals slowed to 0.8 x the measured capacity."""
+def run_serve(count, box_s, max_active=16, baseline=0):
+    """A prefix of the seeded 4000-request stream (Poisson 200/s: 70 % FM
+    with demag, 30 % two-sublattice AFM, 0.5 ns of relaxation each) served by
+    the library's server in FP32 with continuous batching, arrivals at their
+    stream times, in a time box; then the same requests with arrivals at 0.8
+    times the capacity the first pass measured; then the first `baseline`
+    requests run one at a time in plain FP64 and, for a like-for-like ratio,
+    served in FP32."""
     from paper_2411_18194_amd import inputs, mmp
 
     reqs = inputs.request_stream(seed=5, count=count)
     states = [inputs.request_state(r) for r in reqs]
-    full = _serve_pass(reqs, states, mmp.FP32, 1.0, max_active)
-    _progress("serving: offered stream done")
-    # arrivals at 0.8 x capacity: scale the stream's mean rate (200/s) down
-    scale = 200.0 / (0.8 * full["solves_per_s"])
-    sus = _serve_pass(reqs, states, mmp.FP32, scale, max_active)
+    _progress(f"serving: {count} request states generated")
+    arr = np.array([r["t_arrive"] for r in reqs])
+    full = _serve_pass(reqs, states, mmp.FP32, arr, box_s, max_active)
+    _progress(f"serving: offered stream done ({full['completed']}/{count} in "
+              f"{full['elapsed_s']} s)")
+    cap = max(full["solves_per_s"], 1e-3)
+    rate = 0.8 * cap
+    # the stream's inter-arrival pattern, stretched to the lower mean rate
+    sus = _serve_pass(reqs, states, mmp.FP32, arr * (200.0 / rate), box_s, max_active)
     _progress("serving: 0.8 x capacity done")
     base = None
     if baseline > 0:
         base = _sequential_fp64(reqs[:baseline], states[:baseline])
         _progress("serving: sequential FP64 baseline done")
-        # the same subsample through the server, for a like-for-like ratio
-        sub = _serve_pass(reqs[:baseline], states[:baseline], mmp.FP32, 1.0, max_active)
-        base["served_fp32_same_requests"] = {k: round(v, 4) if isinstance(v, float) else v
-                                             for k, v in sub.items()}
-        base["note"] = (f"sequential plain FP64 timed on the first {baseline} requests only "
-                        "(a seeded subsample; the full list would take minutes)")
-    return {"workload": f"first {count} requests of the seeded c5 stream (Poisson 200/s, "
-                        "nx, ny log-uniform 32..512, nz log-uniform 1..8, 70 % FM with "
-                        "demag / 30 % AFM, 0.5 ns DP45 relaxation each, tol 1e-5)",
-            "precision": "f32", "max_active": max_active,
-            "offered": {k: round(v, 4) if isinstance(v, float) else v for k, v in full.items()},
-            "at_0.8_capacity": {k: round(v, 4) if isinstance(v, float) else v
-                                for k, v in sus.items()},
-            "arrival_rate_0.8_capacity_per_s": round(200.0 / scale, 3),
+        sub = _serve_pass(reqs[:baseline], states[:baseline], mmp.FP32, arr[:baseline],
+                          1e9, max_active)
+        base["served_fp32_same_requests"] = sub
+        base["served_fp32_speedup"] = round(sub["solves_per_s"] / base["solves_per_s"], 3)
+        base["note"] = (f"sequential plain FP64 timed on the first {baseline} requests of the "
+                        "prefix (a seeded subsample)")
+    return {"workload": f"first {count} requests of the seeded 4000-request stream (Poisson "
+                        "200/s, nx, ny log-uniform 32..512, nz log-uniform 1..8, cubic cells "
+                        "1-5 nm, 70 % FM with demag / 30 % two-sublattice AFM, 0.5 ns DP45 "
+                        "relaxation each, tol 1e-5)",
+            "precision": "f32", "max_active": max_active, "offered": full,
+            "at_0.8_capacity": dict(sus, arrival_rate_per_s=round(rate, 4)),
             "sequential_fp64": base}
 
 
@@ -402,10 +522,14 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-prof", action="store_true")
-    ap.add_argument("--serve", type=int, default=8,
-                    help="requests in the serving measurement (0 = skip)")
+    ap.add_argument("--serve", type=int, default=200,
+                    help="requests of the stream in the serving measurement (0 = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=45.0,
+                    help="time box of each serving pass")
+    ap.add_argument("--serve-active", type=int, default=16,
+                    help="requests on the device at once")
     ap.add_argument("--serve-baseline", type=int, default=3,
-                    help="requests of that list also run one at a time in FP64")
+                    help="first requests of that list also run one at a time in FP64")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default demag plan instead of timing candidates first")
     ap.add_argument("--copy-calib", action="store_true",
@@ -465,10 +589,18 @@ def main():
                        "fp32_speedup": round(r32["value"] / r64["value"], 3),
                        "plan": {k: v for k, v in r64["plan"].items() if k != "demag_ms"}}
     if args.serve > 0:
-        out["serving"] = run_serve(args.serve, baseline=min(args.serve_baseline, args.serve))
+        out["serving"] = run_serve(args.serve, args.serve_seconds, args.serve_active,
+                                   baseline=min(args.serve_baseline, args.serve))
+    acc = accuracy_c2crop()
+    if acc is not None:
+        out["accuracy"] = acc
+        _progress("accuracy check done")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(gpu_first_torque())
         _progress("CPU baseline done")
+        if "gpu_first_stage_torque_rel_err" in out["cpu_baseline"]:
+            out.setdefault("accuracy", {})["fullsize_first_stage_torque_rel_err"] = \
+                out["cpu_baseline"].pop("gpu_first_stage_torque_rel_err")
     print(json.dumps(out), flush=True)
 
 

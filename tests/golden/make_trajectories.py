@@ -3,7 +3,8 @@
 Runs only the FP64 CPU oracle (oracle/) on the seeded crop systems from
 paper_2411_18194_amd.inputs and stores, per system, the state after every
 `every` steps' worth of time (<m> per sublattice) and the full final state
-rounded to float32 (enough for a 1e-4 comparison).  Usage:
+rounded to float32 (enough for a 1e-4 comparison), with the per-term
+energies of the final FP64 state.  Usage:
 
     python tests/golden/make_trajectories.py [c2crop c3crop c4crop]
 
@@ -46,6 +47,11 @@ def run(name):
         samples.append([t] + [float(v) for v in y[0].mean(axis=(2, 3, 4)).ravel()])
         print(f"{name}: {done}/{steps} steps, {time.perf_counter() - t0:.0f} s", flush=True)
     out = {"m": y[0].astype(np.float32), "samples": np.array(samples)}
+    # energies of the final FP64 state, per term (joules), for the relative
+    # energy error of a run against this one
+    E = P.energies(*y) if len(y) > 1 else P.energies(y[0])
+    out["energy_names"] = np.array(list(E.keys()))
+    out["energy"] = np.array([E[k] for k in E])
     if len(y) > 1:
         out["u"] = y[1].astype(np.float32)
         out["v"] = y[2].astype(np.float32)
