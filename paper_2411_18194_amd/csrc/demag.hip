@@ -53,7 +53,7 @@ struct XArgs {
 // The pass bodies take the block's coordinates (and the stage) as
 // arguments: the single-grid kernels pass blockIdx, the batched kernels
 // the entry of their work table.
-template <typename T, bool P2>
+template <typename T, bool P2, bool TWL>
 __device__ __forceinline__ void fftx_fwd_body(const XArgs<T>& a, int stage, int bx, int by,
                                               int bz) {
   using V = cpx<T>;
@@ -85,8 +85,15 @@ __device__ __forceinline__ void fftx_fwd_body(const XArgs<T>& a, int stage, int 
     }
     buf[q * a.Px + x] = cmk<T>(re, im);
   }
+  const V* tw = a.tw;
+  if constexpr (TWL) {
+    // the twiddle table in LDS beside the lines: every stage reads it there
+    V* twl = buf + (nl * a.Px);
+    for (int i = tid; i < a.Px; i += nthr) twl[i] = a.tw[i];
+    tw = twl;
+  }
   __syncthreads();
-  lds_fft<T, false, P2>(buf, a.tw, a.Px, nl, a.Px, a.rad.n, a.rad.code, tid, nthr);
+  lds_fft<T, false, P2>(buf, tw, a.Px, nl, a.Px, a.rad.n, a.rad.code, tid, nthr);
   // unpack the two real spectra and store them transposed
   V* out = a.S1 + ((long)(c * a.nz + z) * a.Hx) * a.ldy + y0;
   for (int idx = tid; idx < nl * a.Hx; idx += nthr) {
@@ -103,12 +110,12 @@ __device__ __forceinline__ void fftx_fwd_body(const XArgs<T>& a, int stage, int 
   }
 }
 
-template <typename T, bool P2>
+template <typename T, bool P2, bool TWL>
 __global__ void k_fftx_fwd(XArgs<T> a) {
-  fftx_fwd_body<T, P2>(a, a.stage, blockIdx.x, blockIdx.y, blockIdx.z);
+  fftx_fwd_body<T, P2, TWL>(a, a.stage, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
-template <typename T, bool P2>
+template <typename T, bool P2, bool TWL>
 __device__ __forceinline__ void fftx_inv_body(const XArgs<T>& a, int bx, int by, int bz) {
   using V = cpx<T>;
   if (ctrl_stopped(a.ctrl)) return;
@@ -126,8 +133,15 @@ __device__ __forceinline__ void fftx_inv_body(const XArgs<T>& a, int bx, int by,
     if (kx > 0 && 2 * kx < a.Px)
       buf[q * a.Px + a.Px - kx] = cmk<T>(xa.x + xb.y, xb.x - xa.y);
   }
+  const V* tw = a.tw;
+  if constexpr (TWL) {
+    // the twiddle table in LDS beside the lines: every stage reads it there
+    V* twl = buf + (nl * a.Px);
+    for (int i = tid; i < a.Px; i += nthr) twl[i] = a.tw[i];
+    tw = twl;
+  }
   __syncthreads();
-  lds_fft<T, true, P2>(buf, a.tw, a.Px, nl, a.Px, a.rad.n, a.rad.code, tid, nthr);
+  lds_fft<T, true, P2>(buf, tw, a.Px, nl, a.Px, a.rad.n, a.rad.code, tid, nthr);
   const long N = (long)a.nx * a.ny * a.nz;
   T* out = a.Bd + (long)c * N + (long)z * a.ny * a.nx;
   for (int idx = tid; idx < nl * a.nx; idx += nthr) {
@@ -139,9 +153,9 @@ __device__ __forceinline__ void fftx_inv_body(const XArgs<T>& a, int bx, int by,
   }
 }
 
-template <typename T, bool P2>
+template <typename T, bool P2, bool TWL>
 __global__ void k_fftx_inv(XArgs<T> a) {
-  fftx_inv_body<T, P2>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+  fftx_inv_body<T, P2, TWL>(a, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // --------------------------------------------------------------- y pass --
@@ -155,7 +169,7 @@ struct YArgs {
   Rad rad;
 };
 
-template <typename T, bool INV, bool P2>
+template <typename T, bool INV, bool P2, bool TWL>
 __device__ __forceinline__ void ffty_body(const YArgs<T>& a, int bx) {
   using V = cpx<T>;
   if (ctrl_stopped(a.ctrl)) return;
@@ -170,8 +184,15 @@ __device__ __forceinline__ void ffty_body(const YArgs<T>& a, int bx) {
     if (gl < a.nlines && e < a.nvalid_in) v = a.in[(long)gl * a.ld_in + e];
     buf[q * a.L + e] = v;
   }
+  const V* tw = a.tw;
+  if constexpr (TWL) {
+    // the twiddle table in LDS beside the lines: every stage reads it there
+    V* twl = buf + (a.nl * a.L);
+    for (int i = tid; i < a.L; i += nthr) twl[i] = a.tw[i];
+    tw = twl;
+  }
   __syncthreads();
-  lds_fft<T, INV, P2>(buf, a.tw, a.L, a.nl, a.L, a.rad.n, a.rad.code, tid, nthr);
+  lds_fft<T, INV, P2>(buf, tw, a.L, a.nl, a.L, a.rad.n, a.rad.code, tid, nthr);
   for (int idx = tid; idx < a.nl * a.nvalid_out; idx += nthr) {
     const int q = idx / a.nvalid_out, e = idx - q * a.nvalid_out;
     const int gl = l0 + q;
@@ -179,9 +200,9 @@ __device__ __forceinline__ void ffty_body(const YArgs<T>& a, int bx) {
   }
 }
 
-template <typename T, bool INV, bool P2>
+template <typename T, bool INV, bool P2, bool TWL>
 __global__ void k_ffty(YArgs<T> a) {
-  ffty_body<T, INV, P2>(a, blockIdx.x);
+  ffty_body<T, INV, P2, TWL>(a, blockIdx.x);
 }
 
 // Symmetric 3x3 multiply with the octant kernel; sy/sz flip the odd parts.
@@ -214,7 +235,7 @@ struct M2Args {
   Rad rad;
 };
 
-template <typename T, bool P2>
+template <typename T, bool P2, bool TWL>
 __device__ __forceinline__ void ffty_mul2d_body(const M2Args<T>& a, int bx) {
   using V = cpx<T>;
   if (ctrl_stopped(a.ctrl)) return;
@@ -232,8 +253,15 @@ __device__ __forceinline__ void ffty_mul2d_body(const M2Args<T>& a, int bx) {
     if (kx < a.Hx && e < a.ny) v = a.S1[((long)c * a.Hx + kx) * a.ldy + e];
     buf[line * L + e] = v;
   }
+  const V* tw = a.tw;
+  if constexpr (TWL) {
+    // the twiddle table in LDS beside the lines: every stage reads it there
+    V* twl = buf + (nl * L);
+    for (int i = tid; i < L; i += nthr) twl[i] = a.tw[i];
+    tw = twl;
+  }
   __syncthreads();
-  lds_fft<T, false, P2>(buf, a.tw, L, nl, L, a.rad.n, a.rad.code, tid, nthr);
+  lds_fft<T, false, P2>(buf, tw, L, nl, L, a.rad.n, a.rad.code, tid, nthr);
   const long kstride = (long)a.Hx * a.Hy;
   for (int idx = tid; idx < a.nk * L; idx += nthr) {
     const int j = idx / L, ky = idx - j * L;
@@ -250,7 +278,7 @@ __device__ __forceinline__ void ffty_mul2d_body(const M2Args<T>& a, int bx) {
     buf[(2 * a.nk + j) * L + ky] = mz;
   }
   __syncthreads();
-  lds_fft<T, true, P2>(buf, a.tw, L, nl, L, a.rad.n, a.rad.code, tid, nthr);
+  lds_fft<T, true, P2>(buf, tw, L, nl, L, a.rad.n, a.rad.code, tid, nthr);
   for (int idx = tid; idx < nl * a.ny; idx += nthr) {
     const int line = idx / a.ny, e = idx - line * a.ny;
     const int c = line / a.nk, j = line - c * a.nk;
@@ -259,9 +287,9 @@ __device__ __forceinline__ void ffty_mul2d_body(const M2Args<T>& a, int bx) {
   }
 }
 
-template <typename T, bool P2>
+template <typename T, bool P2, bool TWL>
 __global__ void k_ffty_mul2d(M2Args<T> a) {
-  ffty_mul2d_body<T, P2>(a, blockIdx.x);
+  ffty_mul2d_body<T, P2, TWL>(a, blockIdx.x);
 }
 
 // 3-D grids: z forward, multiply, z inverse for tk ky values of one kx.
@@ -275,7 +303,7 @@ struct ZArgs {
   Rad rad;
 };
 
-template <typename T, bool P2>
+template <typename T, bool P2, bool TWL>
 __device__ __forceinline__ void fftz_mul_body(const ZArgs<T>& a, int bx, int by) {
   using V = cpx<T>;
   if (ctrl_stopped(a.ctrl)) return;
@@ -296,8 +324,15 @@ __device__ __forceinline__ void fftz_mul_body(const ZArgs<T>& a, int bx, int by)
     if (z < a.nz && ky0 + j < a.Py) v = base[c * cstride + z * zstride + j];
     buf[(c * a.tk + j) * a.ls + z] = v;
   }
+  const V* tw = a.tw;
+  if constexpr (TWL) {
+    // the twiddle table in LDS beside the lines: every stage reads it there
+    V* twl = buf + (nl * a.ls);
+    for (int i = tid; i < L; i += nthr) twl[i] = a.tw[i];
+    tw = twl;
+  }
   __syncthreads();
-  lds_fft<T, false, P2>(buf, a.tw, L, nl, a.ls, a.rad.n, a.rad.code, tid, nthr);
+  lds_fft<T, false, P2>(buf, tw, L, nl, a.ls, a.rad.n, a.rad.code, tid, nthr);
   const long kstride = (long)a.Hz * a.Hx * a.Hy;
   for (int idx = tid; idx < a.tk * L; idx += nthr) {
     const int j = idx % a.tk, kz = idx / a.tk;
@@ -316,7 +351,7 @@ __device__ __forceinline__ void fftz_mul_body(const ZArgs<T>& a, int bx, int by)
     buf[(2 * a.tk + j) * a.ls + kz] = mz;
   }
   __syncthreads();
-  lds_fft<T, true, P2>(buf, a.tw, L, nl, a.ls, a.rad.n, a.rad.code, tid, nthr);
+  lds_fft<T, true, P2>(buf, tw, L, nl, a.ls, a.rad.n, a.rad.code, tid, nthr);
   V* obase = a.S2 + (long)kx * a.Py + ky0;
   for (int idx = tid; idx < 3 * a.tk * a.nz; idx += nthr) {
     const int j = idx % a.tk;
@@ -326,9 +361,9 @@ __device__ __forceinline__ void fftz_mul_body(const ZArgs<T>& a, int bx, int by)
   }
 }
 
-template <typename T, bool P2>
+template <typename T, bool P2, bool TWL>
 __global__ void k_fftz_mul(ZArgs<T> a) {
-  fftz_mul_body<T, P2>(a, blockIdx.x, blockIdx.y);
+  fftz_mul_body<T, P2, TWL>(a, blockIdx.x, blockIdx.y);
 }
 
 // --------------------------------------------------------- batched passes --
@@ -342,38 +377,41 @@ template <typename T>
 __global__ __launch_bounds__(kMultiThreads) void k_fftx_fwd_multi(
     const XArgs<T>* __restrict__ args, const int4* __restrict__ work, int stage) {
   const int4 w = work[blockIdx.x];
-  fftx_fwd_body<T, false>(args[w.x], stage, w.y, w.z, w.w);
+  fftx_fwd_body<T, false, true>(args[w.x], stage, w.y, w.z, w.w);
 }
 
 template <typename T>
 __global__ __launch_bounds__(kMultiThreads) void k_fftx_inv_multi(
     const XArgs<T>* __restrict__ args, const int4* __restrict__ work) {
   const int4 w = work[blockIdx.x];
-  fftx_inv_body<T, false>(args[w.x], w.y, w.z, w.w);
+  fftx_inv_body<T, false, true>(args[w.x], w.y, w.z, w.w);
 }
 
 template <typename T, bool INV>
 __global__ __launch_bounds__(kMultiThreads) void k_ffty_multi(const YArgs<T>* __restrict__ args,
                                                               const int4* __restrict__ work) {
   const int4 w = work[blockIdx.x];
-  ffty_body<T, INV, false>(args[w.x], w.y);
+  ffty_body<T, INV, false, true>(args[w.x], w.y);
 }
 
 template <typename T>
 __global__ __launch_bounds__(kMultiThreads) void k_fftz_mul_multi(
     const ZArgs<T>* __restrict__ args, const int4* __restrict__ work) {
   const int4 w = work[blockIdx.x];
-  fftz_mul_body<T, false>(args[w.x], w.y, w.z);
+  fftz_mul_body<T, false, true>(args[w.x], w.y, w.z);
 }
 
 template <typename T>
 __global__ __launch_bounds__(kMultiThreads) void k_ffty_mul2d_multi(
     const M2Args<T>* __restrict__ args, const int4* __restrict__ work) {
   const int4 w = work[blockIdx.x];
-  ffty_mul2d_body<T, false>(args[w.x], w.y);
+  ffty_mul2d_body<T, false, true>(args[w.x], w.y);
 }
 
 // ------------------------------------------------------------------ plan --
+constexpr long kMixedTarget = 2048;
+constexpr size_t kLdsMax = 65536;   // dynamic LDS of one block
+
 static int threads_for(long elems) {
   long t = (elems + kMaxE - 1) / kMaxE;
   t = (t + 63) / 64 * 64;
@@ -464,10 +502,15 @@ int demag_plan(int nx, int ny, int nz, int real_bytes, const int* pads, DemagPla
   d.p2z = is_pow2(d.Pz) && d.Pz <= 64;
   d.ldy = round_up(ny, 16);
   const long cap = lds_cap(real_bytes);
+  // the mixed-radix LDS passes are latency-bound: at most kMixedTarget
+  // complex elements per block, so that even small grids launch many
+  // blocks (the power-of-two register passes take as many as fit)
+  const long mcap = std::min<long>(cap, kMixedTarget);
   // x passes: the most rows per block that the LDS, the block size and the
   // grid (no more rows than it has) allow
   int ty = 2;
-  while (ty < 16 && (long)ty * d.Px <= cap && ty < ny + (ny & 1)) ty *= 2;
+  const long xcap = d.p2x ? cap : mcap;
+  while (ty < 16 && (long)ty * d.Px <= xcap && ty < ny + (ny & 1)) ty *= 2;
   while (ty > 2 && ((long)(ty / 2) * d.Px > cap || x_threads(d, ty) > (d.p2x ? 256 : 1024)))
     ty /= 2;
   d.tyf = d.tyi = ty;
@@ -478,7 +521,7 @@ int demag_plan(int nx, int ny, int nz, int real_bytes, const int* pads, DemagPla
       const int l2 = split_l2(d.Py);
       while (n < 64 && (long)(2 * n) * d.Py <= cap && 2 * n * l2 <= 256) n *= 2;
     } else {
-      while (n < 8 && (long)(2 * n) * d.Py <= cap && (long)(2 * n) * d.Py <= 4096) n *= 2;
+      while (n < 8 && (long)(2 * n) * d.Py <= mcap) n *= 2;
     }
     d.nlyf = d.nlyi = n;
   }
@@ -489,14 +532,14 @@ int demag_plan(int nx, int ny, int nz, int real_bytes, const int* pads, DemagPla
       const int l2 = split_l2(d.Py);
       while (k < 64 && (long)3 * (2 * k) * d.Py <= cap && 3 * (2 * k) * l2 <= 256) k *= 2;
     } else {
-      while (k < 64 && (long)3 * (2 * k) * d.Py <= cap && (long)3 * (2 * k) * d.Py <= 6144) k *= 2;
+      while (k < 64 && (long)3 * (2 * k) * d.Py <= mcap) k *= 2;
     }
     d.nk = k;
   }
   // z pass: mixed-radix ky per block; register lanes per column
   {
     int tk = 64;
-    while (tk > 1 && (long)3 * tk * (d.Pz + 1) > cap) tk /= 2;
+    while (tk > 1 && (long)3 * tk * (d.Pz + 1) > mcap) tk /= 2;
     d.tk = tk;
     int q = 1;
     while (q < 4 && (!zreg_ok(real_bytes, d.Pz, q) || zreg_data_vgprs(real_bytes, d.Pz, q) > 96))
@@ -543,10 +586,15 @@ void demag_pass(int pass, const DemagPlan& p, const DemagBufs<T>& b, const Table
         a.S1 = b.S1; a.Bd = b.Bd; a.tw = b.twx;
         a.nx = p.nx; a.ny = p.ny; a.nz = p.nz; a.Px = p.Px; a.Hx = p.Hx; a.ldy = p.ldy;
         a.ty = ty; a.rad = p.rx;
-        if (inv)
-          hipLaunchKernelGGL((k_fftx_inv<T, false>), g, dim3(x_threads(p, ty)), lds, st, a);
-        else
-          hipLaunchKernelGGL((k_fftx_fwd<T, false>), g, dim3(x_threads(p, ty)), lds, st, a);
+        const dim3 blk(x_threads(p, ty));
+        const size_t ldt = lds + (size_t)p.Px * sizeof(V);   // with the twiddle table
+        if (ldt <= kLdsMax) {
+          if (inv) hipLaunchKernelGGL((k_fftx_inv<T, false, true>), g, blk, ldt, st, a);
+          else hipLaunchKernelGGL((k_fftx_fwd<T, false, true>), g, blk, ldt, st, a);
+        } else {
+          if (inv) hipLaunchKernelGGL((k_fftx_inv<T, false, false>), g, blk, lds, st, a);
+          else hipLaunchKernelGGL((k_fftx_fwd<T, false, false>), g, blk, lds, st, a);
+        }
       }
       break;
     }
@@ -563,7 +611,11 @@ void demag_pass(int pass, const DemagPlan& p, const DemagBufs<T>& b, const Table
         a.ctrl = ctrl; a.S1 = b.S1; a.K = b.K; a.tw = b.twy;
         a.ny = p.ny; a.Py = p.Py; a.Hx = p.Hx; a.Hy = p.Hy; a.ldy = p.ldy; a.nk = p.nk;
         a.rad = p.ry;
-        hipLaunchKernelGGL((k_ffty_mul2d<T, false>), g, dim3(m2_threads(p)), lds, st, a);
+        const size_t ldt = lds + (size_t)p.Py * sizeof(V);
+        if (ldt <= kLdsMax)
+          hipLaunchKernelGGL((k_ffty_mul2d<T, false, true>), g, dim3(m2_threads(p)), ldt, st, a);
+        else
+          hipLaunchKernelGGL((k_ffty_mul2d<T, false, false>), g, dim3(m2_threads(p)), lds, st, a);
       }
       break;
     }
@@ -589,10 +641,15 @@ void demag_pass(int pass, const DemagPlan& p, const DemagBufs<T>& b, const Table
         a.ctrl = ctrl; a.in = in; a.out = out; a.tw = b.twy;
         a.nlines = nlines; a.nvalid_in = nvi; a.ld_in = ldi; a.nvalid_out = nvo; a.ld_out = ldo;
         a.L = p.Py; a.nl = nl; a.rad = p.ry;
-        if (inv)
-          hipLaunchKernelGGL((k_ffty<T, true, false>), g, dim3(y_threads(p, nl)), lds, st, a);
-        else
-          hipLaunchKernelGGL((k_ffty<T, false, false>), g, dim3(y_threads(p, nl)), lds, st, a);
+        const dim3 blk(y_threads(p, nl));
+        const size_t ldt = lds + (size_t)p.Py * sizeof(V);
+        if (ldt <= kLdsMax) {
+          if (inv) hipLaunchKernelGGL((k_ffty<T, true, false, true>), g, blk, ldt, st, a);
+          else hipLaunchKernelGGL((k_ffty<T, false, false, true>), g, blk, ldt, st, a);
+        } else {
+          if (inv) hipLaunchKernelGGL((k_ffty<T, true, false, false>), g, blk, lds, st, a);
+          else hipLaunchKernelGGL((k_ffty<T, false, false, false>), g, blk, lds, st, a);
+        }
       }
       break;
     }
@@ -610,8 +667,11 @@ void demag_pass(int pass, const DemagPlan& p, const DemagBufs<T>& b, const Table
         a.ctrl = ctrl; a.S2 = b.S2; a.K = b.K; a.tw = b.twz;
         a.nz = p.nz; a.Pz = p.Pz; a.Hx = p.Hx; a.Py = p.Py; a.Hy = p.Hy; a.Hz = p.Hz;
         a.tk = p.tk; a.ls = p.Pz + 1; a.rad = p.rz;
-        hipLaunchKernelGGL((k_fftz_mul<T, false>), dim3((p.Py + p.tk - 1) / p.tk, p.Hx),
-                           dim3(z_threads(p)), (size_t)3 * p.tk * (p.Pz + 1) * sizeof(V), st, a);
+        const dim3 g((p.Py + p.tk - 1) / p.tk, p.Hx), blk(z_threads(p));
+        const size_t lds = (size_t)3 * p.tk * (p.Pz + 1) * sizeof(V);
+        const size_t ldt = lds + (size_t)p.Pz * sizeof(V);
+        if (ldt <= kLdsMax) hipLaunchKernelGGL((k_fftz_mul<T, false, true>), g, blk, ldt, st, a);
+        else hipLaunchKernelGGL((k_fftz_mul<T, false, false>), g, blk, lds, st, a);
       }
       break;
     }
@@ -658,10 +718,11 @@ static int pow2_floor(long cap, int hi) {
 }
 
 bool demag_multi_fits(const DemagPlan& p) {
+  // one line and its twiddle table per block
   const long cap = (long)kMaxE * kMultiThreads;
-  if (p.Px > cap || p.Py > cap) return false;
-  if (p.nz == 1) return 3L * p.Py <= cap;
-  return 3L * (p.Pz + 1) <= cap;
+  if (2L * p.Px > cap || 2L * p.Py > cap) return false;
+  if (p.nz == 1) return 4L * p.Py <= cap;
+  return 3L * (p.Pz + 1) + p.Pz <= cap;
 }
 
 template <typename T>
@@ -682,8 +743,9 @@ int DemagMulti<T>::build(const std::vector<DemagMember<T>>& members, hipStream_t
     const DemagPlan& p = *mb.plan;
     const int gi = (int)g;
     // x passes: the most rows per block (<= 16) that fit
+    // (the twiddle table of the line length sits in LDS beside the lines)
     int ty = 2;
-    while (ty < 16 && (long)ty * p.Px <= cap && ty < p.ny + (p.ny & 1)) ty *= 2;
+    while (ty < 16 && (long)(ty + 1) * p.Px <= cap && ty < p.ny + (p.ny & 1)) ty *= 2;
     XArgs<T> xa{};
     xa.tbl = mb.tbl; xa.ctrl = mb.ctrl; xa.stage = 0;
     xa.ms0 = mb.ms0; xa.ms1 = mb.ms1; xa.ms2 = mb.ms2; xa.nsub = mb.nsub;
@@ -698,9 +760,9 @@ int DemagMulti<T>::build(const std::vector<DemagMember<T>>& members, hipStream_t
           I.wxf.push_back(make_int4(xf_idx, b, z, c));
           I.wxi.push_back(make_int4(xf_idx, b, z, c));
         }
-    I.lds_x = std::max(I.lds_x, (size_t)(ty / 2) * p.Px * sizeof(V));
+    I.lds_x = std::max(I.lds_x, (size_t)(ty / 2 + 1) * p.Px * sizeof(V));
     if (p.nz == 1) {
-      const int nk = pow2_floor(cap / (3L * p.Py), 64);
+      const int nk = pow2_floor((cap / p.Py - 1) / 3, 64);
       M2Args<T> a{};
       a.ctrl = mb.ctrl; a.S1 = mb.bufs.S1; a.K = mb.bufs.K; a.tw = mb.bufs.twy;
       a.ny = p.ny; a.Py = p.Py; a.Hx = p.Hx; a.Hy = p.Hy; a.ldy = p.ldy; a.nk = nk;
@@ -708,9 +770,9 @@ int DemagMulti<T>::build(const std::vector<DemagMember<T>>& members, hipStream_t
       I.m2.push_back(a);
       const int idx = (int)I.m2.size() - 1;
       for (int b = 0; b < (p.Hx + nk - 1) / nk; ++b) I.wm2.push_back(make_int4(idx, b, 0, 0));
-      I.lds_m2 = std::max(I.lds_m2, (size_t)3 * nk * p.Py * sizeof(V));
+      I.lds_m2 = std::max(I.lds_m2, (size_t)(3 * nk + 1) * p.Py * sizeof(V));
     } else {
-      const int nl = pow2_floor(cap / p.Py, 64);
+      const int nl = pow2_floor(cap / p.Py - 1, 64);
       const int nlines = 3 * p.nz * p.Hx;
       YArgs<T> a{};
       a.ctrl = mb.ctrl; a.tw = mb.bufs.twy; a.nlines = nlines; a.L = p.Py; a.nl = nl;
@@ -727,8 +789,8 @@ int DemagMulti<T>::build(const std::vector<DemagMember<T>>& members, hipStream_t
         I.wyf.push_back(make_int4(idx, b, 0, 0));
         I.wyi.push_back(make_int4(idx, b, 0, 0));
       }
-      I.lds_y = std::max(I.lds_y, (size_t)nl * p.Py * sizeof(V));
-      const int tk = pow2_floor(cap / (3L * (p.Pz + 1)), 64);
+      I.lds_y = std::max(I.lds_y, (size_t)(nl + 1) * p.Py * sizeof(V));
+      const int tk = pow2_floor((cap - p.Pz) / (3L * (p.Pz + 1)), 64);
       ZArgs<T> za{};
       za.ctrl = mb.ctrl; za.S2 = mb.bufs.S2; za.K = mb.bufs.K; za.tw = mb.bufs.twz;
       za.nz = p.nz; za.Pz = p.Pz; za.Hx = p.Hx; za.Py = p.Py; za.Hy = p.Hy; za.Hz = p.Hz;
@@ -737,7 +799,7 @@ int DemagMulti<T>::build(const std::vector<DemagMember<T>>& members, hipStream_t
       const int zi = (int)I.z.size() - 1;
       for (int kx = 0; kx < p.Hx; ++kx)
         for (int b = 0; b < (p.Py + tk - 1) / tk; ++b) I.wz.push_back(make_int4(zi, b, kx, 0));
-      I.lds_z = std::max(I.lds_z, (size_t)3 * tk * (p.Pz + 1) * sizeof(V));
+      I.lds_z = std::max(I.lds_z, ((size_t)3 * tk * (p.Pz + 1) + p.Pz) * sizeof(V));
     }
   }
   // one device allocation, 256-byte aligned segments

@@ -4,8 +4,11 @@
 // buf + l*ls) and transforms them in place: every stage loads each
 // butterfly's inputs into registers, synchronises, and writes the autosorted
 // outputs, so no second LDS buffer is needed.  Twiddles w^j = exp(-2 pi i
-// j/L) come from an FP64-built table in global memory (cached; indexes are
-// exact integers, so no run-time trig in the passes).  The caller guarantees
+// j/L) come from an FP64-built table (indexes are exact integers, so no
+// run-time trig in the passes); the kernels copy it into LDS beside the
+// lines when it fits, so every stage reads it at LDS latency, and each
+// thread issues the loads of all its butterflies of a stage before the
+// first product.  The caller guarantees
 // nlines*L <= kMaxE * blockDim.x, which bounds the butterflies per thread.
 #pragma once
 
@@ -122,7 +125,11 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, const cpx<T>* __restrict_
   const int Lr = L / R;
   const int total = nlines * Lr;
   const int tstride = Lr / Ns;  // = L / (Ns * R)
+  // the loads of all of a thread's butterflies (LDS values and twiddle
+  // table entries) are issued before the first twiddle product, so they
+  // overlap instead of each butterfly waiting for its own
   V v[MAXB][R];
+  V tt[MAXB][R];
 #pragma unroll
   for (int q = 0; q < MAXB; ++q) {
     const int w = tid + q * nthr;
@@ -135,8 +142,17 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, const cpx<T>* __restrict_
       for (int r = 0; r < R; ++r) v[q][r] = b[j + r * Lr];
       if (Ns > 1) {
 #pragma unroll
+        for (int r = 1; r < R; ++r) tt[q][r] = tw[r * k * tstride];
+      }
+    }
+  }
+  if (Ns > 1) {
+#pragma unroll
+    for (int q = 0; q < MAXB; ++q) {
+      if (tid + q * nthr < total) {
+#pragma unroll
         for (int r = 1; r < R; ++r) {
-          V t = tw[r * k * tstride];
+          V t = tt[q][r];
           if (INV) t.y = -t.y;
           v[q][r] = cmul(v[q][r], t);
         }
@@ -165,7 +181,7 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, const cpx<T>* __restrict_
 // stages are then not compiled into the kernel, which keeps its register
 // footprint small enough to avoid spilling.
 template <typename T, bool INV, bool P2>
-__device__ void lds_fft(cpx<T>* buf, const cpx<T>* __restrict__ tw, int L, int nlines,
+__device__ __forceinline__ void lds_fft(cpx<T>* buf, const cpx<T>* __restrict__ tw, int L, int nlines,
                         int ls, const int nstages, const uint64_t code, int tid, int nthr) {
   int Ns = 1;
   for (int s = 0; s < nstages; ++s) {

@@ -312,12 +312,14 @@ struct Grid final : GridBase {
                    p.pbc[1]);
   }
 
-  // enough waves to cover the chip a few times over, but marches of at
-  // least a few planes so that z neighbours are reused
+  // enough waves to cover the chip a few times over (8 per SIMD), with the
+  // longest z march that still gives them: a small grid marches one plane
+  // per thread, since its few blocks would otherwise leave most of the
+  // chip idle while each thread walks its column
   int default_field_zc() const {
-    const long cols = (long)((nx + kTileX - 1) / kTileX) * ((ny + kTileY - 1) / kTileY) * 4;
+    const long waves = (long)((nx + kTileX - 1) / kTileX) * ((ny + kTileY - 1) / kTileY) * 4;
     int zc = nz;
-    while (zc > 4 && cols * ((nz + zc - 1) / zc) < 8192) zc = (zc + 1) / 2;
+    while (zc > 1 && waves * ((nz + zc - 1) / zc) < 8192) zc = (zc + 1) / 2;
     return zc;
   }
 
