@@ -31,7 +31,7 @@ server (FP32, continuous batching), time-boxed, then at 0.8x the measured
 capacity, beside plain sequential FP64 on a subsample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-fp64]
-       [--no-cpu-baseline] [--no-prof] [--no-autotune] [--serve N]
+       [--no-cpu-baseline] [--no-prof] [--no-autotune] [--no-accuracy] [--serve N]
        [--serve-seconds S] [--serve-active A] [--serve-baseline K]
 """
 from __future__ import annotations
@@ -522,6 +522,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-prof", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the accuracy check against the stored oracle run")
     ap.add_argument("--serve", type=int, default=200,
                     help="requests of the stream in the serving measurement (0 = skip)")
     ap.add_argument("--serve-seconds", type=float, default=45.0,
@@ -591,7 +593,7 @@ def main():
     if args.serve > 0:
         out["serving"] = run_serve(args.serve, args.serve_seconds, args.serve_active,
                                    baseline=min(args.serve_baseline, args.serve))
-    acc = accuracy_c2crop()
+    acc = None if args.no_accuracy else accuracy_c2crop()
     if acc is not None:
         out["accuracy"] = acc
         _progress("accuracy check done")
