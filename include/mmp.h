@@ -339,6 +339,12 @@ typedef struct {
                              (power-of-two Pz <= 64): 1, 2 or 4            */
   int32_t z_waves;        /* waves-per-SIMD hint of that pass: 1, 2 or 4   */
   int32_t z_threads;      /* threads per block of that pass: 64, 128, 256  */
+  int32_t z_mode;         /* 0: that pass loads the kernel values after
+                             the forward transforms; 1 (FP32, z_waves 1):
+                             it copies them into LDS as it loads the
+                             columns (z_threads/64 * 6 * rows * 256 bytes of
+                             LDS <= 64 KiB, rows = Pz/2 + 1 for z_lanes 1,
+                             else Pz/z_lanes).  Same arithmetic per column */
   int32_t field_zplanes;  /* z cells per thread of the field kernel        */
   uint32_t kinds;         /* out: bits 0/1/2 set when the x/y/z passes use
                              the power-of-two register kernels             */

@@ -32,6 +32,7 @@ struct DemagPlan {
   int nk = 0;                       // 2-D fused y pass: kx columns per block
   int tk = 0;                       // mixed-radix z pass: ky columns per block
   int zq = 1, zw = 1, zt = 0;       // register z pass: lanes per column, waves hint, threads
+  int zmode = 0;                    // register z pass: 1 = kernel values staged through LDS
   // image repetitions per axis; > 0 makes the axis periodic (x and y only):
   // P = n, no zero padding, the kernel summed over the images
   int rep[3] = {0, 0, 0};

@@ -412,6 +412,7 @@ __global__ __launch_bounds__(kMultiThreads) void k_ffty_mul2d_multi(
 constexpr long kMixedTarget = 2048;
 constexpr size_t kLdsMax = 65536;   // dynamic LDS of one block
 
+
 static int threads_for(long elems) {
   long t = (elems + kMaxE - 1) / kMaxE;
   t = (t + 63) / 64 * 64;
@@ -464,6 +465,10 @@ int demag_plan_check(const DemagPlan& p, int real_bytes) {
     if (p.p2z) {
       if (!zreg_waves_ok(real_bytes, p.Pz, p.zq, p.zw)) return -1;
       if (p.zt != 64 && p.zt != 128 && p.zt != 256) return -1;
+      if (p.zmode < 0 || p.zmode > 1) return -1;
+      if (p.zmode == 1 &&
+          (real_bytes != 4 || p.zw != 1 || zk_lds_bytes(p.Pz, p.zq, p.zt) > (long)kLdsMax))
+        return -1;
     } else {
       if (!pow2_in(p.tk, 1, 64) || (long)3 * p.tk * (p.Pz + 1) > cap) return -1;
       if (z_threads(p) > 1024) return -1;
@@ -541,12 +546,21 @@ int demag_plan(int nx, int ny, int nz, int real_bytes, const int* pads, DemagPla
     int tk = 64;
     while (tk > 1 && (long)3 * tk * (d.Pz + 1) > mcap) tk /= 2;
     d.tk = tk;
-    int q = 1;
-    while (q < 4 && (!zreg_ok(real_bytes, d.Pz, q) || zreg_data_vgprs(real_bytes, d.Pz, q) > 96))
-      q *= 2;
-    if (!zreg_ok(real_bytes, d.Pz, q)) q = 1;
+    // FP32 columns of up to 32 points: one lane per column, two waves per
+    // SIMD (the column's 192 registers and the transform's temporaries fit
+    // the 256 of a wave); otherwise the fewest lanes whose share of a
+    // column takes at most 96 registers, one wave's worth of the rest
+    int q = 1, w = 1;
+    if (real_bytes == 4 && zreg_waves_ok(real_bytes, d.Pz, 1, 2)) {
+      w = 2;
+    } else {
+      while (q < 4 &&
+             (!zreg_ok(real_bytes, d.Pz, q) || zreg_data_vgprs(real_bytes, d.Pz, q) > 96))
+        q *= 2;
+      if (!zreg_ok(real_bytes, d.Pz, q)) q = 1;
+    }
     d.zq = q;
-    d.zw = 1;
+    d.zw = w;
     d.zt = 128;
     if (d.p2z && !zreg_ok(real_bytes, d.Pz, d.zq)) d.p2z = false;
   }
@@ -661,7 +675,7 @@ void demag_pass(int pass, const DemagPlan& p, const DemagBufs<T>& b, const Table
         const int cpb = p.zt / p.zq;
         const int nblk = ((p.Py + cpb - 1) / cpb) * p.Hx;
         a.nb_pad = round_up(nblk, 8);
-        launch_z4<T>(p.Pz, p.zq, p.zw, dim3(a.nb_pad), p.zt, st, a);
+        launch_z4<T>(p.Pz, p.zq, p.zw, p.zmode, dim3(a.nb_pad), p.zt, st, a);
       } else {
         ZArgs<T> a;
         a.ctrl = ctrl; a.S2 = b.S2; a.K = b.K; a.tw = b.twz;
@@ -995,11 +1009,12 @@ double demag_tune(DemagPlan* pp, const DemagBufs<T>& b, const Table<T>* tbl, T m
         if (best.p2z) {
           for (int q = 1; q <= 4; q *= 2)
             for (int w = 1; w <= 4; w *= 2)
-              for (int t = 64; t <= 256; t *= 2) {
-                DemagPlan c = best;
-                c.zq = q; c.zw = w; c.zt = t;
-                add(c);
-              }
+              for (int t = 64; t <= 256; t *= 2)
+                for (int k = 0; k <= 1; ++k) {
+                  DemagPlan c = best;
+                  c.zq = q; c.zw = w; c.zt = t; c.zmode = k;
+                  add(c);
+                }
         } else {
           for (int tk = 1; tk <= 64; tk *= 2) {
             DemagPlan c = best;

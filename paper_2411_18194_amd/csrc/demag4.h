@@ -58,6 +58,13 @@ constexpr bool zreg_ok(int real_bytes, int pz, int zq) {
   return (zq == 1 || zq == 2 || zq == 4) && pz >= 2 && pz <= 64 && (zq == 1 || pz / zq >= 2) &&
          zreg_data_vgprs(real_bytes, pz, zq) <= 192;
 }
+// LDS of one block of the register z pass with its kernel values staged
+// through LDS (32-bit values only, one wave per SIMD): six rows of one word
+// per lane for each of the PZ/2 + 1 mirrored planes (one lane per column) or
+// PZ/zq registers (zq lanes per column).
+constexpr long zk_lds_bytes(int pz, int zq, int threads) {
+  return (long)(threads / 64) * 6 * (zq == 1 ? pz / 2 + 1 : pz / zq) * 64 * 4;
+}
 constexpr bool zreg_waves_ok(int real_bytes, int pz, int zq, int zw) {
   return zreg_ok(real_bytes, pz, zq) &&
          (zw == 1 || ((zw == 2 || zw == 4) && zreg_data_vgprs(real_bytes, pz, zq) * zw <= 384));
@@ -75,6 +82,7 @@ template <typename T>
 void launch_m4(int L, bool full, dim3 g, int thr, size_t lds, hipStream_t st,
                const M4Args<T>& a);
 template <typename T>
-void launch_z4(int PZ, int q, int w, dim3 g, int thr, hipStream_t st, const Z4Args<T>& a);
+void launch_z4(int PZ, int q, int w, int mode, dim3 g, int thr, hipStream_t st,
+               const Z4Args<T>& a);
 
 }  // namespace mmp

@@ -535,6 +535,60 @@ __device__ __forceinline__ void zcol_inverse_store(cpx<T>* v, cpx<T>* col, long 
   }
 }
 
+// B(kz) = K(kz) M(kz) for the spectra of one column, held at bit-reversed
+// register positions; kv(c, j, kzo) is kernel component c (xx, yy, zz, xy,
+// xz, yz) at the mirrored plane kzo of lane q's register j.  The stored
+// octant is mirrored to the full spectrum: the diagonal components are even
+// in every wave number, an off-diagonal one is odd in each of the two wave
+// numbers it pairs (sy past Py/2, sz past Pz/2; kx is never mirrored).
+template <typename T, int PZ, int Q, typename KV>
+__device__ __forceinline__ void zcol_kmul(cpx<T>* vx, cpx<T>* vy, cpx<T>* vz, int q, T sy,
+                                          KV&& kv) {
+  constexpr int R = PZ / Q;
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int kz = Q * j + q;
+    const int kzo = kz <= PZ / 2 ? kz : PZ - kz;
+    const T sz = kz <= PZ / 2 ? T(1) : T(-1);
+    T k6[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) k6[c] = kv(c, j, kzo);
+    const T kxx = k6[0], kyy = k6[1], kzz = k6[2];
+    const T kxy = sy * k6[3], kxz = sz * k6[4], kyz = sy * sz * k6[5];
+    const int r = bitrev<R>(j);
+    const cpx<T> mx = vx[r], my = vy[r], mz = vz[r];
+    vx[r] = cmk<T>(kxx * mx.x + kxy * my.x + kxz * mz.x, kxx * mx.y + kxy * my.y + kxz * mz.y);
+    vy[r] = cmk<T>(kxy * mx.x + kyy * my.x + kyz * mz.x, kxy * mx.y + kyy * my.y + kyz * mz.y);
+    vz[r] = cmk<T>(kxz * mx.x + kyz * my.x + kzz * mz.x, kxz * mx.y + kyz * my.y + kzz * mz.y);
+  }
+}
+
+// Asynchronous copy of one 32-bit word per lane from global memory into LDS
+// (the lanes' words land at consecutive addresses from wave-uniform dst): the
+// data occupies no registers while in flight and completes with vmcnt.
+__device__ __forceinline__ void lds_dma_b32(const float* src, float* dst) {
+  __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void*)const_cast<float*>(src),
+                                   (__attribute__((address_space(3))) void*)dst, 4, 0, 0);
+}
+
+// K rows a lane of the register z pass reads: with one lane per column the
+// PZ/2 + 1 distinct planes kzo of the mirrored spectrum, else one per
+// register j (lane q's kz = Q j + q).
+template <int PZ, int Q>
+constexpr int zk_rows() { return Q == 1 ? PZ / 2 + 1 : PZ / Q; }
+
+// Makes the N complex values in registers at this point of the program: the
+// compiler can neither sink their computation below it nor hoist later uses
+// above it (an empty asm that reads and rewrites each register).  Between
+// the phases of a register z pass this keeps the forward transforms, the
+// kernel products and the inverse transforms from interleaving, which would
+// hold more values live at once than the 256 registers of two waves per SIMD.
+template <int N, typename T>
+__device__ __forceinline__ void pin_regs(cpx<T>* v) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) asm volatile("" : "+v"(v[i].x), "+v"(v[i].y));
+}
+
 // Q adjacent lanes (Q = 1, 2 or 4, within one quad) carry the three
 // components of one (kx, ky) column through forward FFT, kernel multiply and
 // inverse FFT in registers: no LDS and no barriers, so the pass streams like
@@ -543,11 +597,16 @@ __device__ __forceinline__ void zcol_inverse_store(cpx<T>* v, cpx<T>* col, long 
 // lanes per column mean fewer registers per lane.  Blocks are ordered so that
 // all ky tiles of one kx run back to back on one XCD, which keeps that kx
 // slice of the kernel (read for ky and its mirror Py - ky) in the XCD's L2.
-template <typename T, int PZ, int Q>
+// KL: the lane's 6 zk_rows kernel values are copied into the wave's LDS
+// slice right behind the column loads, so both latencies overlap and the
+// multiply reads LDS instead of waiting on a second round of loads after the
+// forward transforms (one wave per SIMD leaves nothing else to hide it).
+template <typename T, int PZ, int Q, bool KL>
 __device__ __forceinline__ void fftz_mul_body(const Z4Args<T>& a) {
   using V = cpx<T>;
   constexpr int R = PZ / Q, NH = PZ / 2;
   static_assert(zreg_ok((int)sizeof(T), PZ, Q), "lanes per column");
+  static_assert(!KL || sizeof(T) == 4, "LDS-staged kernel values are 32-bit words");
   if (ctrl_stopped(a.ctrl)) return;
   const int cpb = blockDim.x / Q;
   const int ntile = (a.Py + cpb - 1) / cpb;
@@ -591,6 +650,29 @@ __device__ __forceinline__ void fftz_mul_body(const Z4Args<T>& a) {
       }
     });
   }
+  const int kyo = ky <= a.Py / 2 ? ky : a.Py - ky;
+  const T sy = ky <= a.Py / 2 ? T(1) : T(-1);
+  const long ks = (long)a.Hz * a.Hx * a.Hy;
+  const T* K = a.K + (long)kx * a.Hy + kyo;
+  const long kzs = (long)a.Hx * a.Hy;
+  constexpr int NJ = zk_rows<PZ, Q>();
+  [[maybe_unused]] T* kw = nullptr;
+  if constexpr (KL) {
+    extern __shared__ char smem_raw[];
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);  // uniform: M0 is scalar
+    kw = reinterpret_cast<T*>(smem_raw) + wv * (6 * NJ * 64);
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        int kzo = j;
+        if constexpr (Q > 1) {
+          const int kz = Q * j + q;
+          kzo = kz <= PZ / 2 ? kz : PZ - kz;
+        }
+        lds_dma_b32(K + c * ks + kzo * kzs, kw + (c * NJ + j) * 64);
+      }
+  }
   if constexpr (Q == 1) {
     reg_fft_hz<T, PZ, false>(vx);
     reg_fft_hz<T, PZ, false>(vy);
@@ -600,26 +682,22 @@ __device__ __forceinline__ void fftz_mul_body(const Z4Args<T>& a) {
     reg_fft<T, R, false>(vy);
     reg_fft<T, R, false>(vz);
   }
-  const int kyo = ky <= a.Py / 2 ? ky : a.Py - ky;
-  const T sy = ky <= a.Py / 2 ? T(1) : T(-1);
-  const long ks = (long)a.Hz * a.Hx * a.Hy;
-  const T* K = a.K + (long)kx * a.Hy + kyo;
-  const long kzs = (long)a.Hx * a.Hy;
-  // B(kz) = K(kz) M(kz); the spectra sit at bit-reversed register positions
-#pragma unroll
-  for (int j = 0; j < R; ++j) {
-    const int kz = Q * j + q;
-    const int kzo = kz <= PZ / 2 ? kz : PZ - kz;
-    const T sz = kz <= PZ / 2 ? T(1) : T(-1);
-    const T* kr = K + kzo * kzs;
-    const T kxx = kr[0], kyy = kr[ks], kzz = kr[2 * ks];
-    const T kxy = sy * kr[3 * ks], kxz = sz * kr[4 * ks], kyz = sy * sz * kr[5 * ks];
-    const int r = bitrev<R>(j);
-    const V mx = vx[r], my = vy[r], mz = vz[r];
-    vx[r] = cmk<T>(kxx * mx.x + kxy * my.x + kxz * mz.x, kxx * mx.y + kxy * my.y + kxz * mz.y);
-    vy[r] = cmk<T>(kxy * mx.x + kyy * my.x + kyz * mz.x, kxy * mx.y + kyy * my.y + kyz * mz.y);
-    vz[r] = cmk<T>(kxz * mx.x + kyz * my.x + kzz * mz.x, kxz * mx.y + kyz * my.y + kzz * mz.y);
-  }
+  pin_regs<R, T>(vx);
+  pin_regs<R, T>(vy);
+  pin_regs<R, T>(vz);
+  const int lane = threadIdx.x & 63;
+  // the LDS copies complete with the vector memory counter (vmcnt 0)
+  if constexpr (KL) __builtin_amdgcn_s_waitcnt(0x0F70);
+  zcol_kmul<T, PZ, Q>(vx, vy, vz, q, sy, [&](int c, int j, int kzo) {
+    if constexpr (KL) return kw[(c * NJ + (Q == 1 ? kzo : j)) * 64 + lane];
+    else return K[kzo * kzs + c * ks];
+  });
+  pin_regs<R, T>(vx);
+  pin_regs<R, T>(vy);
+  pin_regs<R, T>(vz);
+  // the store addresses are formed anew, not kept in registers from the
+  // loads
+  asm volatile("" : "+v"(col));
   zcol_inverse_store<T, PZ, Q>(vx, col, zs, a.nz, q);
   zcol_inverse_store<T, PZ, Q>(vy, col + cs, zs, a.nz, q);
   zcol_inverse_store<T, PZ, Q>(vz, col + 2 * cs, zs, a.nz, q);
@@ -629,11 +707,15 @@ __device__ __forceinline__ void fftz_mul_body(const Z4Args<T>& a) {
 template <typename T, int PZ, int Q, int W>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k4_fftz_mul_w(
     Z4Args<T> a) {
-  fftz_mul_body<T, PZ, Q>(a);
+  fftz_mul_body<T, PZ, Q, false>(a);
 }
 template <typename T, int PZ, int Q>
 __global__ __launch_bounds__(256) void k4_fftz_mul(Z4Args<T> a) {
-  fftz_mul_body<T, PZ, Q>(a);
+  fftz_mul_body<T, PZ, Q, false>(a);
+}
+template <typename T, int PZ, int Q>
+__global__ __launch_bounds__(256) void k4_fftz_mul_kl(Z4Args<T> a) {
+  fftz_mul_body<T, PZ, Q, true>(a);
 }
 
 // ------------------------------------------------------------ dispatch --
@@ -696,9 +778,16 @@ void launch_m4(int L, bool full, dim3 g, int thr, size_t lds, hipStream_t st,
 }
 
 template <typename T, int PZ, int Q, int W>
-static bool lzw(int q, int w, dim3 g, int thr, hipStream_t st, const Z4Args<T>& a) {
+static bool lzw(int q, int w, int mode, dim3 g, int thr, hipStream_t st, const Z4Args<T>& a) {
   if constexpr (zreg_waves_ok((int)sizeof(T), PZ, Q, W)) {
     if (q == Q && w == W) {
+      if constexpr (W == 1 && sizeof(T) == 4) {
+        if (mode == 1) {
+          hipLaunchKernelGGL((k4_fftz_mul_kl<T, PZ, Q>), g, dim3(thr),
+                             (size_t)zk_lds_bytes(PZ, Q, thr), st, a);
+          return true;
+        }
+      }
       if constexpr (W == 1)
         hipLaunchKernelGGL((k4_fftz_mul<T, PZ, Q>), g, dim3(thr), 0, st, a);
       else
@@ -710,24 +799,25 @@ static bool lzw(int q, int w, dim3 g, int thr, hipStream_t st, const Z4Args<T>& 
 }
 
 template <typename T, int PZ>
-static void lz(int q, int w, dim3 g, int thr, hipStream_t st, const Z4Args<T>& a) {
-  (void)(lzw<T, PZ, 1, 1>(q, w, g, thr, st, a) || lzw<T, PZ, 1, 2>(q, w, g, thr, st, a) ||
-         lzw<T, PZ, 1, 4>(q, w, g, thr, st, a) || lzw<T, PZ, 2, 1>(q, w, g, thr, st, a) ||
-         lzw<T, PZ, 2, 2>(q, w, g, thr, st, a) || lzw<T, PZ, 2, 4>(q, w, g, thr, st, a) ||
-         lzw<T, PZ, 4, 1>(q, w, g, thr, st, a) || lzw<T, PZ, 4, 2>(q, w, g, thr, st, a) ||
-         lzw<T, PZ, 4, 4>(q, w, g, thr, st, a));
+static void lz(int q, int w, int mode, dim3 g, int thr, hipStream_t st, const Z4Args<T>& a) {
+  (void)(lzw<T, PZ, 1, 1>(q, w, mode, g, thr, st, a) || lzw<T, PZ, 1, 2>(q, w, mode, g, thr, st, a) ||
+         lzw<T, PZ, 1, 4>(q, w, mode, g, thr, st, a) || lzw<T, PZ, 2, 1>(q, w, mode, g, thr, st, a) ||
+         lzw<T, PZ, 2, 2>(q, w, mode, g, thr, st, a) || lzw<T, PZ, 2, 4>(q, w, mode, g, thr, st, a) ||
+         lzw<T, PZ, 4, 1>(q, w, mode, g, thr, st, a) || lzw<T, PZ, 4, 2>(q, w, mode, g, thr, st, a) ||
+         lzw<T, PZ, 4, 4>(q, w, mode, g, thr, st, a));
 }
 
 // The plan admits only (PZ, q, w) with zreg_waves_ok, so a launch is made.
 template <typename T>
-void launch_z4(int PZ, int q, int w, dim3 g, int thr, hipStream_t st, const Z4Args<T>& a) {
+void launch_z4(int PZ, int q, int w, int mode, dim3 g, int thr, hipStream_t st,
+               const Z4Args<T>& a) {
   switch (PZ) {
-    case 2: lz<T, 2>(q, w, g, thr, st, a); break;
-    case 4: lz<T, 4>(q, w, g, thr, st, a); break;
-    case 8: lz<T, 8>(q, w, g, thr, st, a); break;
-    case 16: lz<T, 16>(q, w, g, thr, st, a); break;
-    case 32: lz<T, 32>(q, w, g, thr, st, a); break;
-    case 64: lz<T, 64>(q, w, g, thr, st, a); break;
+    case 2: lz<T, 2>(q, w, mode, g, thr, st, a); break;
+    case 4: lz<T, 4>(q, w, mode, g, thr, st, a); break;
+    case 8: lz<T, 8>(q, w, mode, g, thr, st, a); break;
+    case 16: lz<T, 16>(q, w, mode, g, thr, st, a); break;
+    case 32: lz<T, 32>(q, w, mode, g, thr, st, a); break;
+    case 64: lz<T, 64>(q, w, mode, g, thr, st, a); break;
   }
 }
 
@@ -737,7 +827,7 @@ void launch_z4(int PZ, int q, int w, dim3 g, int thr, hipStream_t st, const Z4Ar
   template void launch_x4<T>(int, bool, bool, dim3, int, size_t, hipStream_t,              \
                              const X4Args<T>&);                                             \
   template void launch_m4<T>(int, bool, dim3, int, size_t, hipStream_t, const M4Args<T>&);  \
-  template void launch_z4<T>(int, int, int, dim3, int, hipStream_t, const Z4Args<T>&);
+  template void launch_z4<T>(int, int, int, int, dim3, int, hipStream_t, const Z4Args<T>&);
 INST(float)
 INST(double)
 

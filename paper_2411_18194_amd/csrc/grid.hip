@@ -348,6 +348,7 @@ struct Grid final : GridBase {
       o->xy_cols = plan.nk;
       o->z_cols = plan.tk;
       o->z_lanes = plan.zq; o->z_waves = plan.zw; o->z_threads = plan.zt;
+      o->z_mode = plan.zmode;
       o->kinds = (plan.p2x ? 1u : 0u) | (plan.p2y ? 2u : 0u) | (plan.p2z ? 4u : 0u);
       o->lds_axes = plan.force_lds;
       o->demag_ms = tuned_ms;
@@ -385,7 +386,9 @@ struct Grid final : GridBase {
       np.nlyf = in->y_lines[0]; np.nlyi = in->y_lines[1];
       np.nk = in->xy_cols;
       np.tk = in->z_cols;
-      if (np.p2z) { np.zq = in->z_lanes; np.zw = in->z_waves; np.zt = in->z_threads; }
+      if (np.p2z) {
+        np.zq = in->z_lanes; np.zw = in->z_waves; np.zt = in->z_threads; np.zmode = in->z_mode;
+      }
       if (demag_plan_check(np, (int)sizeof(T)) != 0) {
         set_error("plan launch shape outside the kernels' limits");
         return MMP_E_ARG;

@@ -101,12 +101,12 @@ class Plan(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("pad", C.c_int32 * 3), ("x_rows", C.c_int32 * 2),
                 ("y_lines", C.c_int32 * 2), ("xy_cols", C.c_int32), ("z_cols", C.c_int32),
                 ("z_lanes", C.c_int32), ("z_waves", C.c_int32), ("z_threads", C.c_int32),
-                ("field_zplanes", C.c_int32), ("kinds", C.c_uint32), ("lds_axes", C.c_int32),
+                ("z_mode", C.c_int32), ("field_zplanes", C.c_int32), ("kinds", C.c_uint32), ("lds_axes", C.c_int32),
                 ("demag_ms", C.c_double), ("field_ms", C.c_double)]
 
 
 PLAN_KEYS = ("pad", "x_rows", "y_lines", "xy_cols", "z_cols", "z_lanes", "z_waves",
-             "z_threads", "field_zplanes", "lds_axes")
+             "z_threads", "z_mode", "field_zplanes", "lds_axes")
 
 
 def _plan_dict(pl: Plan) -> dict:

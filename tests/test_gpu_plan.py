@@ -70,21 +70,55 @@ def try_plan(g, **kw):
 
 
 @pytest.mark.parametrize("prec", [mmp.FP32, mmp.FP64])
-@pytest.mark.parametrize("name", ["pow2_z32", "pow2_z64", "pow2_z16"])
+@pytest.mark.parametrize("name", ["pow2_z32", "pow2_z64", "pow2_z16", "ragged3d"])
 def test_register_z_variants(name, prec):
-    """Every built (lanes, waves, threads) variant of the register z pass."""
+    """Every built (lanes, waves, threads, mode) variant of the register z pass.
+
+    ragged3d runs on pads (80, 50, 16): a power-of-two z pad over an odd
+    nz = 5 and a y pad of 50, which leaves part of a block's columns empty."""
     p, _, _, _ = reference(name)
     g = mmp.Grid(p, prec)
+    if name == "ragged3d":
+        g.set_plan(pad=[80, 50, 16])
     assert g.plan()["kinds"] & 4
     tried = {}
-    for q, w, t in itertools.product((1, 2, 4), (1, 2, 4), (64, 128, 256)):
-        if not try_plan(g, z_lanes=q, z_waves=w, z_threads=t):
+    for q, w, t, k in itertools.product((1, 2, 4), (1, 2, 4), (64, 128, 256), (0, 1)):
+        if not try_plan(g, z_lanes=q, z_waves=w, z_threads=t, z_mode=k):
             continue
-        tried[(q, w, t)] = demag_err(g, name, prec)
+        tried[(q, w, t, k)] = demag_err(g, name, prec)
+        if k:
+            b = g.eval_heff(mmp.T_DEMAG)[0]
+            assert try_plan(g, z_mode=0)
+            # the same arithmetic per column, the kernel values staged
+            # through LDS
+            assert relerr(b, g.eval_heff(mmp.T_DEMAG)[0]) <= 1e-6, (q, w, t, k)
     g.close()
     assert any(k[0] > 1 for k in tried), tried
+    modes = {k[3] for k in tried}
+    # LDS staging exists for 32-bit values only
+    assert modes == ({0, 1} if prec == mmp.FP32 else {0}), modes
+    assert all(k[3] == 0 or k[1] == 1 for k in tried)
     bad = {k: v for k, v in tried.items() if not v <= TOL[prec]}
     assert not bad, (name, prec, bad)
+
+
+@pytest.mark.parametrize("threads", [64, 128, 256])
+def test_two_wave_z_pass_at_film_shape(threads):
+    """One lane per column at two waves per SIMD (the default FP32 z pass)
+    on a 256x256x16 film, 2056 blocks of columns of 32 points: same field
+    as the one-wave pass, with and without the kernel values in LDS."""
+    p, m = inputs.config_c2(n=(256, 256, 16))
+    g = mmp.Grid(p, mmp.FP32)
+    g.set_state(m)
+    pl = g.plan()
+    assert pl["pad"] == [512, 512, 32] and (pl["z_lanes"], pl["z_waves"]) == (1, 2)
+    g.set_plan(z_lanes=1, z_waves=1, z_threads=threads, z_mode=0)
+    ref = g.eval_heff(mmp.T_DEMAG)[0]
+    # the kernel values of 256 columns (104 KiB) do not fit the LDS of a block
+    for w, k in ((1, 1), (2, 0)) if threads <= 128 else ((2, 0),):
+        g.set_plan(z_waves=w, z_mode=k)
+        assert relerr(g.eval_heff(mmp.T_DEMAG)[0], ref) <= 1e-6, (w, k)
+    g.close()
 
 
 @pytest.mark.parametrize("prec", [mmp.FP32, mmp.FP64])
