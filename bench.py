@@ -105,7 +105,7 @@ def src_hash():
     return h.hexdigest()[:16]
 
 
-def run_gpu(precision, steps, warmup, prof=True, tune=True):
+def run_gpu(precision, steps, warmup, prof=True, tune=True, plan_fields=None):
     import torch
 
     from paper_2411_18194_amd import inputs, mmp
@@ -116,7 +116,10 @@ def run_gpu(precision, steps, warmup, prof=True, tune=True):
     g.set_stream(stream.cuda_stream)
     g.set_state(m0)
     t_tune = time.perf_counter()
-    plan = g.autotune() if tune else g.plan()
+    if plan_fields:
+        plan = g.set_plan(**plan_fields)
+    else:
+        plan = g.autotune() if tune else g.plan()
     t_tune = time.perf_counter() - t_tune
     dt = inputs.c2_fixed_dt()
     g.run_fixed(dt, warmup)
@@ -443,7 +446,8 @@ def run_serve(count, box_s, max_active=16, baseline=0):
 # rocprofv3 kernel names -> kernel classes of the library's event profiler
 KERNEL_CLASSES = (("k4_fftx_fwd", "fftx_fwd"), ("k_fftx_fwd", "fftx_fwd"),
                   ("k4_fftx_inv", "fftx_inv"), ("k_fftx_inv", "fftx_inv"),
-                  ("k4_fftz_mul", "fftz_mul"), ("k_fftz_mul", "fftz_mul"),
+                  ("k4_fftz_mul", "fftz_mul"), ("k4_fftz_mul_w", "fftz_mul"),
+                  ("k4_fftz_mul_kl", "fftz_mul"), ("k_fftz_mul", "fftz_mul"),
                   ("k4_ffty_mul2d", "ffty_mul2d"), ("k_ffty_mul2d", "ffty_mul2d"),
                   ("k_field", "field"))
 
@@ -534,6 +538,9 @@ def main():
                     help="first requests of that list also run one at a time in FP64")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default demag plan instead of timing candidates first")
+    ap.add_argument("--plan", metavar="JSON",
+                    help="FP32 demag/field plan fields to install instead of autotuning "
+                         "(so that profiler runs time and count the same launches)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a 1 GiB device-to-device copy (counter calibration)")
     ap.add_argument("--counters-from", metavar="DIR",
@@ -561,7 +568,8 @@ def main():
         sys.exit(2)
     from paper_2411_18194_amd import mmp
     tune = not args.no_autotune
-    r32 = run_gpu(mmp.FP32, args.steps, args.warmup, prof=not args.no_prof, tune=tune)
+    r32 = run_gpu(mmp.FP32, args.steps, args.warmup, prof=not args.no_prof, tune=tune,
+                  plan_fields=json.loads(args.plan) if args.plan else None)
     _progress("FP32 film done")
     out = {
         "metric": METRIC, "value": round(r32["value"], 1), "unit": "cell-field-evals/s",

@@ -143,6 +143,15 @@ __global__ __launch_bounds__(256) void k4_ffty(Y4Args<T> a) {
 }
 
 // ------------------------------------------------------------- x rows --
+// The x passes pack and unpack the two real rows of a line in natural order
+// with one (line, kx) per thread, eight lines of a block side by side: lines
+// 8 KiB apart put element kx of every line in the same LDS bank.  Element e
+// of line q therefore sits at e ^ xsw<L>(q): a permutation within aligned
+// groups of 32 (so runs of 32 consecutive elements stay conflict-free) that
+// spreads the lines over the banks (lines shorter than 32 keep their order).
+template <int L>
+__device__ __forceinline__ int xsw(int q) { return L >= 32 ? (q & 3) << 3 : 0; }
+
 template <typename T, int L1, int L2, bool FULL>
 __global__ __launch_bounds__(256) void k4_fftx_fwd(X4Args<T> a) {
   using V = cpx<T>;
@@ -202,18 +211,19 @@ __global__ __launch_bounds__(256) void k4_fftx_fwd(X4Args<T> a) {
   V u[L1 / L2][L2];
   fs_step3<T, L1, L2, false>(u, line, t);
   __syncthreads();
+  const int sq = xsw<L>(q);
 #pragma unroll
   for (int i = 0; i < L1 / L2; ++i)
 #pragma unroll
-    for (int k2 = 0; k2 < L2; ++k2) line[t + L2 * i + L1 * k2] = u[i][bitrev<L2>(k2)];
+    for (int k2 = 0; k2 < L2; ++k2) line[(t + L2 * i + L1 * k2) ^ sq] = u[i][bitrev<L2>(k2)];
   __syncthreads();
   // unpack the two real spectra and store them transposed (y contiguous,
   // rows 2qq and 2qq+1 as one 16-byte store for FP32)
   V* out = a.S1 + ((long)(c * a.nz + z) * a.Hx) * a.ldy + y0;
   for (int idx = tid; idx < nl * a.Hx; idx += nthr) {
     const int qq = idx & (nl - 1), kx = idx >> a.lnl;
-    const V zk = lds[qq * L + kx];
-    const V zm = lds[qq * L + ((L - kx) & (L - 1))];
+    const V zk = lds[qq * L + (kx ^ xsw<L>(qq))];
+    const V zm = lds[qq * L + (((L - kx) & (L - 1)) ^ xsw<L>(qq))];
     const T h = T(0.5);
     store2<T>(out + (long)kx * a.ldy + 2 * qq, cmk<T>(h * (zk.x + zm.x), h * (zk.y - zm.y)),
               cmk<T>(h * (zk.y + zm.y), h * (zm.x - zk.x)));
@@ -250,15 +260,16 @@ __global__ __launch_bounds__(256) void k4_fftx_inv(X4Args<T> a) {
     if (idx < npair) {
       const int qq = idx & (nl - 1), kx = idx >> a.lnl;
       const V xa = pa[j], xb = pb[j];
-      lds[qq * L + kx] = cmk<T>(xa.x - xb.y, xa.y + xb.x);
-      if (kx > 0 && 2 * kx < L) lds[qq * L + L - kx] = cmk<T>(xa.x + xb.y, xb.x - xa.y);
+      lds[qq * L + (kx ^ xsw<L>(qq))] = cmk<T>(xa.x - xb.y, xa.y + xb.x);
+      if (kx > 0 && 2 * kx < L)
+        lds[qq * L + ((L - kx) ^ xsw<L>(qq))] = cmk<T>(xa.x + xb.y, xb.x - xa.y);
     }
   }
   __syncthreads();
   V* line = lds + q * L;
   V v[L1];
 #pragma unroll
-  for (int n1 = 0; n1 < L1; ++n1) v[n1] = line[L2 * n1 + t];
+  for (int n1 = 0; n1 < L1; ++n1) v[n1] = line[(L2 * n1 + t) ^ xsw<L>(q)];
   __syncthreads();
   fs_step1<T, L1, L2, true>(v, line, a.tw4, t);
   __syncthreads();
