@@ -245,6 +245,15 @@ __device__ __forceinline__ int xcd_remap(int b, int nb_pad) {
 
 namespace mmp {
 
+// Pointers typed as global memory.  A kernel that reads its buffers through
+// pointers loaded from a device-resident table would otherwise use flat
+// memory instructions (the compiler cannot prove where such a pointer
+// points): an aperture check on every access, and waits that cover LDS too.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+using gcptr = const __attribute__((address_space(1))) T*;
+
 // Input of RK stage s (1..ns): y_n, then sa/sb alternating, then y_new.
 template <typename T>
 __device__ __forceinline__ const T* stage_in(const Table<T>* tbl, int s) {

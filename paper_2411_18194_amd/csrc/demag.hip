@@ -64,9 +64,9 @@ __device__ __forceinline__ void fftx_fwd_body(const XArgs<T>& a, int stage, int 
   const int c = bz, z = by, y0 = bx * a.ty;
   const int nl = a.ty >> 1;
   const long N = (long)a.nx * a.ny * a.nz;
-  const T* m = stage_in(a.tbl, stage);
-  const T* m0 = m + (long)c * N + (long)z * a.ny * a.nx;
-  const T* m1 = m0 + 3 * N;
+  const gcptr<T> m = (gcptr<T>)stage_in(a.tbl, stage);
+  const gcptr<T> m0 = m + (long)c * N + (long)z * a.ny * a.nx;
+  const gcptr<T> m1 = m0 + 3 * N;
   for (int idx = tid; idx < nl * a.Px; idx += nthr) {
     const int q = idx / a.Px, x = idx - q * a.Px;
     const int ya = y0 + 2 * q, yb = ya + 1;

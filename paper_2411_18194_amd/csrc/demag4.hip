@@ -164,9 +164,9 @@ __global__ __launch_bounds__(256) void k4_fftx_fwd(X4Args<T> a) {
   const int c = blockIdx.z, z = blockIdx.y, y0 = blockIdx.x * a.ty;
   const int nl = a.ty >> 1;
   const long N = (long)a.nx * a.ny * a.nz;
-  const T* m = stage_in(a.tbl, a.stage);
-  const T* m0 = m + (long)c * N + (long)z * a.ny * a.nx;
-  const T* m1 = m0 + 3 * N;
+  const gcptr<T> m = (gcptr<T>)stage_in(a.tbl, a.stage);
+  const gcptr<T> m0 = m + (long)c * N + (long)z * a.ny * a.nx;
+  const gcptr<T> m1 = m0 + 3 * N;
   const int ya = y0 + 2 * q, yb = ya + 1;
   V* line = lds + q * L;
   V v[L1];
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(256) void k4_fftx_fwd(X4Args<T> a) {
     }
   }
   if (a.nsub == 3) {
-    const T* m2 = m1 + 3 * N;
+    const gcptr<T> m2 = m1 + 3 * N;
 #pragma unroll
     for (int n1 = 0; n1 < NLOAD; ++n1) {
       const int x = L2 * n1 + t;

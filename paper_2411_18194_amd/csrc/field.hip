@@ -155,30 +155,30 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
   const bool in = x < a.nx && y < a.ny;
   const long N = a.N;
   const long N3 = 3 * N;
-  const T* __restrict__ m = EVAL ? a.tbl->yn : stage_in(a.tbl, stage);
+  const gcptr<T> m = (gcptr<T>)(EVAL ? a.tbl->yn : stage_in(a.tbl, stage));
 
   double h = 0.0;
   int ns = 0;
   T ca[6] = {0, 0, 0, 0, 0, 0};
   double ew[7] = {0, 0, 0, 0, 0, 0, 0};
-  const T* kin[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  T* kout = nullptr;
-  T* ynext = nullptr;
-  const T* yn = nullptr;
+  gcptr<T> kin[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  gptr<T> kout = nullptr;
+  gptr<T> ynext = nullptr;
+  gcptr<T> yn = nullptr;
   if (!EVAL) {
     h = a.ctrl->h;
     ns = a.tbl->ns;
     const RKTab& rk = RK::t[a.tbl->rk];
-    kout = a.tbl->k[stage - 1];
-    yn = a.tbl->yn;
-    for (int j = 0; j < stage - 1; ++j) kin[j] = a.tbl->k[j];
+    kout = (gptr<T>)a.tbl->k[stage - 1];
+    yn = (gcptr<T>)a.tbl->yn;
+    for (int j = 0; j < stage - 1; ++j) kin[j] = (gcptr<T>)a.tbl->k[j];
     if (stage < ns) {
-      ynext = stage_out(a.tbl, stage);
+      ynext = (gptr<T>)stage_out(a.tbl, stage);
       for (int j = 0; j < stage; ++j) ca[j] = (T)(rk.a[stage][j] * h);
     } else {
-      if (fuse2) ynext = a.tbl->sa;
+      if (fuse2) ynext = (gptr<T>)a.tbl->sa;
       ca[0] = (T)(rk.a[1][0] * h);
-      for (int j = 0; j < ns - 1; ++j) kin[j] = a.tbl->k[j];
+      for (int j = 0; j < ns - 1; ++j) kin[j] = (gcptr<T>)a.tbl->k[j];
       for (int j = 0; j < ns; ++j) ew[j] = rk.e[j];
     }
   }
@@ -220,7 +220,7 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
       for (int s = 0; s < NSUB; ++s)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const T* mc = m + s * N3 + c * N + i;
+          const gcptr<T> mc = m + s * N3 + c * N + i;
           xm[s][c] = mc[dxm];
           xp[s][c] = mc[dxp];
           ym[s][c] = mc[dym];
@@ -695,12 +695,12 @@ __device__ __forceinline__ void combine2_cell(const Table<T>* tbl, const Ctrl* c
   const long s = i / Ncell, cell = i - s * Ncell;
   const long base = s * 3 * Ncell + cell;
   const T c = (T)(RK::t[tbl->rk].a[1][0] * ctrl->h);
-  const T* yn = tbl->yn;
-  const T* k1 = tbl->k[0];
+  const gcptr<T> yn = (gcptr<T>)tbl->yn;
+  const gcptr<T> k1 = (gcptr<T>)tbl->k[0];
   T v[3];
   for (int q = 0; q < 3; ++q) v[q] = yn[base + q * Ncell] + c * k1[base + q * Ncell];
   const T inv = T(1) / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-  T* o = tbl->sa;
+  const gptr<T> o = (gptr<T>)tbl->sa;
   for (int q = 0; q < 3; ++q) o[base + q * Ncell] = v[q] * inv;
 }
 

@@ -76,6 +76,14 @@ int64_t estimate_bytes(const mmp_request& r, int precision) {
 
 }  // namespace
 
+// Attempts per chunk for `cells` cell-sublattices: about 2^23 / (cells +
+// 2^15), between 8 and 128, i.e. a few ms of device work whether the grid is
+// large (time per attempt grows with its cells) or small (an attempt still
+// costs some tens of us of launches and latency).
+static int chunk_attempts(long long cells) {
+  return (int)std::max<long long>(8, std::min<long long>(128, (1LL << 23) / (cells + (1LL << 15))));
+}
+
 struct mmp_server_s {
   mmp_server_opts o{};
   std::mutex mu;
@@ -220,10 +228,12 @@ struct mmp_server_s {
         return 0;
       }
     }
-    // attempts per chunk: a few ms of device work for any grid size; two
-    // chunks stay in flight so the device never waits for the host
+    // attempts per chunk: a few ms of device work for any grid size (an
+    // attempt costs some tens of us of launches and latency on top of its
+    // cells); two chunks stay in flight so the device never waits for the
+    // host
     const int64_t N = (int64_t)q->r.nx * q->r.ny * q->r.nz * q->r.params.nsub;
-    q->chunk = (int)std::max<int64_t>(8, std::min<int64_t>(64, (int64_t(1) << 21) / N));
+    q->chunk = chunk_attempts(N);
     if (int rc = q->g->impl->run_chunk(q->chunk)) return rc;
     return q->g->impl->run_chunk(q->chunk);
   }
@@ -270,8 +280,12 @@ struct mmp_server_s {
       for (Req* q : B.members)
         if (member_done(q, &st)) B.draining = true;
     }
-    if (B.b->in_flight() > 0) return any;
-    if (B.draining) {
+    // membership changes wait until the batch is idle; otherwise the next
+    // chunk goes out as soon as one has finished, so the device always has
+    // one queued behind the one it runs
+    const bool change = B.draining || !B.joining.empty();
+    if (change && B.b->in_flight() > 0) return any;
+    if (change) {
       for (size_t i = 0; i < B.members.size();) {
         Req* q = B.members[i];
         int st = 0;
@@ -293,9 +307,7 @@ struct mmp_server_s {
       any = true;
     }
     if (!B.members.empty()) {
-      // a few ms of device work per chunk
-      const long long cells = std::max<long long>(1, B.b->cells());
-      const int chunk = (int)std::max<long long>(8, std::min<long long>(64, (1LL << 21) / cells));
+      const int chunk = chunk_attempts(std::max<long long>(1, B.b->cells()));
       while (B.b->in_flight() < 2) {
         const int rc = B.b->run_chunk(chunk);
         if (rc) {
@@ -391,7 +403,7 @@ struct mmp_server_s {
       }
       if (!any) {
         std::unique_lock<std::mutex> lk(mu);
-        cv.wait_for(lk, std::chrono::microseconds(200));
+        cv.wait_for(lk, std::chrono::microseconds(50));
       }
     }
     for (Req* q : active) finish(q, MMP_E_STATE);
