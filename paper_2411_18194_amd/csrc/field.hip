@@ -182,6 +182,16 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
       for (int j = 0; j < ns; ++j) ew[j] = rk.e[j];
     }
   }
+  // slopes the one-sublattice march loads up front (see below): the ones
+  // this stage sums, and in the other slots a buffer read anyway (k_1, or
+  // y_n at stage 1, which has no earlier slope; never a null table entry)
+  const gcptr<T> spare = stage >= 2 ? kin[0] : yn;
+  gcptr<T> kslot[6];
+  for (int j = 0; j < 6; ++j) {
+    const bool used = !EVAL && (stage < ns ? j < stage - 1 : (j < ns - 1 && ew[j] != 0.0));
+    kslot[j] = used ? kin[j] : spare;
+  }
+  const gcptr<T> yslot = stage < ns ? yn : spare;
 
   double eacc[kNE];
   for (int t = 0; t < kNE; ++t) eacc[t] = 0.0;
@@ -211,6 +221,23 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
     for (int z = z0; z < z1; ++z) {
       const long i = (long)z * plane + col;
       const long dzp = z + 1 < a.nz ? plane : 0;
+      // one sublattice: the stage slopes and y_n of this cell are requested
+      // with the stencil loads (they do not depend on the field, and loaded
+      // after the k_s stores below they would wait for a second round trip)
+      // Every slot is loaded (a slot this stage does not use reads k_1
+      // again, a cache hit): no branch between the loads, which then all go
+      // out before the first wait.
+      T kv1[6][3], yv1[3];
+      if constexpr (NSUB == 1 && !EVAL) {
+        if (stage < ns || !fuse2) {
+#pragma unroll
+          for (int j = 0; j < 6; ++j)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) kv1[j][c] = kslot[j][i + c * N];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) yv1[c] = yslot[i + c * N];
+        }
+      }
 #pragma unroll
       for (int s = 0; s < NSUB; ++s)
 #pragma unroll
@@ -514,22 +541,16 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
           if (stage < ns) {
             T v[3];
             if constexpr (NSUB == 1) {
-              // the slopes this stage needs are loaded first (uniform
-              // branches on the stage, no use in between), then summed in
-              // order.  (Two sublattices would need twice the registers and
-              // lose more waves than the batching gains.)
-              T kv[5][3];
-#pragma unroll
-              for (int j = 0; j < 5; ++j)
-                if (j < stage - 1)
-#pragma unroll
-                  for (int c = 0; c < 3; ++c) kv[j][c] = kin[j][base + c * N];
+              // the slopes this stage needs, loaded at the top of the
+              // iteration, summed in order.  (Two sublattices would need
+              // twice the registers and lose more waves than the batching
+              // gains.)
 #pragma unroll
               for (int c = 0; c < 3; ++c) {
-                T acc = yn[base + c * N];
+                T acc = yv1[c];
 #pragma unroll
                 for (int j = 0; j < 5; ++j)
-                  if (j < stage - 1) acc += ca[j] * kv[j][c];
+                  if (j < stage - 1) acc += ca[j] * kv1[j][c];
                 acc += ca[stage - 1] * tau[c];
                 v[c] = acc;
               }
@@ -551,18 +572,12 @@ __device__ __forceinline__ void field_block(const FieldArgs<T>& a, const int w, 
             // their loads), then e_ns of this stage's own slope
             double ev[3];
             if constexpr (NSUB == 1) {
-              T kv[6][3];
-#pragma unroll
-              for (int j = 0; j < 6; ++j)
-                if (j < ns - 1 && ew[j] != 0.0)
-#pragma unroll
-                  for (int c = 0; c < 3; ++c) kv[j][c] = kin[j][base + c * N];
 #pragma unroll
               for (int c = 0; c < 3; ++c) {
                 double acc = 0.0;
 #pragma unroll
                 for (int j = 0; j < 6; ++j)
-                  if (j < ns - 1 && ew[j] != 0.0) acc += ew[j] * (double)kv[j][c];
+                  if (j < ns - 1 && ew[j] != 0.0) acc += ew[j] * (double)kv1[j][c];
                 ev[c] = acc + ew[ns - 1] * (double)tau[c];
               }
             } else {
