@@ -402,7 +402,7 @@ def _progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_serve(count, box_s, max_active=16, baseline=0):
+def run_serve(count, box_s, max_active=16, baseline=0, baseline_short=0, short_frac=0.1):
     """A prefix of the seeded 4000-request stream (Poisson 200/s: 70 % FM
     with demag, 30 % two-sublattice AFM, 0.5 ns of relaxation each) served by
     the library's server in FP32 with continuous batching, arrivals at their
@@ -434,13 +434,27 @@ def run_serve(count, box_s, max_active=16, baseline=0):
         base["served_fp32_speedup"] = round(sub["solves_per_s"] / base["solves_per_s"], 3)
         base["note"] = (f"sequential plain FP64 timed on the first {baseline} requests of the "
                         "prefix (a seeded subsample)")
+    short = None
+    if baseline_short > 0:
+        # the first requests of the prefix with their relaxation shortened,
+        # so that a larger subsample of both fits the run's time budget
+        sreqs = [dict(r, t_relax=r["t_relax"] * short_frac) for r in reqs[:baseline_short]]
+        sstates = states[:baseline_short]
+        short = _sequential_fp64(sreqs, sstates)
+        _progress("serving: sequential FP64 baseline (shortened relaxations) done")
+        sub = _serve_pass(sreqs, sstates, mmp.FP32, arr[:baseline_short], 1e9, max_active)
+        short["served_fp32_same_requests"] = sub
+        short["served_fp32_speedup"] = round(sub["solves_per_s"] / short["solves_per_s"], 3)
+        short["note"] = (f"the first {baseline_short} requests of the prefix with t_relax x "
+                         f"{short_frac} ({short_frac * 0.5:g} ns): sequential plain FP64 vs "
+                         "served FP32")
     return {"workload": f"first {count} requests of the seeded 4000-request stream (Poisson "
                         "200/s, nx, ny log-uniform 32..512, nz log-uniform 1..8, cubic cells "
                         "1-5 nm, 70 % FM with demag / 30 % two-sublattice AFM, 0.5 ns DP45 "
                         "relaxation each, tol 1e-5)",
             "precision": "f32", "max_active": max_active, "offered": full,
             "at_0.8_capacity": dict(sus, arrival_rate_per_s=round(rate, 4)),
-            "sequential_fp64": base}
+            "sequential_fp64": base, "sequential_fp64_shortened": short}
 
 
 # rocprofv3 kernel names -> kernel classes of the library's event profiler
@@ -534,6 +548,9 @@ def main():
                     help="time box of each serving pass")
     ap.add_argument("--serve-active", type=int, default=16,
                     help="requests on the device at once")
+    ap.add_argument("--serve-baseline-short", type=int, default=20,
+                    help="first requests of that list, relaxations cut to a tenth, also run "
+                         "one at a time in FP64 and served in FP32")
     ap.add_argument("--serve-baseline", type=int, default=3,
                     help="first requests of that list also run one at a time in FP64")
     ap.add_argument("--no-autotune", action="store_true",
@@ -600,7 +617,8 @@ def main():
                        "plan": {k: v for k, v in r64["plan"].items() if k != "demag_ms"}}
     if args.serve > 0:
         out["serving"] = run_serve(args.serve, args.serve_seconds, args.serve_active,
-                                   baseline=min(args.serve_baseline, args.serve))
+                                   baseline=min(args.serve_baseline, args.serve),
+                                   baseline_short=min(args.serve_baseline_short, args.serve))
     acc = None if args.no_accuracy else accuracy_c2crop()
     if acc is not None:
         out["accuracy"] = acc
