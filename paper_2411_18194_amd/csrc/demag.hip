@@ -938,11 +938,15 @@ void demag_field(const DemagPlan& p, const DemagBufs<T>& b, const Table<T>* tbl,
 }
 
 // ------------------------------------------------------------ autotuner --
-// Mean time of one launch of `pass` over `reps` back-to-back launches after
-// one warm-up launch; a failed launch reads as infinitely slow.
+// Mean time of `reps` launches of the passes in seq[0..ns) after one warm-up
+// launch of the last; negative when a launch fails. The tuner times each
+// candidate of a pass right after the pass before it in an evaluation, so
+// the candidate meets the caches as it does there (the pair's time ranks
+// the candidates as their own would).
 template <typename T>
-static double time_pass(int pass, const DemagPlan& p, const DemagBufs<T>& b, const Table<T>* tbl,
-                        T ms0, T ms1, int nsub, hipStream_t st, int reps, T ms2) {
+static double time_passes(const int* seq, int ns, const DemagPlan& p, const DemagBufs<T>& b,
+                          const Table<T>* tbl, T ms0, T ms1, int nsub, hipStream_t st, int reps,
+                          T ms2) {
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return -1.0;
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -950,10 +954,10 @@ static double time_pass(int pass, const DemagPlan& p, const DemagBufs<T>& b, con
     return -1.0;
   }
   double ms = -1.0;
-  demag_pass<T>(pass, p, b, tbl, 1, nullptr, ms0, ms1, nsub, st, ms2);
+  demag_pass<T>(seq[ns - 1], p, b, tbl, 1, nullptr, ms0, ms1, nsub, st, ms2);
   if (hipGetLastError() == hipSuccess && hipEventRecord(e0, st) == hipSuccess) {
     for (int r = 0; r < reps; ++r)
-      demag_pass<T>(pass, p, b, tbl, 1, nullptr, ms0, ms1, nsub, st, ms2);
+      for (int j = 0; j < ns; ++j) demag_pass<T>(seq[j], p, b, tbl, 1, nullptr, ms0, ms1, nsub, st, ms2);
     float f = 0.f;
     if (hipGetLastError() == hipSuccess && hipEventRecord(e1, st) == hipSuccess &&
         hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&f, e0, e1) == hipSuccess)
@@ -972,9 +976,9 @@ double demag_tune(DemagPlan* pp, const DemagBufs<T>& b, const Table<T>* tbl, T m
   int passes[DP_COUNT];
   const int n = demag_passes(best, passes);
   // launches per timing: enough to average out launch jitter on small grids
+  // and run-to-run spread of a few percent on large ones
   const long work = (long)best.Hx * best.Py * best.Pz;
-  const int reps = work >= (1L << 22) ? 3 : work >= (1L << 16) ? 10 : 30;
-  double total = 0.0;
+  const int reps = work >= (1L << 22) ? 8 : work >= (1L << 16) ? 10 : 30;
   for (int i = 0; i < n; ++i) {
     const int pass = passes[i];
     std::vector<DemagPlan> cand;
@@ -1026,7 +1030,8 @@ double demag_tune(DemagPlan* pp, const DemagBufs<T>& b, const Table<T>* tbl, T m
     }
     double bt = -1.0;
     for (const DemagPlan& c : cand) {
-      const double t = time_pass<T>(pass, c, b, tbl, ms0, ms1, nsub, st, reps, ms2);
+      const double t = time_passes<T>(passes + (i > 0 ? i - 1 : 0), i > 0 ? 2 : 1, c, b, tbl,
+                                      ms0, ms1, nsub, st, reps, ms2);
       if (t < 0.0) continue;
       if (bt < 0.0 || t < bt) {
         bt = t;
@@ -1034,8 +1039,10 @@ double demag_tune(DemagPlan* pp, const DemagBufs<T>& b, const Table<T>* tbl, T m
       }
     }
     if (bt < 0.0) return -1.0;
-    total += bt;
   }
+  // the reported estimate: one whole evaluation with the chosen plan
+  const double total = time_passes<T>(passes, n, best, b, tbl, ms0, ms1, nsub, st, reps, ms2);
+  if (total < 0.0) return -1.0;
   *pp = best;
   return total;
 }

@@ -220,13 +220,21 @@ __global__ __launch_bounds__(256) void k4_fftx_fwd(X4Args<T> a) {
   // unpack the two real spectra and store them transposed (y contiguous,
   // rows 2qq and 2qq+1 as one 16-byte store for FP32)
   V* out = a.S1 + ((long)(c * a.nz + z) * a.Hx) * a.ldy + y0;
-  for (int idx = tid; idx < nl * a.Hx; idx += nthr) {
-    const int qq = idx & (nl - 1), kx = idx >> a.lnl;
+  auto unpack = [&](int qq, int kx) {
     const V zk = lds[qq * L + (kx ^ xsw<L>(qq))];
     const V zm = lds[qq * L + (((L - kx) & (L - 1)) ^ xsw<L>(qq))];
     const T h = T(0.5);
     store2<T>(out + (long)kx * a.ldy + 2 * qq, cmk<T>(h * (zk.x + zm.x), h * (zk.y - zm.y)),
               cmk<T>(h * (zk.y + zm.y), h * (zm.x - zk.x)));
+  };
+  // kx < Hx - 1 = L/2 spread evenly over the threads; the Nyquist bin rides
+  // with kx = 0 (no extra, nearly empty round for the whole block)
+  // (a one-cell axis, L = 1, has the single bin kx = 0)
+  const int nh = a.Hx - 1;
+  for (int idx = tid; idx < nl * (nh > 0 ? nh : 1); idx += nthr) {
+    const int qq = idx & (nl - 1), kx = idx >> a.lnl;
+    unpack(qq, kx);
+    if (kx == 0 && nh > 0) unpack(qq, nh);
   }
 }
 
@@ -242,11 +250,13 @@ __global__ __launch_bounds__(256) void k4_fftx_inv(X4Args<T> a) {
   const int c = blockIdx.z, z = blockIdx.y, y0 = blockIdx.x * a.ty;
   const int nl = a.ty >> 1;
   const V* in = a.S1 + ((long)(c * a.nz + z) * a.Hx) * a.ldy + y0;
-  // (spectrum pairs of the block) / threads = Hx / L2 <= L1/2 + 1: all
-  // loads unconditional (clamped to pair 0), issued before the first wait
-  constexpr int NI = L1 / 2 + 1;
-  const int npair = nl * a.Hx;
-  V pa[NI], pb[NI];
+  // spectrum pairs kx < Hx - 1 = L/2 of the block over its nl L2 threads:
+  // L1/2 each, all loads unconditional (clamped to pair 0) and issued before
+  // the first wait; the Nyquist pair rides with kx = 0 (threads tid < nl)
+  constexpr int NI = L1 / 2;
+  const int nh = a.Hx - 1;
+  const int npair = nl * nh;
+  V pa[NI > 0 ? NI : 1], pb[NI > 0 ? NI : 1], qa, qb;
 #pragma unroll
   for (int j = 0; j < NI; ++j) {
     const int idx = tid + j * nthr;
@@ -254,6 +264,8 @@ __global__ __launch_bounds__(256) void k4_fftx_inv(X4Args<T> a) {
     const int qq = ic & (nl - 1), kx = ic >> a.lnl;
     load2<T>(in + (long)kx * a.ldy + 2 * qq, pa[j], pb[j]);
   }
+  const bool nyq = tid < nl;
+  load2<T>(in + (long)nh * a.ldy + 2 * (nyq ? tid : 0), qa, qb);
 #pragma unroll
   for (int j = 0; j < NI; ++j) {
     const int idx = tid + j * nthr;
@@ -265,6 +277,7 @@ __global__ __launch_bounds__(256) void k4_fftx_inv(X4Args<T> a) {
         lds[qq * L + ((L - kx) ^ xsw<L>(qq))] = cmk<T>(xa.x + xb.y, xb.x - xa.y);
     }
   }
+  if (nyq) lds[tid * L + (nh ^ xsw<L>(tid))] = cmk<T>(qa.x - qb.y, qa.y + qb.x);
   __syncthreads();
   V* line = lds + q * L;
   V v[L1];
