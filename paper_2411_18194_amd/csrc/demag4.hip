@@ -504,6 +504,16 @@ __device__ __forceinline__ void zcol_load_split(const cpx<T>* col, long zs, long
   }
 }
 
+// one complex value through a global-typed pointer (a global, not flat,
+// store), component by component: the vector type's assignment does not
+// take an address-space-qualified destination
+template <typename T>
+__device__ __forceinline__ void gstore(gptr<cpx<T>> p, cpx<T> v) {
+  const gptr<T> q = (gptr<T>)p;
+  q[0] = v.x;
+  q[1] = v.y;
+}
+
 // Inverse transform of one component held by the Q lanes of a column and
 // store of the first nz planes.  Lane q holds B(kz = Q j + q) at register
 // bitrev<R>(j); with R = PZ/Q,
@@ -513,7 +523,7 @@ __device__ __forceinline__ void zcol_load_split(const cpx<T>* col, long zs, long
 // Plain stores: the y inverse pass reads these planes next, and part of
 // them is still in the Infinity Cache when it does.
 template <typename T, int PZ, int Q>
-__device__ __forceinline__ void zcol_inverse_store(cpx<T>* v, cpx<T>* col, long zs, int nz,
+__device__ __forceinline__ void zcol_inverse_store(cpx<T>* v, gptr<cpx<T>> col, long zs, int nz,
                                                    int q) {
   using V = cpx<T>;
   constexpr int R = PZ / Q, NH = PZ / 2;
@@ -524,7 +534,7 @@ __device__ __forceinline__ void zcol_inverse_store(cpx<T>* v, cpx<T>* col, long 
   if constexpr (Q == 1) {
 #pragma unroll
     for (int z = 0; z < NH; ++z)
-      if (z < nz) col[z * zs] = t[bitrev<PZ>(z)];
+      if (z < nz) gstore<T>(col + z * zs, t[bitrev<PZ>(z)]);
   } else {
     V c[NH];
     static_for<0, NH>([&](auto nc) {
@@ -555,7 +565,7 @@ __device__ __forceinline__ void zcol_inverse_store(cpx<T>* v, cpx<T>* col, long 
     base += hi ? S / 2 : 0;
 #pragma unroll
     for (int i = 0; i < S / 2; ++i)
-      if (base + i < nz) col[(base + i) * zs] = c[i];
+      if (base + i < nz) gstore<T>(col + (base + i) * zs, c[i]);
   }
 }
 
@@ -720,11 +730,12 @@ __device__ __forceinline__ void fftz_mul_body(const Z4Args<T>& a) {
   pin_regs<R, T>(vy);
   pin_regs<R, T>(vz);
   // the store addresses are formed anew, not kept in registers from the
-  // loads
-  asm volatile("" : "+v"(col));
-  zcol_inverse_store<T, PZ, Q>(vx, col, zs, a.nz, q);
-  zcol_inverse_store<T, PZ, Q>(vy, col + cs, zs, a.nz, q);
-  zcol_inverse_store<T, PZ, Q>(vz, col + 2 * cs, zs, a.nz, q);
+  // loads (through a global-typed pointer: global, not flat, stores)
+  gptr<V> gcol = (gptr<V>)col;
+  asm volatile("" : "+v"(gcol));
+  zcol_inverse_store<T, PZ, Q>(vx, gcol, zs, a.nz, q);
+  zcol_inverse_store<T, PZ, Q>(vy, gcol + cs, zs, a.nz, q);
+  zcol_inverse_store<T, PZ, Q>(vz, gcol + 2 * cs, zs, a.nz, q);
 }
 
 // W > 1: ask the register allocator for at least W waves per SIMD
