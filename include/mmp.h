@@ -240,6 +240,33 @@ mmp_status mmp_get_state(mmp_grid g, double* m, double* u, double* v,
 mmp_status mmp_eval_heff(mmp_grid g, uint32_t term_mask, double* b_out,
                          double* energy_out);
 
+/* Device-pointer variants of mmp_set_state, mmp_get_state and
+ * mmp_eval_heff, for callers whose data already live on the GPU (e.g.
+ * PyTorch tensors): the interface sketch's device variants of the state
+ * and field calls.  Every buffer is FP64 DEVICE memory of the grid's device
+ * in the host layout of the matching call ([sub][comp][z][y][x], x
+ * fastest; u, v [comp][z][y][x]), owned by the caller.  The work is
+ * enqueued on the grid's stream (mmp_set_stream) after whatever is already
+ * queued there, and the call returns without synchronising: inputs must
+ * stay valid, and outputs are written, when that stream reaches the work
+ * (order a torch stream after it, or call mmp_synchronize).  MMP_E_ARG for
+ * a buffer that is not device memory of the grid's device.
+ *
+ * mmp_set_state_device: m_dev (nsub*3*N) is rounded to the grid's precision
+ *   as given (not renormalised, like mmp_set_state); u_dev, v_dev (3*N, may
+ *   be NULL = zero) for elastic grids; the step controller restarts at t.
+ * mmp_get_state_device: any output may be NULL; t_dt_dev (2 doubles)
+ *   receives t and the next step size.
+ * mmp_eval_heff_device: b_dev (nsub*3*N) receives what mmp_eval_heff's
+ *   b_out does for term_mask (B in tesla, or dm/dt with MMP_OUT_TORQUE);
+ *   no energies.  An FP32 grid keeps an FP32 buffer of that size from its
+ *   first call. */
+mmp_status mmp_set_state_device(mmp_grid g, const double* m_dev, const double* u_dev,
+                                const double* v_dev, double t);
+mmp_status mmp_get_state_device(mmp_grid g, double* m_dev, double* u_dev, double* v_dev,
+                                double* t_dt_dev);
+mmp_status mmp_eval_heff_device(mmp_grid g, uint32_t term_mask, double* b_dev);
+
 /* One step of the grid's Runge-Kutta pair (mmp_params.solver).
  * dt_fixed > 0: fixed step, enqueued without a host synchronisation when
  * info is NULL.  dt_fixed == 0: adaptive, retried until accepted

@@ -276,6 +276,35 @@ mmp_status mmp_eval_heff(mmp_grid g, uint32_t mask, double* b, double* e) {
   MMP_GUARD_END
 }
 
+mmp_status mmp_set_state_device(mmp_grid g, const double* m_dev, const double* u_dev,
+                                const double* v_dev, double t) {
+  MMP_GUARD_BEGIN
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!m_dev) { set_error("null magnetisation"); return MMP_E_ARG; }
+  return g->impl->set_state_device(m_dev, u_dev, v_dev, t);
+  MMP_GUARD_END
+}
+
+mmp_status mmp_get_state_device(mmp_grid g, double* m_dev, double* u_dev, double* v_dev,
+                                double* t_dt_dev) {
+  MMP_GUARD_BEGIN
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!g->impl->state_set) { set_error("mmp_set_state has not been called"); return MMP_E_STATE; }
+  return g->impl->get_state_device(m_dev, u_dev, v_dev, t_dt_dev);
+  MMP_GUARD_END
+}
+
+mmp_status mmp_eval_heff_device(mmp_grid g, uint32_t mask, double* b_dev) {
+  MMP_GUARD_BEGIN
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!b_dev) { set_error("null output"); return MMP_E_ARG; }
+  return g->impl->eval_device(mask, b_dev);
+  MMP_GUARD_END
+}
+
 mmp_status mmp_step(mmp_grid g, double dt_fixed, mmp_step_info* info) {
   MMP_GUARD_BEGIN
   int rc = check_grid(g);

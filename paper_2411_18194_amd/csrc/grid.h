@@ -32,6 +32,11 @@ struct GridBase {
   virtual int set_state(const double* m, const double* u, const double* v, double t) = 0;
   virtual int get_state(double* m, double* u, double* v, double* t, double* dt) = 0;
   virtual int eval(uint32_t mask, double* b, double* e) = 0;
+  // device-pointer variants: FP64 device buffers in the host layouts,
+  // enqueued on the grid's stream, no host synchronisation
+  virtual int set_state_device(const double* m, const double* u, const double* v, double t) = 0;
+  virtual int get_state_device(double* m, double* u, double* v, double* t_dt) = 0;
+  virtual int eval_device(uint32_t mask, double* b) = 0;
   virtual int step(double dt_fixed, mmp_step_info* info) = 0;
   virtual int run_fixed(double dt, long long n, mmp_step_info* info) = 0;
   virtual int run(double t_end, const mmp_run_opts* o, mmp_run_info* info) = 0;

@@ -35,6 +35,81 @@ static int current_device() {
   return dev;
 }
 
+// ---------------------------------------------- device-pointer state I/O --
+// The state buffers are found through the device pointer table, which the
+// step controller swaps on the device: reading it there keeps these copies
+// ordered on the grid's stream with no host round trip.
+template <typename T>
+__global__ void k_state_in(const Table<T>* tbl, const double* m, long nm, const double* u,
+                           const double* v, long n3, int elastic) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nm; i += stride)
+    tbl->yn[i] = (T)m[i];
+  if (elastic)
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n3; i += stride) {
+      tbl->un[i] = u ? (T)u[i] : T(0);
+      tbl->vn[i] = v ? (T)v[i] : T(0);
+    }
+}
+
+template <typename T>
+__global__ void k_state_out(const Table<T>* tbl, const Ctrl* c, double* m, long nm, double* u,
+                            double* v, long n3, int elastic, double* t_dt) {
+  const long i0 = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long stride = (long)gridDim.x * blockDim.x;
+  if (m)
+    for (long i = i0; i < nm; i += stride) m[i] = (double)tbl->yn[i];
+  for (long i = i0; i < n3; i += stride) {
+    if (u) u[i] = elastic ? (double)tbl->un[i] : 0.0;
+    if (v) v[i] = elastic ? (double)tbl->vn[i] : 0.0;
+  }
+  if (t_dt && i0 == 0) {
+    t_dt[0] = c->t;
+    t_dt[1] = c->dt;
+  }
+}
+
+// a fresh controller at time t with first step dt (mmp_set_state's reset)
+__global__ void k_ctrl_reset(Ctrl* c, double t, double dt) {
+  Ctrl z{};
+  z.t = t;
+  z.dt = dt;
+  *c = z;
+}
+
+template <typename T>
+__global__ void k_widen(const T* in, double* out, long n) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += stride)
+    out[i] = (double)in[i];
+}
+
+static unsigned copy_blocks(long n) {
+  const long b = (n + 255) / 256;
+  return (unsigned)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+}
+
+// device memory of the stream's device (MMP_E_ARG otherwise)
+static int check_device_buffer(const void* ptr, hipStream_t st, const char* what) {
+  if (!ptr) return 0;
+  hipPointerAttribute_t at{};
+  if (hipPointerGetAttributes(&at, ptr) != hipSuccess || at.type != hipMemoryTypeDevice) {
+    (void)hipGetLastError();
+    set_error(std::string(what) + " is not device memory");
+    return MMP_E_ARG;
+  }
+  int dev = 0;
+  if (hipStreamGetDevice(st, &dev) != hipSuccess) {
+    set_error("hipStreamGetDevice failed");
+    return MMP_E_HIP;
+  }
+  if (at.device != dev) {
+    set_error(std::string(what) + " is on another device than the grid");
+    return MMP_E_ARG;
+  }
+  return 0;
+}
+
 template <typename T>
 struct Buf {
   T* p = nullptr;
@@ -98,7 +173,7 @@ struct Grid final : GridBase {
   void free_all() {
     drop_graphs();
     for (auto* b : {&y[0], &y[1], &sa, &sb, &u[0], &u[1], &v[0], &v[1], &usa, &usb, &vsa, &vsb,
-                    &eps, &epsv, &sig, &Bd, &gax, &K})
+                    &eps, &epsv, &sig, &Bd, &gax, &K, &evalb})
       b->release();
     for (int i = 0; i < 7; ++i) { k[i].release(); ku[i].release(); kv[i].release(); }
     gid.release();
@@ -680,6 +755,35 @@ struct Grid final : GridBase {
     return 0;
   }
 
+  int set_state_device(const double* m, const double* uu, const double* vv, double t) override {
+    if (int rc = check_device_buffer(m, stream, "m")) return rc;
+    if (int rc = check_device_buffer(uu, stream, "u")) return rc;
+    if (int rc = check_device_buffer(vv, stream, "v")) return rc;
+    const long nm = (long)p.nsub * 3 * N, n3 = 3L * N;
+    const double dt = p.dt0 > 0 ? p.dt0 : 1e-14;
+    hipLaunchKernelGGL(k_state_in<T>, dim3(copy_blocks(nm)), dim3(256), 0, stream, dtbl.p, m, nm,
+                       uu, vv, n3, p.elastic ? 1 : 0);
+    hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(1), 0, stream, dctrl.p, t, dt);
+    MMP_HIP_TRY(hipGetLastError());
+    t_host = t;
+    dt_host = dt;
+    k1_valid = false;
+    state_set = true;
+    return 0;
+  }
+
+  int get_state_device(double* m, double* uu, double* vv, double* t_dt) override {
+    if (int rc = check_device_buffer(m, stream, "m")) return rc;
+    if (int rc = check_device_buffer(uu, stream, "u")) return rc;
+    if (int rc = check_device_buffer(vv, stream, "v")) return rc;
+    if (int rc = check_device_buffer(t_dt, stream, "t_dt")) return rc;
+    const long nm = (long)p.nsub * 3 * N, n3 = 3L * N;
+    hipLaunchKernelGGL(k_state_out<T>, dim3(copy_blocks(nm)), dim3(256), 0, stream, dtbl.p,
+                       dctrl.p, m, nm, uu, vv, n3, p.elastic ? 1 : 0, t_dt);
+    MMP_HIP_TRY(hipGetLastError());
+    return 0;
+  }
+
   int get_state(double* m, double* uu, double* vv, double* t, double* dt) override {
     MMP_HIP_TRY(hipStreamSynchronize(stream));
     Table<T> tb{};
@@ -1053,6 +1157,50 @@ struct Grid final : GridBase {
       }
       e[kNE - 1] = el;
     }
+    return 0;
+  }
+
+  // B of the selected terms (or the torque) in the grid's precision, widened
+  // into the caller's FP64 device buffer; the grid keeps the precision-sized
+  // output buffer from the first call on
+  Buf<T> evalb;
+  int eval_device(uint32_t mask, double* b) override {
+    int rc = ensure_ready();
+    if (rc) return rc;
+    if ((rc = check_device_buffer(b, stream, "b"))) return rc;
+    const size_t nm = (size_t)p.nsub * 3 * N;
+    T* out = nullptr;
+    if constexpr (sizeof(T) == sizeof(double)) {
+      out = reinterpret_cast<T*>(b);
+    } else {
+      if (evalb.n < nm) {
+        evalb.release();
+        if (evalb.alloc(nm)) { set_error("device allocation failed"); return MMP_E_NOMEM; }
+      }
+      out = evalb.p;
+    }
+    if (p.elastic) {
+      ElasticArgs<T> ee = ea;
+      ee.stage = 1;
+      ee.ctrl = nullptr;
+      launch_strain(ee, stream, &prof);
+    }
+    if (p.demag)
+      demag_field<T>(plan, db, dtbl.p, 1, nullptr, (T)p.sub[0].Ms, ms_of(1), p.nsub, stream,
+                     &prof, ms_of(2));
+    FieldArgs<T> a = fa;
+    a.ctrl = nullptr;
+    a.stage = 1;
+    a.mask = mask & MMP_T_ALL;
+    a.add_zl = (mask & MMP_T_ZL) ? 1 : 0;
+    a.out_torque = (mask & MMP_OUT_TORQUE) ? 1 : 0;
+    a.bout = out;
+    a.epart = nullptr;
+    launch_field<T>(a, true, stream, &prof);
+    if constexpr (sizeof(T) != sizeof(double))
+      hipLaunchKernelGGL(k_widen<T>, dim3(copy_blocks((long)nm)), dim3(256), 0, stream, out, b,
+                         (long)nm);
+    MMP_HIP_TRY(hipGetLastError());
     return 0;
   }
 

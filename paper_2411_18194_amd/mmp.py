@@ -123,7 +123,8 @@ EXPORTS = ("mmp_grid_create", "mmp_grid_destroy", "mmp_set_params", "mmp_set_sta
            "mmp_get_plan", "mmp_set_plan", "mmp_autotune", "mmp_stray_field",
            "mmp_stray_field_noalloc", "mmp_prof_enable", "mmp_prof_count", "mmp_prof_read", "mmp_prof_reset",
            "mmp_server_create", "mmp_submit", "mmp_poll", "mmp_server_destroy",
-           "mmp_server_clock", "mmp_last_error")
+           "mmp_server_clock", "mmp_last_error", "mmp_set_state_device", "mmp_get_state_device",
+           "mmp_eval_heff_device")
 
 _lib = None
 
@@ -145,6 +146,9 @@ def load(path: str = LIB_PATH):
         "mmp_set_state": ([vp, dp, dp, dp, C.c_double], C.c_int32),
         "mmp_get_state": ([vp, dp, dp, dp, dp, dp], C.c_int32),
         "mmp_eval_heff": ([vp, C.c_uint32, dp, dp], C.c_int32),
+        "mmp_set_state_device": ([vp, vp, vp, vp, C.c_double], C.c_int32),
+        "mmp_get_state_device": ([vp, vp, vp, vp, vp], C.c_int32),
+        "mmp_eval_heff_device": ([vp, C.c_uint32, vp], C.c_int32),
         "mmp_step": ([vp, C.c_double, C.POINTER(StepInfo)], C.c_int32),
         "mmp_run_fixed": ([vp, C.c_double, C.c_int64, C.POINTER(StepInfo)], C.c_int32),
         "mmp_run": ([vp, C.c_double, C.POINTER(RunOpts), C.POINTER(RunInfo)], C.c_int32),
@@ -186,6 +190,20 @@ def _check(rc):
 
 def _dptr(a):
     return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+def _dev_buf(x, n, name):
+    """Address of a caller's FP64 device buffer of n elements: a tensor
+    (checked to be float64, on a GPU, contiguous, of n elements) or a raw
+    device address (int); None stays NULL."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return C.c_void_p(x)
+    if (str(getattr(x, "dtype", "")) != "torch.float64" or not getattr(x, "is_cuda", False)
+            or not x.is_contiguous() or x.numel() != n):
+        raise MMPError(-1, f"{name}: need a contiguous float64 GPU tensor of {n} elements")
+    return C.c_void_p(x.data_ptr())
 
 
 def make_params(p: dict, precision=FP32, tol=1e-5, dt0=1e-14, dt_min=1e-20):
@@ -304,6 +322,25 @@ class Grid:
         e = np.empty(10)
         _check(self.lib.mmp_eval_heff(self.h, mask, _dptr(b), _dptr(e)))
         return b, dict(zip(ENERGY_NAMES, e))
+
+    # device-pointer variants: buffers are FP64 GPU tensors (or raw device
+    # addresses) in the layouts of set_state / get_state / eval_heff; the
+    # work is enqueued on the grid's stream and the calls return at once
+    def set_state_device(self, m, u=None, v=None, t=0.0):
+        n = int(np.prod(self.shape_m()))
+        n3 = n // self.nsub
+        _check(self.lib.mmp_set_state_device(self.h, _dev_buf(m, n, "m"), _dev_buf(u, n3, "u"),
+                                             _dev_buf(v, n3, "v"), float(t)))
+
+    def get_state_device(self, m=None, u=None, v=None, t_dt=None):
+        n = int(np.prod(self.shape_m()))
+        n3 = n // self.nsub
+        _check(self.lib.mmp_get_state_device(self.h, _dev_buf(m, n, "m"), _dev_buf(u, n3, "u"),
+                                             _dev_buf(v, n3, "v"), _dev_buf(t_dt, 2, "t_dt")))
+
+    def eval_heff_device(self, b, mask=T_ALL):
+        n = int(np.prod(self.shape_m()))
+        _check(self.lib.mmp_eval_heff_device(self.h, mask, _dev_buf(b, n, "b")))
 
     def step(self, dt_fixed=0.0):
         info = StepInfo()
