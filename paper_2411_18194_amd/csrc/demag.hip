@@ -585,6 +585,7 @@ void demag_pass(int pass, const DemagPlan& p, const DemagBufs<T>& b, const Table
       const dim3 g((p.ny + ty - 1) / ty, p.nz, 3);
       const size_t lds = (size_t)(ty / 2) * p.Px * sizeof(V);
       if (p.p2x) {
+        const size_t lds4 = x4_lds_bytes(p.Px, ty / 2, inv, (int)sizeof(V));
         X4Args<T> a;
         a.tbl = tbl; a.ctrl = ctrl; a.stage = stage; a.ms0 = ms0; a.ms1 = ms1; a.nsub = nsub;
         a.ms2 = ms2;
@@ -592,7 +593,7 @@ void demag_pass(int pass, const DemagPlan& p, const DemagBufs<T>& b, const Table
         a.nx = p.nx; a.ny = p.ny; a.nz = p.nz; a.Hx = p.Hx; a.ldy = p.ldy; a.ty = ty;
         a.lnl = 0;
         while ((2 << a.lnl) < ty) ++a.lnl;
-        launch_x4<T>(p.Px, inv, p.rep[0] > 0, g, x_threads(p, ty), lds, st, a);
+        launch_x4<T>(p.Px, inv, p.rep[0] > 0, g, x_threads(p, ty), lds4, st, a);
       } else {
         XArgs<T> a;
         a.tbl = tbl; a.ctrl = ctrl; a.stage = stage; a.ms0 = ms0; a.ms1 = ms1; a.nsub = nsub;

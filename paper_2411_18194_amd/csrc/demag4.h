@@ -75,6 +75,14 @@ constexpr bool zreg_waves_ok(int real_bytes, int pz, int zq, int zw) {
 template <typename T>
 void launch_y4(int L, bool inv, bool full, dim3 g, int thr, size_t lds, hipStream_t st,
                const Y4Args<T>& a);
+// dynamic LDS bytes of a power-of-two x block of nl lines of L points
+// (complex value bytes vb): the FP32 forward pass holds half a line per
+// line from 64 points on (plus one aligned group of 32), the others a
+// whole line
+inline size_t x4_lds_bytes(int L, int nl, bool inv, int vb) {
+  const long per = (!inv && L >= 64 && vb == 8) ? L / 2 + 32 : L;
+  return (size_t)nl * (size_t)per * (size_t)vb;
+}
 template <typename T>
 void launch_x4(int L, bool inv, bool full, dim3 g, int thr, size_t lds, hipStream_t st,
                const X4Args<T>& a);

@@ -152,7 +152,113 @@ __global__ __launch_bounds__(256) void k4_ffty(Y4Args<T> a) {
 template <int L>
 __device__ __forceinline__ int xsw(int q) { return L >= 32 ? (q & 3) << 3 : 0; }
 
+// Makes the N complex values in registers at this point of the program: the
+// compiler can neither sink their computation below it nor hoist later uses
+// above it (an empty asm that reads and rewrites each register).  Between
+// the phases of a register z pass this keeps the forward transforms, the
+// kernel products and the inverse transforms from interleaving, which would
+// hold more values live at once than the 256 registers of two waves per SIMD.
+template <int N, typename T>
+__device__ __forceinline__ void pin_regs(cpx<T>* v) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) asm volatile("" : "+v"(v[i].x), "+v"(v[i].y));
+}
+
+// The half-LDS x forward pass after the loads: register FFTs and twiddles
+// of step 1, the transpose in two halves of rows, the step-3 FFTs, then the
+// unpack of the two real spectra in two halves of the spectrum.
+template <int L>
+constexpr int xhalf_stride();
+
 template <typename T, int L1, int L2, bool FULL>
+__device__ __forceinline__ void fwd_half_rest(const X4Args<T>& a, cpx<T>* v, cpx<T>* line,
+                                              cpx<T>* lds, int t, int q, int tid, int nthr, int c,
+                                              int z, int y0, int nl) {
+  using V = cpx<T>;
+  constexpr int L = L1 * L2, R = L1 / 2, H = xhalf_stride<L>();
+  if constexpr (!FULL && L1 >= 2) reg_fft_hz<T, L1, false>(v);
+  else reg_fft<T, L1, false>(v);
+  V x1[L1];
+#pragma unroll
+  for (int k1 = 0; k1 < L1; ++k1) {
+    V x = v[bitrev<L1>(k1)];
+    if (k1 > 0) x = cmul(x, a.tw4[k1 * L2 + t]);
+    x1[k1] = x;
+  }
+  pin_regs<L1, T>(x1);
+  V u[L1 / L2][L2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    // rows k1 of this half at local row k1 - h R (same swizzle as the
+    // whole-line transpose)
+#pragma unroll
+    for (int k1 = h * R; k1 < (h + 1) * R; ++k1)
+      line[(k1 - h * R) * L2 + (t ^ (k1 & (L2 - 1)))] = x1[k1];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < L1 / L2; ++i) {
+      const int k1 = t + L2 * i;
+      if ((k1 >= R) == (h == 1)) {
+#pragma unroll
+        for (int n2 = 0; n2 < L2; ++n2)
+          u[i][n2] = line[(k1 - h * R) * L2 + (n2 ^ (k1 & (L2 - 1)))];
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < L1 / L2; ++i) pin_regs<L2, T>(u[i]);
+#pragma unroll
+  for (int i = 0; i < L1 / L2; ++i) reg_fft<T, L2, false>(u[i]);
+#pragma unroll
+  for (int i = 0; i < L1 / L2; ++i) pin_regs<L2, T>(u[i]);
+  V* out = a.S1 + ((long)(c * a.nz + z) * a.Hx) * a.ldy + y0;
+  const int sq = xsw<L>(q);
+  const T hf = T(0.5);
+  // spectrum half 0: bins [0, L/4) at their index, (3L/4, L) at k - L/2;
+  // half 1: bins [L/4, 3L/4] at k - L/4
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int i = 0; i < L1 / L2; ++i)
+#pragma unroll
+      for (int k2 = 0; k2 < L2; ++k2) {
+        const int k = t + L2 * i + L1 * k2;
+        const bool mid = k >= L / 4 && k <= 3 * L / 4;
+        if (mid == (h == 1)) {
+          const int loc = h ? k - L / 4 : (k < L / 4 ? k : k - L / 2);
+          line[loc ^ sq] = u[i][bitrev<L2>(k2)];
+        }
+      }
+    __syncthreads();
+    // this half's bins kx (and their partners L - kx), every line of the block
+    const int kx0 = h ? L / 4 : 0, cnt = h ? L / 4 + 1 : L / 4;
+    for (int idx = tid; idx < nl * cnt; idx += nthr) {
+      const int qq = idx & (nl - 1), kx = kx0 + (idx >> a.lnl);
+      const int kp = (L - kx) & (L - 1);
+      const int lk = h ? kx - L / 4 : kx;
+      const int lp = h ? kp - L / 4 : (kp < L / 4 ? kp : kp - L / 2);
+      const V* lq = lds + qq * H;
+      const V zk = lq[lk ^ xsw<L>(qq)];
+      const V zm = lq[lp ^ xsw<L>(qq)];
+      store2<T>(out + (long)kx * a.ldy + 2 * qq, cmk<T>(hf * (zk.x + zm.x), hf * (zk.y - zm.y)),
+                cmk<T>(hf * (zk.y + zm.y), hf * (zm.x - zk.x)));
+    }
+    if (h == 0) __syncthreads();
+  }
+}
+
+// LDS elements per line of the half-LDS x forward pass: half a line, plus
+// one aligned group of 32 for the last element of the second spectrum half
+// and the bank swizzle
+template <int L>
+constexpr int xhalf_stride() { return L / 2 + 32; }
+
+// HALF (lines of 64 points or more): the step-1/step-3 transpose and the
+// unpack each go through LDS in two halves of a line (rows k1 < L1/2, then
+// the rest; spectrum bins k in [0, L/4) and (3L/4, L), then [L/4, 3L/4]),
+// so a block holds half the LDS and twice as many blocks fit on a CU.
+template <typename T, int L1, int L2, bool FULL, bool HALF = false>
 __global__ __launch_bounds__(256) void k4_fftx_fwd(X4Args<T> a) {
   using V = cpx<T>;
   if (ctrl_stopped(a.ctrl)) return;
@@ -168,7 +274,7 @@ __global__ __launch_bounds__(256) void k4_fftx_fwd(X4Args<T> a) {
   const gcptr<T> m0 = m + (long)c * N + (long)z * a.ny * a.nx;
   const gcptr<T> m1 = m0 + 3 * N;
   const int ya = y0 + 2 * q, yb = ya + 1;
-  V* line = lds + q * L;
+  V* line = lds + q * (HALF ? xhalf_stride<L>() : L);
   V v[L1];
   constexpr int NLOAD = (!FULL && L1 >= 2) ? L1 / 2 : L1;
   // rows ya, yb (clamped to row 0 past ny, column 0 past nx): every load is
@@ -205,6 +311,10 @@ __global__ __launch_bounds__(256) void k4_fftx_fwd(X4Args<T> a) {
   for (int n1 = 0; n1 < NLOAD; ++n1) {
     const bool inx = L2 * n1 + t < a.nx;
     v[n1] = cmk<T>(inx && ya < a.ny ? xa[n1] : T(0), inx && yb < a.ny ? xb[n1] : T(0));
+  }
+  if constexpr (HALF) {
+    fwd_half_rest<T, L1, L2, FULL>(a, v, line, lds, t, q, tid, nthr, c, z, y0, nl);
+    return;
   }
   fs_step1<T, L1, L2, false, !FULL>(v, line, a.tw4, t);
   __syncthreads();
@@ -611,17 +721,6 @@ __device__ __forceinline__ void lds_dma_b32(const float* src, float* dst) {
 template <int PZ, int Q>
 constexpr int zk_rows() { return Q == 1 ? PZ / 2 + 1 : PZ / Q; }
 
-// Makes the N complex values in registers at this point of the program: the
-// compiler can neither sink their computation below it nor hoist later uses
-// above it (an empty asm that reads and rewrites each register).  Between
-// the phases of a register z pass this keeps the forward transforms, the
-// kernel products and the inverse transforms from interleaving, which would
-// hold more values live at once than the 256 registers of two waves per SIMD.
-template <int N, typename T>
-__device__ __forceinline__ void pin_regs(cpx<T>* v) {
-#pragma unroll
-  for (int i = 0; i < N; ++i) asm volatile("" : "+v"(v[i].x), "+v"(v[i].y));
-}
 
 // Q adjacent lanes (Q = 1, 2 or 4, within one quad) carry the three
 // components of one (kx, ky) column through forward FFT, kernel multiply and
@@ -780,9 +879,12 @@ template <typename T, int L>
 static void lx(bool inv, bool full, dim3 g, int thr, size_t lds, hipStream_t st,
                const X4Args<T>& a) {
   constexpr int L1 = Split<L>::L1, L2 = Split<L>::L2;
+  // half-LDS forward pass for 32-bit values (x4_lds_bytes); 64-bit lines
+  // would hold more registers than the LDS saving gains
+  constexpr bool H = L >= 64 && sizeof(T) == 4;
   if (inv) hipLaunchKernelGGL((k4_fftx_inv<T, L1, L2>), g, dim3(thr), lds, st, a);
-  else if (full) hipLaunchKernelGGL((k4_fftx_fwd<T, L1, L2, true>), g, dim3(thr), lds, st, a);
-  else hipLaunchKernelGGL((k4_fftx_fwd<T, L1, L2, false>), g, dim3(thr), lds, st, a);
+  else if (full) hipLaunchKernelGGL((k4_fftx_fwd<T, L1, L2, true, H>), g, dim3(thr), lds, st, a);
+  else hipLaunchKernelGGL((k4_fftx_fwd<T, L1, L2, false, H>), g, dim3(thr), lds, st, a);
 }
 
 template <typename T>
