@@ -941,9 +941,9 @@ void demag_field(const DemagPlan& p, const DemagBufs<T>& b, const Table<T>* tbl,
 // ------------------------------------------------------------ autotuner --
 // Mean time of `reps` launches of the passes in seq[0..ns) after one warm-up
 // launch of the last; negative when a launch fails. The tuner times each
-// candidate of a pass right after the pass before it in an evaluation, so
-// the candidate meets the caches as it does there (the pair's time ranks
-// the candidates as their own would).
+// candidate of a pass right after the pass before it in an evaluation (the
+// first pass after the last one), so the candidate meets the caches as it
+// does there (the pair's time ranks the candidates as their own would).
 template <typename T>
 static double time_passes(const int* seq, int ns, const DemagPlan& p, const DemagBufs<T>& b,
                           const Table<T>* tbl, T ms0, T ms1, int nsub, hipStream_t st, int reps,
@@ -1031,8 +1031,10 @@ double demag_tune(DemagPlan* pp, const DemagBufs<T>& b, const Table<T>* tbl, T m
     }
     double bt = -1.0;
     for (const DemagPlan& c : cand) {
-      const double t = time_passes<T>(passes + (i > 0 ? i - 1 : 0), i > 0 ? 2 : 1, c, b, tbl,
-                                      ms0, ms1, nsub, st, reps, ms2);
+      // the first pass follows the last one of the previous evaluation
+      const int pair[2] = {passes[i > 0 ? i - 1 : n - 1], pass};
+      const double t = time_passes<T>(pair, n > 1 ? 2 : 1, c, b, tbl, ms0, ms1, nsub, st, reps,
+                                      ms2);
       if (t < 0.0) continue;
       if (bt < 0.0 || t < bt) {
         bt = t;
