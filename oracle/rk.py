@@ -23,7 +23,7 @@ slope is the next step's k_1; otherwise k_1 = f(y') is evaluated at the
 start of the next step.  A rejected step keeps k_1 (y is unchanged).
 
 Step control (the paper names the methods and the error-estimate order but
-no controller; these constants are this build's reading, "parity unpinned"
+no controller; these constants are a reading taken here, "parity unpinned"
 beyond GPU/oracle agreement):
   err   = h * max over cells and sublattices of |sum_j e_j k_j|_2
   accept when err <= tol

@@ -3,7 +3,7 @@
 Follows the Methods section ("Magnetostatic field"): the interaction between
 two cells is the analytic Newell-Williams-Dunlop result below a cutoff
 radius and an asymptotic (multipole) result beyond it.  The paper gives no
-cutoff radius; this build reads it as three regimes of r = |R| / max(d):
+cutoff radius; it is read here as three regimes of r = |R| / max(d):
 
 * r <  R_NEAR (3):  Newell's closed form - the 27-point second difference of
   the functions f (diagonal) and g (off-diagonal), in plain FP64.

@@ -9,7 +9,7 @@ not reproduced in the paper):
 with the drift velocity u = P mu_B j / (e Ms) (g = 2).  The torque's
 structure is pinned (a uniform state feels no torque; a periodic helix
 gives the closed form of both terms, tests/test_oracle_pbc.py), but the
-drift-velocity prefactor is a reading of this build: it is "parity
+drift-velocity prefactor is a reading taken here: it is "parity
 unpinned" beyond GPU/oracle agreement.  (u.grad) m uses central differences with clamped neighbours
 (the boundary cell stands in for the missing one) over 2*d.
 """
